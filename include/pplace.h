@@ -1,0 +1,117 @@
+/*
+ * pplace.h -- C ABI of the MI355X (gfx950) library for the truncated analytical cosine-series
+ * solution of Poisson's equation with Neumann boundary conditions, driven by the exact
+ * rectangle-block density (arXiv 2307.12041, Sec. III-A).
+ *
+ * Problem (Sec. II-A): a placement region [0, W] x [0, H] holding n rectangular blocks; block i
+ * has centre (x_i, y_i) and size (w_i, h_i).  Its density is the sum of the block indicators
+ * minus their mean (Sec. III-A, exact density and its mean-subtracted redefinition).
+ *
+ * Series (Sec. III-A, eq. psi): psi(x, y) = sum_{u<Mu} sum_{p<Mp} a_up cos(w_u x) cos(v_p y),
+ * with w_u = u pi / W and v_p = p pi / H, truncated to u in [0, Mu), p in [0, Mp).
+ *
+ * Coefficients (Sec. III-A, the closed forms for a_{mu,eta}, a_{mu,0}, a_{0,eta}, and
+ * a_00 = 0 from the compatibility condition): with the block integrals
+ *     X_iu = integral of cos(w_u t) over [x_i - w_i/2, x_i + w_i/2]   (X_i0 = w_i),
+ *     Y_ip = the same in y                                           (Y_i0 = h_i),
+ * and the moments A_up = sum_i X_iu Y_ip,
+ *     a_up = s_up A_up,   s_up = e_u e_p / (W H (w_u^2 + v_p^2)),  e_0 = 1, e_k = 2,  s_00 = 0.
+ *
+ * Energy (Sec. II-B, N = 1/2 sum_i q_i psi_i, read with the exact block density, so each block
+ * contributes its charge density times psi integrated over its area):
+ *     E = 1/2 iint rho psi = 1/2 sum_up a_up A_up.
+ *
+ * Gradient ("forces"; the field of eq. ksi integrated over each block, with the sign of a
+ * gradient):  gx_i = dE/dx_i = sum_up a_up (cos(w_u x_i^+) - cos(w_u x_i^-)) Y_ip,
+ *             gy_i = dE/dy_i = sum_up a_up X_iu (cos(v_p y_i^+) - cos(v_p y_i^-)).
+ * The force on block i is -(gx_i, gy_i).
+ *
+ * Conventions for every entry point
+ *   - Every array argument is a DEVICE pointer (memory of the current HIP device), owned by the
+ *     caller, contiguous, 8-byte aligned.  Coefficient arrays are row-major, a[u * Mp + p].
+ *   - ws is caller-owned device scratch of at least pp_workspace_size() bytes, 256-byte
+ *     aligned.  The library allocates no memory and keeps no state between calls; concurrent
+ *     calls need separate workspaces.
+ *   - stream is a hipStream_t (NULL: the default stream).  Calls only enqueue work and return;
+ *     outputs are valid once the stream has reached that point.  No call synchronises the host.
+ *   - Return value: PP_OK (0) or a negative pp_status.  Argument errors are detected on the host
+ *     before anything is enqueued, and then no output is touched.  PP_ERR_DEVICE means a launch
+ *     failed; outputs are then undefined.  Non-finite block data is not checked (NaN in, NaN out).
+ *   - Blocks may overhang the region; the series then integrates the whole block extent (the
+ *     overhang is folded back by the even reflection that the Neumann cosine basis implies).
+ */
+#ifndef PPLACE_H
+#define PPLACE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pp_status {
+    PP_OK = 0,
+    PP_ERR_ARG = -1,          /* NULL pointer, bad size, non-finite or non-positive W/H, misalignment */
+    PP_ERR_WORKSPACE = -2,    /* ws_bytes smaller than pp_workspace_size() */
+    PP_ERR_UNSUPPORTED = -3,  /* precision / basis mode not available in this build */
+    PP_ERR_DEVICE = -4        /* a HIP launch or runtime call failed */
+} pp_status;
+
+/* Arithmetic of the basis tables and the three contractions.  Seeds of the basis recurrences are
+ * always reduced in FP64; the final reductions (coefficients, energy, per-block gradient sums)
+ * are always FP64. */
+typedef enum pp_precision {
+    PP_FP64 = 0,    /* FP64 tables, FP64 MFMA */
+    PP_FP32 = 1,    /* FP32 tables, FP32 MFMA */
+    PP_BF16 = 2,    /* BF16 tables, BF16 MFMA, FP32 accumulation */
+    PP_BF16X3 = 3,  /* BF16 hi/lo split of FP32 tables: hi*hi + hi*lo + lo*hi, FP32 accumulation */
+    PP_FP8 = 4,     /* reserved */
+    PP_FP8X3 = 5    /* reserved */
+} pp_precision;
+
+typedef enum pp_basis_mode {
+    PP_BASIS_RECOMPUTE = 0,  /* basis tiles regenerated on chip, never stored */
+    PP_BASIS_STORE = 1       /* reserved */
+} pp_basis_mode;
+
+/* Problem description (Sec. II-A: region and blocks; truncation of the series, Sec. III-B/C). */
+typedef struct pp_problem {
+    double W, H;         /* region [0, W] x [0, H]; finite, > 0 */
+    int64_t n;           /* number of blocks, >= 0 */
+    int32_t Mu, Mp;      /* frequencies u in [0, Mu), p in [0, Mp); 1 <= Mu, Mp <= 65536 */
+    int32_t precision;   /* pp_precision */
+    int32_t basis_mode;  /* pp_basis_mode */
+} pp_problem;
+
+/* Bytes of device workspace that pp_coeffs, pp_energy and pp_field need for problem P (one size
+ * serves all three).  Host only: makes no HIP call. */
+int pp_workspace_size(const pp_problem *P, size_t *bytes);
+
+/* Series coefficients a_up (Sec. III-A closed forms; a_00 = 0).
+ * x, y, w, h: [n] FP64 block centres and sizes.  a: out [Mu * Mp] FP64. */
+int pp_coeffs(const pp_problem *P, const double *x, const double *y, const double *w, const double *h,
+              double *a, void *ws, size_t ws_bytes, void *stream);
+
+/* Energy E = 1/2 sum_up a_up A_up (Sec. II-B energy under the exact density) and optionally the
+ * coefficients.  E: out, one FP64 value in device memory.  a: out [Mu * Mp] FP64, or NULL. */
+int pp_energy(const pp_problem *P, const double *x, const double *y, const double *w, const double *h,
+              double *E, double *a, void *ws, size_t ws_bytes, void *stream);
+
+/* Per-block energy gradient, scaled by an upstream derivative (Sec. III-A field, eq. ksi,
+ * integrated over each block).
+ * a: in [Mu * Mp] FP64, the coefficients of the same problem and blocks (from pp_coeffs or
+ *    pp_energy).  dE: in, one FP64 value in device memory, or NULL for 1.
+ * gx, gy: out [n] FP64, gx_i = dE * dE/dx_i, gy_i = dE * dE/dy_i. */
+int pp_field(const pp_problem *P, const double *x, const double *y, const double *w, const double *h,
+             const double *a, const double *dE, double *gx, double *gy, void *ws, size_t ws_bytes,
+             void *stream);
+
+/* Static description of a status code. */
+const char *pp_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PPLACE_H */

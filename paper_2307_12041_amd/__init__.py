@@ -1,0 +1,201 @@
+"""Python binding of libpplace (include/pplace.h): argument marshalling only.
+
+Every step of the computation runs in the HIP kernels of ``libpplace.so``; this module passes
+device pointers of contiguous FP64 torch tensors, a caller-sized workspace and torch's current
+HIP stream.  PyTorch supplies memory and streams, nothing else.  If the library has not been
+built, every entry point raises instead of computing anything another way.
+
+The method (arXiv 2307.12041, Sec. III-A): on the region [0, W] x [0, H] with n rectangular blocks,
+the potential is psi = sum_{u<Mu, p<Mp} a_up cos(u pi x / W) cos(p pi y / H) with the closed-form
+coefficients of the exact block density; the energy is E = 1/2 iint rho psi and the gradient of E
+with respect to the block centres is minus the field (eq. ksi) integrated over each block.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+__all__ = ["PRECISIONS", "BASIS_MODES", "PPError", "library_path", "load", "workspace_size", "coeffs",
+           "energy", "field", "PPEnergy", "energy_autograd"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libpplace.so")
+
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "fp8": 4, "fp8x3": 5}
+BASIS_MODES = {"recompute": 0, "store": 1}
+
+PP_OK = 0
+EXPORTS = ("pp_workspace_size", "pp_coeffs", "pp_energy", "pp_field", "pp_strerror")
+
+
+class PPError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {_strerror(status)} (status {status})")
+
+
+class PPProblem(ctypes.Structure):
+    _fields_ = [("W", ctypes.c_double), ("H", ctypes.c_double), ("n", ctypes.c_int64),
+                ("Mu", ctypes.c_int32), ("Mp", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("basis_mode", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Load libpplace.so and declare the C signatures.  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.POINTER(PPProblem)
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    lib.pp_workspace_size.argtypes = [P, ctypes.POINTER(sz)]
+    lib.pp_coeffs.argtypes = [P, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.pp_energy.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.pp_field.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.pp_strerror.argtypes = [ctypes.c_int]
+    lib.pp_strerror.restype = ctypes.c_char_p
+    for f in ("pp_workspace_size", "pp_coeffs", "pp_energy", "pp_field"):
+        getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _strerror(status: int) -> str:
+    try:
+        return load().pp_strerror(int(status)).decode()
+    except Exception:  # pragma: no cover
+        return "unknown"
+
+
+def _problem(W, H, n, Mu, Mp, precision, basis) -> PPProblem:
+    if precision not in PRECISIONS:
+        raise ValueError(f"unknown precision {precision!r}; one of {sorted(PRECISIONS)}")
+    if basis not in BASIS_MODES:
+        raise ValueError(f"unknown basis mode {basis!r}; one of {sorted(BASIS_MODES)}")
+    return PPProblem(float(W), float(H), int(n), int(Mu), int(Mp), PRECISIONS[precision], BASIS_MODES[basis])
+
+
+def workspace_size(W, H, n, Mu, Mp, precision="fp64", basis="recompute") -> int:
+    P = _problem(W, H, n, Mu, Mp, precision, basis)
+    out = ctypes.c_size_t(0)
+    st = load().pp_workspace_size(ctypes.byref(P), ctypes.byref(out))
+    if st != PP_OK:
+        raise PPError(st, "pp_workspace_size")
+    return int(out.value)
+
+
+def _blocks(x, y, w, h):
+    ts = (x, y, w, h)
+    dev = x.device
+    n = x.shape[0]
+    for t in ts:
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.dim() != 1:
+            raise TypeError("x, y, w, h must be 1-D float64 tensors")
+        if t.device != dev or t.shape[0] != n or not t.is_contiguous():
+            raise ValueError("x, y, w, h must be contiguous, on one device, of equal length")
+    if dev.type != "cuda":
+        raise ValueError("x, y, w, h must live on a GPU (HIP) device")
+    return dev, n
+
+
+def _vp(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(dev):
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _workspace(P, dev):
+    nbytes = ctypes.c_size_t(0)
+    st = load().pp_workspace_size(ctypes.byref(P), ctypes.byref(nbytes))
+    if st != PP_OK:
+        raise PPError(st, "pp_workspace_size")
+    ws = torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device=dev)
+    return ws, int(nbytes.value)
+
+
+def coeffs(x, y, w, h, *, W, H, Mu, Mp, precision="fp64", basis="recompute"):
+    """Series coefficients a [Mu, Mp] (FP64, on the device of x)."""
+    dev, n = _blocks(x, y, w, h)
+    P = _problem(W, H, n, Mu, Mp, precision, basis)
+    a = torch.empty((Mu, Mp), dtype=torch.float64, device=dev)
+    ws, nb = _workspace(P, dev)
+    with torch.cuda.device(dev):
+        st = load().pp_coeffs(ctypes.byref(P), _vp(x), _vp(y), _vp(w), _vp(h), _vp(a), _vp(ws), nb, _stream(dev))
+    if st != PP_OK:
+        raise PPError(st, "pp_coeffs")
+    return a
+
+
+def energy(x, y, w, h, *, W, H, Mu, Mp, precision="fp64", basis="recompute", want_coeffs=True):
+    """Energy E (0-d FP64 tensor) and, if asked, the coefficients a [Mu, Mp]."""
+    dev, n = _blocks(x, y, w, h)
+    P = _problem(W, H, n, Mu, Mp, precision, basis)
+    E = torch.empty((), dtype=torch.float64, device=dev)
+    a = torch.empty((Mu, Mp), dtype=torch.float64, device=dev) if want_coeffs else None
+    ws, nb = _workspace(P, dev)
+    with torch.cuda.device(dev):
+        st = load().pp_energy(ctypes.byref(P), _vp(x), _vp(y), _vp(w), _vp(h), _vp(E), _vp(a), _vp(ws), nb,
+                              _stream(dev))
+    if st != PP_OK:
+        raise PPError(st, "pp_energy")
+    return E, a
+
+
+def field(x, y, w, h, a, *, W, H, precision="fp64", basis="recompute", dE=None):
+    """Per-block gradient (gx, gy) = dE * (dE/dx_i, dE/dy_i); the force on block i is -(gx, gy)."""
+    dev, n = _blocks(x, y, w, h)
+    if a.dtype != torch.float64 or a.dim() != 2 or not a.is_contiguous() or a.device != dev:
+        raise ValueError("a must be a contiguous [Mu, Mp] float64 tensor on the blocks' device")
+    Mu, Mp = a.shape
+    P = _problem(W, H, n, Mu, Mp, precision, basis)
+    if dE is not None:
+        dE = dE.to(device=dev, dtype=torch.float64).contiguous()
+    gx = torch.empty(n, dtype=torch.float64, device=dev)
+    gy = torch.empty(n, dtype=torch.float64, device=dev)
+    ws, nb = _workspace(P, dev)
+    with torch.cuda.device(dev):
+        st = load().pp_field(ctypes.byref(P), _vp(x), _vp(y), _vp(w), _vp(h), _vp(a), _vp(dE), _vp(gx), _vp(gy),
+                             _vp(ws), nb, _stream(dev))
+    if st != PP_OK:
+        raise PPError(st, "pp_field")
+    return gx, gy
+
+
+class PPEnergy(torch.autograd.Function):
+    """E(x, y) with a backward that maps dE to per-block gradients through pp_field.
+
+    The forward keeps only the coefficients a (Mu*Mp FP64); the backward regenerates every basis
+    tile on chip rather than storing n x M tables.  w and h are not differentiated."""
+
+    @staticmethod
+    def forward(ctx, x, y, w, h, W, H, Mu, Mp, precision, basis):
+        E, a = energy(x, y, w, h, W=W, H=H, Mu=Mu, Mp=Mp, precision=precision, basis=basis)
+        ctx.save_for_backward(x, y, w, h, a)
+        ctx.cfg = (W, H, precision, basis)
+        return E
+
+    @staticmethod
+    def backward(ctx, gE):
+        x, y, w, h, a = ctx.saved_tensors
+        W, H, precision, basis = ctx.cfg
+        gx, gy = field(x.detach(), y.detach(), w.detach(), h.detach(), a, W=W, H=H, precision=precision,
+                       basis=basis, dE=gE.detach())
+        return gx, gy, None, None, None, None, None, None, None, None
+
+
+def energy_autograd(x, y, w, h, *, W, H, Mu, Mp, precision="fp64", basis="recompute"):
+    """Differentiable energy: ``E.backward()`` fills x.grad, y.grad with dE/dx_i, dE/dy_i."""
+    return PPEnergy.apply(x, y, w, h, W, H, Mu, Mp, precision, basis)

@@ -1,0 +1,199 @@
+// api.hip -- the C ABI of include/pplace.h: argument validation (host only, before any enqueue),
+// work decomposition, workspace layout and the launch sequence of each entry point.
+#include <math.h>
+#include <string.h>
+
+#include "../../include/pplace.h"
+#include "common.h"
+
+namespace pp {
+namespace {
+
+constexpr int kMaxFreq = 65536;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool supported_precision(int prec) { return prec == PP_FP64; }
+
+int validate_problem(const pp_problem *P) {
+    if (!P) return PP_ERR_ARG;
+    if (!(isfinite(P->W) && P->W > 0.0) || !(isfinite(P->H) && P->H > 0.0)) return PP_ERR_ARG;
+    if (P->n < 0 || P->n > ((int64_t)1 << 40)) return PP_ERR_ARG;
+    if (P->Mu < 1 || P->Mp < 1 || P->Mu > kMaxFreq || P->Mp > kMaxFreq) return PP_ERR_ARG;
+    if (P->precision < PP_FP64 || P->precision > PP_FP8X3) return PP_ERR_ARG;
+    if (P->basis_mode != PP_BASIS_RECOMPUTE && P->basis_mode != PP_BASIS_STORE) return PP_ERR_ARG;
+    if (!supported_precision(P->precision) || P->basis_mode != PP_BASIS_RECOMPUTE) return PP_ERR_UNSUPPORTED;
+    return PP_OK;
+}
+
+bool aligned8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
+
+int validate_blocks(const pp_problem *P, const double *x, const double *y, const double *w, const double *h) {
+    if (P->n == 0) return PP_OK;
+    if (!x || !y || !w || !h) return PP_ERR_ARG;
+    if (!aligned8(x) || !aligned8(y) || !aligned8(w) || !aligned8(h)) return PP_ERR_ARG;
+    return PP_OK;
+}
+
+FwdPlan fwd_plan(const pp_problem &P) {
+    FwdPlan pl{};
+    if (P.Mu >= 128 && P.Mp >= 128) {
+        pl.tu = 128; pl.tp = 128; pl.kb = 16;
+    } else {
+        pl.tu = 64; pl.tp = 64; pl.kb = 32;
+    }
+    pl.tiles_u = (P.Mu + pl.tu - 1) / pl.tu;
+    pl.tiles_p = (P.Mp + pl.tp - 1) / pl.tp;
+    pl.chunks = (P.n + pl.kb - 1) / pl.kb;
+    const int64_t tiles = (int64_t)pl.tiles_u * pl.tiles_p;
+    // Enough workgroups to fill 256 CUs several times over, never more splits than chunks.
+    const int64_t target = 2048;
+    int64_t splits = (target + tiles - 1) / tiles;
+    if (splits > pl.chunks) splits = pl.chunks;
+    if (splits > 4096) splits = 4096;
+    if (splits < 1) splits = 1;
+    pl.chunks_per_split = (pl.chunks + splits - 1) / splits;
+    if (pl.chunks_per_split < 1) pl.chunks_per_split = 1;
+    pl.splits = (int)((pl.chunks + pl.chunks_per_split - 1) / pl.chunks_per_split);
+    if (pl.splits < 1) pl.splits = 1;
+    pl.part_elem = 8;
+    return pl;
+}
+
+BwdPlan bwd_plan(const pp_problem &P) {
+    BwdPlan pl{};
+    pl.tb = 128; pl.tn = 128; pl.kk = 32;
+    pl.tiles_b = (P.n + pl.tb - 1) / pl.tb;
+    pl.tiles_nx = (P.Mu + pl.tn - 1) / pl.tn;
+    pl.tiles_ny = (P.Mp + pl.tn - 1) / pl.tn;
+    pl.bmat_elem = 8;
+    return pl;
+}
+
+struct Layout {
+    size_t part, epart;                  // forward region
+    size_t bx, by, gpx, gpy;             // backward region (overlaps the forward region)
+    size_t fwd_bytes, bwd_bytes, total;
+};
+
+Layout layout(const pp_problem &P) {
+    const FwdPlan f = fwd_plan(P);
+    const BwdPlan b = bwd_plan(P);
+    const size_t MM = (size_t)P.Mu * (size_t)P.Mp;
+    Layout L{};
+    size_t off = 0;
+    L.part = off;  off = align_up(off + (size_t)f.splits * MM * f.part_elem);
+    L.epart = off; off = align_up(off + (size_t)reduce_scale_blocks(P.Mu, P.Mp) * sizeof(double));
+    L.fwd_bytes = off;
+    off = 0;
+    L.bx = off;  off = align_up(off + MM * b.bmat_elem);
+    L.by = off;  off = align_up(off + MM * b.bmat_elem);
+    L.gpx = off; off = align_up(off + (size_t)b.tiles_nx * (size_t)P.n * sizeof(double));
+    L.gpy = off; off = align_up(off + (size_t)b.tiles_ny * (size_t)P.n * sizeof(double));
+    L.bwd_bytes = off;
+    L.total = L.fwd_bytes > L.bwd_bytes ? L.fwd_bytes : L.bwd_bytes;
+    return L;
+}
+
+int check_ws(const Layout &L, void *ws, size_t ws_bytes) {
+    if (ws_bytes < L.total) return PP_ERR_WORKSPACE;
+    if (L.total > 0 && (!ws || ((uintptr_t)ws % kAlign) != 0)) return PP_ERR_ARG;
+    return PP_OK;
+}
+
+// Forward pipeline: partial contractions -> coefficients (+ energy partials) -> energy.
+int run_forward(const pp_problem &P, const double *x, const double *y, const double *w, const double *h,
+                double *a, double *E, void *ws, hipStream_t s) {
+    const FwdPlan f = fwd_plan(P);
+    const Layout L = layout(P);
+    char *base = (char *)ws;
+    void *part = base + L.part;
+    double *epart = (double *)(base + L.epart);
+    hipError_t err = launch_fwd_f64(f, P.n, P.Mu, P.Mp, P.W, P.H, x, y, w, h, (double *)part, s);
+    if (err != hipSuccess) return PP_ERR_DEVICE;
+    int nb = 0;
+    err = launch_reduce_scale(part, f.part_elem == 4, f.splits, P.Mu, P.Mp, P.W, P.H, a, epart, &nb, s);
+    if (err != hipSuccess) return PP_ERR_DEVICE;
+    if (E) {
+        err = launch_energy_final(epart, nb, E, s);
+        if (err != hipSuccess) return PP_ERR_DEVICE;
+    }
+    return PP_OK;
+}
+
+}  // namespace
+}  // namespace pp
+
+using namespace pp;
+
+extern "C" {
+
+int pp_workspace_size(const pp_problem *P, size_t *bytes) {
+    const int st = validate_problem(P);
+    if (st != PP_OK) return st;
+    if (!bytes) return PP_ERR_ARG;
+    *bytes = layout(*P).total;
+    return PP_OK;
+}
+
+int pp_coeffs(const pp_problem *P, const double *x, const double *y, const double *w, const double *h, double *a,
+              void *ws, size_t ws_bytes, void *stream) {
+    int st = validate_problem(P);
+    if (st != PP_OK) return st;
+    if ((st = validate_blocks(P, x, y, w, h)) != PP_OK) return st;
+    if (!a || !aligned8(a)) return PP_ERR_ARG;
+    const Layout L = layout(*P);
+    if ((st = check_ws(L, ws, ws_bytes)) != PP_OK) return st;
+    return run_forward(*P, x, y, w, h, a, nullptr, ws, (hipStream_t)stream);
+}
+
+int pp_energy(const pp_problem *P, const double *x, const double *y, const double *w, const double *h, double *E,
+              double *a, void *ws, size_t ws_bytes, void *stream) {
+    int st = validate_problem(P);
+    if (st != PP_OK) return st;
+    if ((st = validate_blocks(P, x, y, w, h)) != PP_OK) return st;
+    if (!E || !aligned8(E) || (a && !aligned8(a))) return PP_ERR_ARG;
+    const Layout L = layout(*P);
+    if ((st = check_ws(L, ws, ws_bytes)) != PP_OK) return st;
+    return run_forward(*P, x, y, w, h, a, E, ws, (hipStream_t)stream);
+}
+
+int pp_field(const pp_problem *P, const double *x, const double *y, const double *w, const double *h,
+             const double *a, const double *dE, double *gx, double *gy, void *ws, size_t ws_bytes, void *stream) {
+    int st = validate_problem(P);
+    if (st != PP_OK) return st;
+    if ((st = validate_blocks(P, x, y, w, h)) != PP_OK) return st;
+    if (!a || !aligned8(a) || (dE && !aligned8(dE))) return PP_ERR_ARG;
+    if (P->n > 0 && (!gx || !gy || !aligned8(gx) || !aligned8(gy))) return PP_ERR_ARG;
+    const Layout L = layout(*P);
+    if ((st = check_ws(L, ws, ws_bytes)) != PP_OK) return st;
+    if (P->n == 0) return PP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const BwdPlan b = bwd_plan(*P);
+    char *base = (char *)ws;
+    double *bx = (double *)(base + L.bx), *by = (double *)(base + L.by);
+    double *gpx = (double *)(base + L.gpx), *gpy = (double *)(base + L.gpy);
+    if (launch_prep_bwd_f64(a, P->Mu, P->Mp, P->W, P->H, bx, by, s) != hipSuccess) return PP_ERR_DEVICE;
+    // gx: K = p (basis of y), epilogue over u (cosine differences of x), operand BxT[p][u].
+    BwdAxis axx{y, h, P->H, P->Mp, x, w, P->W, P->Mu, bx, gpx};
+    // gy: K = u (basis of x), epilogue over p (cosine differences of y), operand By[u][p].
+    BwdAxis axy{x, w, P->W, P->Mu, y, h, P->H, P->Mp, by, gpy};
+    if (launch_bwd_f64(b, P->n, axx, s) != hipSuccess) return PP_ERR_DEVICE;
+    if (launch_bwd_f64(b, P->n, axy, s) != hipSuccess) return PP_ERR_DEVICE;
+    if (launch_bwd_final(gpx, b.tiles_nx, gpy, b.tiles_ny, P->n, dE, gx, gy, s) != hipSuccess) return PP_ERR_DEVICE;
+    return PP_OK;
+}
+
+const char *pp_strerror(int status) {
+    switch (status) {
+        case PP_OK: return "success";
+        case PP_ERR_ARG: return "invalid argument (NULL or misaligned pointer, bad size, non-finite or non-positive region)";
+        case PP_ERR_WORKSPACE: return "workspace smaller than pp_workspace_size()";
+        case PP_ERR_UNSUPPORTED: return "precision or basis mode not supported by this build";
+        case PP_ERR_DEVICE: return "HIP launch or runtime error";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

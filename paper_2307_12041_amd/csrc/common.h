@@ -1,0 +1,71 @@
+// common.h -- internal declarations shared by the HIP translation units of libpplace.
+//
+// Notation (arXiv 2307.12041, Sec. III-A): region [0,W] x [0,H], frequencies w_u = u pi / W,
+// v_p = p pi / H.  On the device the basis tables are carried WITHOUT their 1/w_u factor:
+//     S_iu = sin(w_u x_i^+) - sin(w_u x_i^-)   (u >= 1),   S_i0 = w_i,
+//     T_ip = sin(v_p y_i^+) - sin(v_p y_i^-)   (p >= 1),   T_i0 = h_i,
+//     K_iu = cos(w_u x_i^+) - cos(w_u x_i^-)   (u >= 1),   K_i0 = 0,   (L_ip likewise in y)
+// so that X_iu = S_iu / wt_u with wt_u = w_u (u >= 1), wt_0 = 1, and the same for Y with vt_p.
+// The device contraction is At = S^T T; then A = At / (wt_u vt_p), a = s_up A and
+// E = 1/2 sum a A, where s_up is the spectral scale of the coefficient closed forms.
+// Backward: gx_i = sum_u K_iu sum_p T_ip (a_up / vt_p), gy_i = sum_p L_ip sum_u S_iu (a_up / wt_u).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pp {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// Work decomposition shared by the host (workspace sizing) and the launchers.
+struct FwdPlan {
+    int tu, tp;          // output tile of one workgroup (frequencies u x p)
+    int kb;              // blocks per K chunk
+    int tiles_u, tiles_p;
+    int splits;          // split-K count
+    int64_t chunks;      // ceil(n / kb)
+    int64_t chunks_per_split;
+    size_t part_elem;    // bytes per partial element (8: FP64, 4: FP32)
+};
+
+struct BwdPlan {
+    int tb, tn, kk;      // block tile, output-frequency tile, K chunk (frequencies)
+    int64_t tiles_b;     // ceil(n / tb)
+    int tiles_nx;        // ceil(Mu / tn)  (gx: N = u)
+    int tiles_ny;        // ceil(Mp / tn)  (gy: N = p)
+    size_t bmat_elem;    // bytes per element of the prepared backward operand matrices
+};
+
+// Arguments of one backward contraction (gx or gy), see common.h header comment.
+struct BwdAxis {
+    const double *ca, *sa;   // K-side basis: coordinates and sizes (y,h for gx; x,w for gy)
+    double La;               // K-side region length (H for gx, W for gy)
+    int Ka;                  // K-side frequency count (Mp for gx, Mu for gy)
+    const double *cb, *sb;   // epilogue basis: coordinates and sizes (x,w for gx; y,h for gy)
+    double Lb;               // epilogue region length
+    int Nb;                  // epilogue frequency count (Mu for gx, Mp for gy)
+    const void *B;           // prepared operand [Ka][Nb] (layout depends on precision)
+    double *gpart;           // out: [tiles_n][n] partial gradients
+};
+
+// ---- launchers (each defined next to its kernels) ----
+hipError_t launch_fwd_f64(const FwdPlan &pl, int64_t n, int Mu, int Mp, double W, double H,
+                          const double *x, const double *y, const double *w, const double *h,
+                          double *part, hipStream_t s);
+hipError_t launch_bwd_f64(const BwdPlan &pl, int64_t n, const BwdAxis &ax, hipStream_t s);
+
+// Sum split-K partials (FP64 or FP32), scale, write a, per-block energy partials.
+hipError_t launch_reduce_scale(const void *part, bool part_f32, int splits, int Mu, int Mp, double W,
+                               double H, double *a, double *epart, int *nblocks_out, hipStream_t s);
+hipError_t launch_energy_final(const double *epart, int nblocks, double *E, hipStream_t s);
+int reduce_scale_blocks(int Mu, int Mp);
+
+// Backward operand preparation from FP64 a:  BxT[p][u] = a_up / vt_p,  By[u][p] = a_up / wt_u.
+hipError_t launch_prep_bwd_f64(const double *a, int Mu, int Mp, double W, double H, double *BxT,
+                               double *By, hipStream_t s);
+// gx[i] = dE * sum_t gpart_x[t][i], gy likewise.
+hipError_t launch_bwd_final(const double *gpx, int tx, const double *gpy, int ty, int64_t n,
+                            const double *dE, double *gx, double *gy, hipStream_t s);
+
+}  // namespace pp

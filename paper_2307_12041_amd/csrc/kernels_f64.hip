@@ -1,0 +1,284 @@
+// kernels_f64.hip -- FP64 path: basis tiles generated on chip, contractions on v_mfma_f64_16x16x4.
+//
+// Forward (coefficients, Sec. III-A closed forms): At[u][p] = sum_i S_iu T_ip over a K range of
+// blocks, one FP64 partial per split.  Backward (field of eq. ksi integrated over each block):
+// G[i][n] = sum_k A_ik B[k][n] with the sine-difference basis A generated along the K frequency
+// axis, then the row dot  g_i = sum_n E_in G[i][n]  with the cosine-difference basis E.
+//
+// Lane layouts of v_mfma_f64_16x16x4 (16x16 output, K = 4, one double per lane for A and B):
+//   A[i][k] in lane i + 16k,  B[k][j] in lane j + 16k,  D[i][j] in lane j + 16 (i % 4), element i / 4.
+//
+// Basis generation: for a block edge e and frequency k, the phase k*pi*e/L is carried in half
+// turns.  A run of consecutive frequencies starts from an FP64 seed, reduced to [-1, 1] half
+// turns before sincospi, and continues by rotating the (cos, sin) pair by the one-step phasor.
+// Runs are at most 32 long, so the rotation error stays at a few ulp.
+#include "common.h"
+
+namespace pp {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double reduce_half_turns(double t) { return t - 2.0 * rint(0.5 * t); }
+
+struct EdgeRot {
+    double cp, sp, cm, sm;      // current phasors of the + and - edges
+    double c1p, s1p, c1m, s1m;  // one-frequency-step phasors
+    __device__ __forceinline__ void init(double c, double sz, double L, int k0) {
+        const double tp = (c + 0.5 * sz) / L;
+        const double tm = (c - 0.5 * sz) / L;
+        sincospi(reduce_half_turns((double)k0 * tp), &sp, &cp);
+        sincospi(reduce_half_turns((double)k0 * tm), &sm, &cm);
+        sincospi(reduce_half_turns(tp), &s1p, &c1p);
+        sincospi(reduce_half_turns(tm), &s1m, &c1m);
+    }
+    __device__ __forceinline__ void step() {
+        double t = cp * c1p - sp * s1p;
+        sp = sp * c1p + cp * s1p;
+        cp = t;
+        t = cm * c1m - sm * s1m;
+        sm = sm * c1m + cm * s1m;
+        cm = t;
+    }
+};
+
+// R consecutive sine-difference values (size at frequency 0) of one block, written at dst[k*stride].
+template <int R>
+__device__ __forceinline__ void gen_sin_run(double c, double sz, double L, int k0, bool valid, double *dst,
+                                            int stride) {
+    if (!valid) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) dst[k * stride] = 0.0;
+        return;
+    }
+    EdgeRot r;
+    r.init(c, sz, L, k0);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        dst[k * stride] = (k0 + k == 0) ? sz : (r.sp - r.sm);
+        r.step();
+    }
+}
+
+// R consecutive cosine-difference values (0 at frequency 0) of one block.
+template <int R>
+__device__ __forceinline__ void gen_cos_run(double c, double sz, double L, int k0, bool valid, double *dst,
+                                            int stride) {
+    if (!valid) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) dst[k * stride] = 0.0;
+        return;
+    }
+    EdgeRot r;
+    r.init(c, sz, L, k0);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        dst[k * stride] = r.cp - r.cm;
+        r.step();
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Forward: grid (tiles_u * tiles_p, splits), 256 threads as 2 x 2 waves over a TU x TP tile.
+// LDS holds the K chunk of the two basis tiles, k-major: Xs[kb][u], Ys[kb][p].
+// ------------------------------------------------------------------------------------------------
+template <int TU, int TP, int KB>
+__global__ __launch_bounds__(256) void k_fwd_f64(int64_t n, int Mu, int Mp, double W, double H,
+                                                 const double *__restrict__ x, const double *__restrict__ y,
+                                                 const double *__restrict__ w, const double *__restrict__ h,
+                                                 double *__restrict__ part, int tiles_p, int64_t chunks,
+                                                 int64_t chunks_per_split) {
+    constexpr int LU = TU + 1, LP = TP + 1;
+    __shared__ double Xs[KB * LU];
+    __shared__ double Ys[KB * LP];
+    constexpr int WU = TU / 2, WP = TP / 2, SU = WU / 16, SP = WP / 16;
+    constexpr int RX = TU * KB / 128, RY = TP * KB / 128;
+    static_assert(RX * 128 == TU * KB && RY * 128 == TP * KB, "tile/thread mismatch");
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tu0 = (int)(blockIdx.x / tiles_p) * TU, tp0 = (int)(blockIdx.x % tiles_p) * TP;
+    const int wu0 = (wave >> 1) * WU, wp0 = (wave & 1) * WP;
+    const int64_t c_begin = (int64_t)blockIdx.y * chunks_per_split;
+    const int64_t c_end = min(chunks, c_begin + chunks_per_split);
+
+    const int side = tid >> 7, j = tid & 127, kb = j % KB, run = j / KB;
+
+    v4d acc[SU][SP];
+#pragma unroll
+    for (int a = 0; a < SU; ++a)
+#pragma unroll
+        for (int b = 0; b < SP; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+
+    for (int64_t c = c_begin; c < c_end; ++c) {
+        const int64_t ib = c * KB + kb;
+        const bool valid = ib < n;
+        __syncthreads();
+        if (side == 0) {
+            const double cx = valid ? x[ib] : 0.0, sx = valid ? w[ib] : 0.0;
+            gen_sin_run<RX>(cx, sx, W, tu0 + run * RX, valid, &Xs[kb * LU + run * RX], 1);
+        } else {
+            const double cy = valid ? y[ib] : 0.0, sy = valid ? h[ib] : 0.0;
+            gen_sin_run<RY>(cy, sy, H, tp0 + run * RY, valid, &Ys[kb * LP + run * RY], 1);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < KB / 4; ++ks) {
+            const int kr = ks * 4 + (lane >> 4);
+            double av[SU], bv[SP];
+#pragma unroll
+            for (int a = 0; a < SU; ++a) av[a] = Xs[kr * LU + wu0 + a * 16 + (lane & 15)];
+#pragma unroll
+            for (int b = 0; b < SP; ++b) bv[b] = Ys[kr * LP + wp0 + b * 16 + (lane & 15)];
+#pragma unroll
+            for (int a = 0; a < SU; ++a)
+#pragma unroll
+                for (int b = 0; b < SP; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+        }
+    }
+
+    double *out = part + (size_t)blockIdx.y * (size_t)Mu * (size_t)Mp;
+#pragma unroll
+    for (int a = 0; a < SU; ++a)
+#pragma unroll
+        for (int b = 0; b < SP; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int u = tu0 + wu0 + a * 16 + 4 * r + (lane >> 4);
+                const int p = tp0 + wp0 + b * 16 + (lane & 15);
+                if (u < Mu && p < Mp) out[(size_t)u * Mp + p] = acc[a][b][r];
+            }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Backward: grid (tiles_b, tiles_n), 256 threads as 2 x 2 waves over a TB (blocks) x TN
+// (epilogue frequencies) tile; K loop over the Ka frequencies of the other axis in chunks of KK.
+// LDS: As[k][i] (generated sine differences), Bs[k][n] (prepared operand); after the K loop the
+// same space holds the cosine differences of one half of the N tile, Es[n][i].
+// ------------------------------------------------------------------------------------------------
+template <int TB, int TN, int KK>
+__global__ __launch_bounds__(256) void k_bwd_f64(int64_t n, BwdAxis ax) {
+    constexpr int LB = TB + 1, LN = TN + 1;
+    constexpr int HALF = TN / 2;
+    static_assert(TB == 128 && TN == 128 && KK == 32, "LDS reuse below assumes this tile");
+    constexpr int SMEM = (KK * LB + KK * LN) > (HALF * LB) ? (KK * LB + KK * LN) : (HALF * LB);
+    __shared__ double smem[SMEM];
+    __shared__ double red[2 * TB];
+    double *As = smem, *Bs = smem + KK * LB, *Es = smem;
+    constexpr int WI = TB / 2, WJ = TN / 2, SI = WI / 16, SJ = WJ / 16;
+    constexpr int RA = KK * TB / 256;   // sine run per thread per chunk
+    constexpr int RE = HALF * TB / 256; // cosine run per thread per half
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t ib0 = (int64_t)blockIdx.x * TB;
+    const int n0 = (int)blockIdx.y * TN;
+    const int wi0 = (wave >> 1) * WI, wc = wave & 1, wj0 = wc * WJ;
+    const int gi = tid % TB, grun = tid / TB;
+    const int64_t ib = ib0 + gi;
+    const bool valid = ib < n;
+    const double ca = valid ? ax.ca[ib] : 0.0, sa = valid ? ax.sa[ib] : 0.0;
+    const double cb = valid ? ax.cb[ib] : 0.0, sb = valid ? ax.sb[ib] : 0.0;
+    const double *__restrict__ B = (const double *)ax.B;
+
+    v4d acc[SI][SJ];
+#pragma unroll
+    for (int a = 0; a < SI; ++a)
+#pragma unroll
+        for (int b = 0; b < SJ; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+
+    for (int k0 = 0; k0 < ax.Ka; k0 += KK) {
+        __syncthreads();
+        gen_sin_run<RA>(ca, sa, ax.La, k0 + grun * RA, valid, &As[(grun * RA) * LB + gi], LB);
+        for (int idx = tid; idx < KK * TN; idx += 256) {
+            const int k = idx / TN, jj = idx % TN;
+            const bool in = (k0 + k < ax.Ka) && (n0 + jj < ax.Nb);
+            Bs[k * LN + jj] = in ? B[(size_t)(k0 + k) * ax.Nb + n0 + jj] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < KK / 4; ++ks) {
+            const int kr = ks * 4 + (lane >> 4);
+            double av[SI], bv[SJ];
+#pragma unroll
+            for (int a = 0; a < SI; ++a) av[a] = As[kr * LB + wi0 + a * 16 + (lane & 15)];
+#pragma unroll
+            for (int b = 0; b < SJ; ++b) bv[b] = Bs[kr * LN + wj0 + b * 16 + (lane & 15)];
+#pragma unroll
+            for (int a = 0; a < SI; ++a)
+#pragma unroll
+                for (int b = 0; b < SJ; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+        }
+    }
+
+    // Epilogue: row dot with the cosine differences, one N half at a time.
+    double rs[SI][4];
+#pragma unroll
+    for (int a = 0; a < SI; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) rs[a][r] = 0.0;
+    for (int hf = 0; hf < 2; ++hf) {
+        __syncthreads();
+        gen_cos_run<RE>(cb, sb, ax.Lb, n0 + hf * HALF + grun * RE, valid, &Es[(grun * RE) * LB + gi], LB);
+        __syncthreads();
+        if (wc == hf) {
+#pragma unroll
+            for (int a = 0; a < SI; ++a)
+#pragma unroll
+                for (int b = 0; b < SJ; ++b)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int il = wi0 + a * 16 + 4 * r + (lane >> 4);
+                        const int jl = b * 16 + (lane & 15);
+                        rs[a][r] += acc[a][b][r] * Es[jl * LB + il];
+                    }
+        }
+    }
+    // Sum over the 16 lanes that share a row (fixed order: butterfly).
+#pragma unroll
+    for (int a = 0; a < SI; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            double v = rs[a][r];
+            v += __shfl_xor(v, 1);
+            v += __shfl_xor(v, 2);
+            v += __shfl_xor(v, 4);
+            v += __shfl_xor(v, 8);
+            rs[a][r] = v;
+        }
+    if ((lane & 15) == 0) {
+#pragma unroll
+        for (int a = 0; a < SI; ++a)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[wc * TB + wi0 + a * 16 + 4 * r + (lane >> 4)] = rs[a][r];
+    }
+    __syncthreads();
+    if (tid < TB && ib0 + tid < n)
+        ax.gpart[(size_t)blockIdx.y * (size_t)n + (size_t)(ib0 + tid)] = red[tid] + red[TB + tid];
+}
+
+}  // namespace
+
+hipError_t launch_fwd_f64(const FwdPlan &pl, int64_t n, int Mu, int Mp, double W, double H, const double *x,
+                          const double *y, const double *w, const double *h, double *part, hipStream_t s) {
+    dim3 grid(pl.tiles_u * pl.tiles_p, pl.splits);
+    if (pl.tu == 128 && pl.tp == 128 && pl.kb == 16)
+        hipLaunchKernelGGL((k_fwd_f64<128, 128, 16>), grid, dim3(256), 0, s, n, Mu, Mp, W, H, x, y, w, h, part,
+                           pl.tiles_p, pl.chunks, pl.chunks_per_split);
+    else if (pl.tu == 64 && pl.tp == 64 && pl.kb == 32)
+        hipLaunchKernelGGL((k_fwd_f64<64, 64, 32>), grid, dim3(256), 0, s, n, Mu, Mp, W, H, x, y, w, h, part,
+                           pl.tiles_p, pl.chunks, pl.chunks_per_split);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_bwd_f64(const BwdPlan &pl, int64_t n, const BwdAxis &ax, hipStream_t s) {
+    if (!(pl.tb == 128 && pl.tn == 128 && pl.kk == 32)) return hipErrorInvalidValue;
+    const int tiles_n = (ax.Nb + pl.tn - 1) / pl.tn;
+    dim3 grid((unsigned)pl.tiles_b, tiles_n);
+    hipLaunchKernelGGL((k_bwd_f64<128, 128, 32>), grid, dim3(256), 0, s, n, ax);
+    return hipGetLastError();
+}
+
+}  // namespace pp

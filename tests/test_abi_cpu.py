@@ -1,0 +1,123 @@
+"""The C ABI on the host (CPU only): the library loads, exports exactly what include/pplace.h
+declares, sizes workspaces, and rejects bad arguments before touching the device.  No call here
+reaches a kernel launch."""
+import ctypes
+import math
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2307_12041_amd as pp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pplace.h")
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pp_[a-z_0-9]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(pp.library_path()):
+        pytest.skip("libpplace.so not built")
+    return pp.load()
+
+
+def test_exports_match_header(lib):
+    declared = header_functions()
+    assert set(pp.EXPORTS) <= set(declared)
+    out = subprocess.run(["nm", "-D", "--defined-only", pp.library_path()], capture_output=True, text=True,
+                         check=True).stdout
+    exported = sorted(set(re.findall(r"\bT (pp_[a-z_0-9]+)$", out, flags=re.M)))
+    assert exported == declared
+    for f in declared:
+        assert hasattr(lib, f)
+
+
+def test_strerror(lib):
+    for st in (0, -1, -2, -3, -4, 7):
+        s = lib.pp_strerror(st)
+        assert isinstance(s, bytes) and len(s) > 3
+
+
+def P(**kw):
+    d = dict(W=100.0, H=50.0, n=1000, Mu=64, Mp=48, precision=0, basis_mode=0)
+    d.update(kw)
+    return pp.PPProblem(d["W"], d["H"], d["n"], d["Mu"], d["Mp"], d["precision"], d["basis_mode"])
+
+
+def ws_size(lib, prob):
+    out = ctypes.c_size_t(12345)
+    st = lib.pp_workspace_size(ctypes.byref(prob), ctypes.byref(out))
+    return st, out.value
+
+
+def test_workspace_size_monotone_and_host_only(lib):
+    st, a = ws_size(lib, P(n=1000))
+    assert st == 0 and a > 0 and a % 256 == 0
+    st, b = ws_size(lib, P(n=100000))
+    assert st == 0 and b >= a
+    st, c = ws_size(lib, P(n=0))
+    assert st == 0
+    st, d = ws_size(lib, P(Mu=2048, Mp=2048, n=2_000_500))
+    assert st == 0 and d > b
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(W=0.0), -1), (dict(W=-1.0), -1), (dict(H=math.nan), -1), (dict(W=math.inf), -1),
+    (dict(Mu=0), -1), (dict(Mp=-3), -1), (dict(Mu=70000), -1), (dict(n=-1), -1),
+    (dict(precision=9), -1), (dict(basis_mode=5), -1),
+])
+def test_workspace_size_rejects(lib, bad, code):
+    st, v = ws_size(lib, P(**bad))
+    assert st == code and v == 12345      # output untouched
+
+
+def test_entry_points_validate_before_launch(lib):
+    prob = P()
+    st, need = ws_size(lib, prob)
+    assert st == 0
+    fake = ctypes.c_void_p(1 << 20)      # never dereferenced: every call below fails validation
+    nul = None
+    # NULL problem
+    assert lib.pp_coeffs(None, fake, fake, fake, fake, fake, fake, need, nul) == -1
+    # NULL block arrays / outputs
+    assert lib.pp_coeffs(ctypes.byref(prob), nul, fake, fake, fake, fake, fake, need, nul) == -1
+    assert lib.pp_coeffs(ctypes.byref(prob), fake, fake, fake, fake, nul, fake, need, nul) == -1
+    assert lib.pp_energy(ctypes.byref(prob), fake, fake, fake, fake, nul, fake, fake, need, nul) == -1
+    assert lib.pp_field(ctypes.byref(prob), fake, fake, fake, fake, nul, nul, fake, fake, fake, need, nul) == -1
+    assert lib.pp_field(ctypes.byref(prob), fake, fake, fake, fake, fake, nul, nul, fake, fake, need, nul) == -1
+    # misaligned pointers
+    odd = ctypes.c_void_p((1 << 20) + 4)
+    assert lib.pp_coeffs(ctypes.byref(prob), odd, fake, fake, fake, fake, fake, need, nul) == -1
+    # short / missing / misaligned workspace
+    assert lib.pp_coeffs(ctypes.byref(prob), fake, fake, fake, fake, fake, fake, need - 1, nul) == -2
+    assert lib.pp_energy(ctypes.byref(prob), fake, fake, fake, fake, fake, fake, fake, need - 8, nul) == -2
+    assert lib.pp_field(ctypes.byref(prob), fake, fake, fake, fake, fake, nul, fake, fake, fake, 0, nul) == -2
+    assert lib.pp_coeffs(ctypes.byref(prob), fake, fake, fake, fake, fake, nul, need, nul) == -1
+    assert lib.pp_coeffs(ctypes.byref(prob), fake, fake, fake, fake, fake, ctypes.c_void_p((1 << 20) + 64),
+                         need, nul) == -1
+    # bad problem fields
+    bad = P(W=-2.0)
+    assert lib.pp_energy(ctypes.byref(bad), fake, fake, fake, fake, fake, fake, fake, need, nul) == -1
+
+
+def test_unsupported_modes_reported(lib):
+    st, _ = ws_size(lib, P(precision=4))
+    assert st == -3
+    st, _ = ws_size(lib, P(basis_mode=1))
+    assert st == -3
+
+
+def test_python_binding_fails_loudly_without_gpu_tensors(lib):
+    import torch
+    x = torch.zeros(4, dtype=torch.float64)
+    with pytest.raises(ValueError):
+        pp.energy(x, x, x, x, W=1.0, H=1.0, Mu=4, Mp=4)
+    with pytest.raises(ValueError):
+        pp.energy(x, x, x, x, W=1.0, H=1.0, Mu=4, Mp=4, precision="fp7")

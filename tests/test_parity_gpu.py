@@ -1,0 +1,166 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle, element by element.
+
+Metrics: coefficients ||a - a*||_F / ||a*||_F, energy |E - E*| / |E*|, gradient
+||g - g*||_2 / ||g*||_2 over all blocks and both components.  Bars: FP64 path 1e-10
+(the FP64 target of this method's GPU form).
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import make_config, make_random
+
+torch = pytest.importorskip("torch")
+pp = pytest.importorskip("paper_2307_12041_amd")
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+FP64_TOL = 1e-10
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def dev(*arrs):
+    return [torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=DEV) for a in arrs]
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b.ravel())
+    return np.linalg.norm((a - b).ravel()) / (nb if nb > 0 else 1.0)
+
+
+def gpu_all(wl, precision="fp64"):
+    x, y, w, h = dev(*wl.arrays())
+    E, a = pp.energy(x, y, w, h, W=wl.W, H=wl.H, Mu=wl.Mu, Mp=wl.Mp, precision=precision)
+    gx, gy = pp.field(x, y, w, h, a, W=wl.W, H=wl.H, precision=precision)
+    torch.cuda.synchronize()
+    return float(E.cpu()), a.cpu().numpy(), gx.cpu().numpy(), gy.cpu().numpy()
+
+
+def oracle_all(wl):
+    E, a, _ = oracle.energy(wl.W, wl.H, *wl.arrays(), wl.Mu, wl.Mp)
+    gx, gy = oracle.grad(wl.W, wl.H, *wl.arrays(), a)
+    return E, a, gx, gy
+
+
+def check_parity(wl, precision="fp64", tol=FP64_TOL):
+    say(f"[parity] {wl.name} n={wl.n} Mu={wl.Mu} Mp={wl.Mp} prec={precision}")
+    E, a, gx, gy = gpu_all(wl, precision)
+    Eo, ao, gxo, gyo = oracle_all(wl)
+    ea = rel(a, ao)
+    eE = abs(E - Eo) / abs(Eo)
+    eg = rel(np.concatenate([gx, gy]), np.concatenate([gxo, gyo]))
+    say(f"   rel err a={ea:.3e} E={eE:.3e} g={eg:.3e}")
+    assert ea <= tol and eE <= tol and eg <= tol, (ea, eE, eg)
+    return ea, eE, eg
+
+
+def test_golden_cases_fp64():
+    path = os.path.join(os.path.dirname(__file__), "golden", "oracle_cases.json")
+    for c in json.load(open(path))["cases"]:
+        say(f"[golden] {c['name']}")
+        x, y, w, h = dev(c["x"], c["y"], c["w"], c["h"])
+        E, a = pp.energy(x, y, w, h, W=c["W"], H=c["H"], Mu=c["Mu"], Mp=c["Mp"])
+        gx, gy = pp.field(x, y, w, h, a, W=c["W"], H=c["H"])
+        E = float(E.cpu())
+        assert abs(E - c["E"]) <= FP64_TOL * abs(c["E"])
+        ac = np.array(c["a_corner"])
+        assert rel(a.cpu().numpy()[:4, :4], ac) <= FP64_TOL
+        g = np.concatenate([gx.cpu().numpy(), gy.cpu().numpy()])
+        assert rel(g, np.concatenate([c["gx"], c["gy"]])) <= FP64_TOL
+
+
+@pytest.mark.parametrize("n,Mu,Mp,W,H,seed", [
+    (1, 5, 3, 10.0, 7.0, 0),           # single block, tiny truncation
+    (37, 24, 20, 100.0, 60.0, 1),      # ragged everything
+    (1000, 64, 64, 1024.0, 1024.0, 2),  # one 64x64 tile, split-K
+    (3001, 200, 150, 500.0, 300.0, 3),  # 128 tiles with ragged edges, non-square
+    (4100, 129, 257, 300.0, 900.0, 4),  # Mu just over a tile, Mp two tiles + 1
+    (257, 63, 130, 64.0, 80.0, 5),      # mixed sizes fall back to the small tile
+])
+def test_fp64_parity_shapes(n, Mu, Mp, W, H, seed):
+    wl = make_random(n, W, H, Mu, Mp, seed=seed)
+    check_parity(wl)
+
+
+def test_fp64_parity_uniform_1k_M64():
+    check_parity(make_config(1))
+
+
+def test_fp64_parity_overhanging_blocks():
+    wl = make_random(500, 40.0, 30.0, 48, 40, seed=8, wmax=12.0, hmax=9.0, inside=False)
+    check_parity(wl)
+
+
+def test_fp64_zero_blocks():
+    say("[edge] n=0")
+    x = torch.empty(0, dtype=torch.float64, device=DEV)
+    E, a = pp.energy(x, x, x, x, W=10.0, H=10.0, Mu=17, Mp=9)
+    gx, gy = pp.field(x, x, x, x, a, W=10.0, H=10.0)
+    assert float(E.cpu()) == 0.0 and float(a.abs().max().cpu()) == 0.0
+    assert gx.numel() == 0 and gy.numel() == 0
+
+
+def test_fp64_tiling_and_mirror_invariants():
+    say("[invariants] tiling, mirror")
+    W, H = 8.0, 6.0
+    xs, ys = np.meshgrid(np.arange(4) * 2 + 1.0, np.arange(3) * 2 + 1.0, indexing="ij")
+    n = xs.size
+    x, y, w, h = dev(xs.ravel(), ys.ravel(), np.full(n, 2.0), np.full(n, 2.0))
+    E, a = pp.energy(x, y, w, h, W=W, H=H, Mu=96, Mp=80)
+    gx, gy = pp.field(x, y, w, h, a, W=W, H=H)
+    assert abs(float(E.cpu())) < 1e-24
+    assert float(a.abs().max().cpu()) < 1e-12
+    assert max(float(gx.abs().max().cpu()), float(gy.abs().max().cpu())) < 1e-11
+    wl = make_random(300, 90.0, 40.0, 150, 70, seed=12)
+    x, y, w, h = dev(*wl.arrays())
+    E0, a0 = pp.energy(x, y, w, h, W=wl.W, H=wl.H, Mu=wl.Mu, Mp=wl.Mp)
+    g0 = pp.field(x, y, w, h, a0, W=wl.W, H=wl.H)
+    xm = wl.W - x
+    E1, a1 = pp.energy(xm, y, w, h, W=wl.W, H=wl.H, Mu=wl.Mu, Mp=wl.Mp)
+    g1 = pp.field(xm, y, w, h, a1, W=wl.W, H=wl.H)
+    assert abs(float(E1.cpu()) - float(E0.cpu())) <= 1e-12 * float(E0.cpu())
+    sc = float(torch.cat(g0).abs().max().cpu())
+    assert float((g1[0] + g0[0]).abs().max().cpu()) <= 1e-11 * sc
+    assert float((g1[1] - g0[1]).abs().max().cpu()) <= 1e-11 * sc
+
+
+def test_fp64_deterministic_repeat():
+    say("[determinism]")
+    wl = make_random(20000, 700.0, 500.0, 160, 140, seed=21, wmax=8, hmax=2)
+    x, y, w, h = dev(*wl.arrays())
+    outs = []
+    for _ in range(2):
+        E, a = pp.energy(x, y, w, h, W=wl.W, H=wl.H, Mu=wl.Mu, Mp=wl.Mp)
+        gx, gy = pp.field(x, y, w, h, a, W=wl.W, H=wl.H)
+        outs.append([t.cpu().numpy().copy() for t in (E, a, gx, gy)])
+    for u, v in zip(*outs):
+        assert np.array_equal(u, v)
+
+
+def test_fp64_autograd_matches_field_and_gradcheck():
+    say("[autograd]")
+    wl = make_random(50, 60.0, 40.0, 40, 30, seed=31)
+    x, y, w, h = dev(*wl.arrays())
+    xr = x.clone().requires_grad_(True)
+    yr = y.clone().requires_grad_(True)
+    E = pp.energy_autograd(xr, yr, w, h, W=wl.W, H=wl.H, Mu=wl.Mu, Mp=wl.Mp)
+    (3.0 * E).backward()
+    _, a = pp.energy(x, y, w, h, W=wl.W, H=wl.H, Mu=wl.Mu, Mp=wl.Mp)
+    gx, gy = pp.field(x, y, w, h, a, W=wl.W, H=wl.H)
+    assert torch.allclose(xr.grad, 3.0 * gx, rtol=1e-13, atol=0)
+    assert torch.allclose(yr.grad, 3.0 * gy, rtol=1e-13, atol=0)
+    tiny = make_random(3, 6.0, 5.0, 6, 5, seed=32)
+    tx, ty, tw, th = dev(*tiny.arrays())
+    tx.requires_grad_(True)
+    ty.requires_grad_(True)
+    f = lambda a_, b_: pp.energy_autograd(a_, b_, tw, th, W=tiny.W, H=tiny.H, Mu=tiny.Mu, Mp=tiny.Mp)
+    assert torch.autograd.gradcheck(f, (tx, ty), eps=1e-6, atol=1e-7, rtol=1e-6)
