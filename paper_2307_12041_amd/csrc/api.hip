@@ -14,7 +14,8 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-bool supported_precision(int prec) { return prec == PP_FP64; }
+bool supported_precision(int prec) { return prec == PP_FP64 || prec == PP_BF16 || prec == PP_BF16X3; }
+bool is_bf16(int prec) { return prec == PP_BF16 || prec == PP_BF16X3; }
 
 int validate_problem(const pp_problem *P) {
     if (!P) return PP_ERR_ARG;
@@ -38,7 +39,9 @@ int validate_blocks(const pp_problem *P, const double *x, const double *y, const
 
 FwdPlan fwd_plan(const pp_problem &P) {
     FwdPlan pl{};
-    if (P.Mu >= 128 && P.Mp >= 128) {
+    if (is_bf16(P.precision)) {
+        pl.tu = 256; pl.tp = 256; pl.kb = 32;
+    } else if (P.Mu >= 128 && P.Mp >= 128) {
         pl.tu = 128; pl.tp = 128; pl.kb = 16;
     } else {
         pl.tu = 64; pl.tp = 64; pl.kb = 32;
@@ -57,13 +60,17 @@ FwdPlan fwd_plan(const pp_problem &P) {
     if (pl.chunks_per_split < 1) pl.chunks_per_split = 1;
     pl.splits = (int)((pl.chunks + pl.chunks_per_split - 1) / pl.chunks_per_split);
     if (pl.splits < 1) pl.splits = 1;
-    pl.part_elem = 8;
+    pl.part_elem = is_bf16(P.precision) ? 4 : 8;
     return pl;
 }
 
 BwdPlan bwd_plan(const pp_problem &P) {
     BwdPlan pl{};
-    pl.tb = 128; pl.tn = 128; pl.kk = 32;
+    if (is_bf16(P.precision)) {
+        pl.tb = 256; pl.tn = 256; pl.kk = 32;
+    } else {
+        pl.tb = 128; pl.tn = 128; pl.kk = 32;
+    }
     pl.tiles_b = (P.n + pl.tb - 1) / pl.tb;
     pl.tiles_nx = (P.Mu + pl.tn - 1) / pl.tn;
     pl.tiles_ny = (P.Mp + pl.tn - 1) / pl.tn;
@@ -71,9 +78,15 @@ BwdPlan bwd_plan(const pp_problem &P) {
     return pl;
 }
 
+// K half length of the bf16 backward (K frequencies split over the two lane halves, 16-aligned).
+int bf16_kh(int Ka) { return (Ka + 31) / 32 * 16; }
+
+// Workspace layout.  The phase tables (bf16 path) sit at the start of both regions; the forward
+// region (partials, energy partials) and the backward region (operands, gradient partials) overlap.
 struct Layout {
+    size_t tx, ty;                       // bf16 path: per-block phase records
     size_t part, epart;                  // forward region
-    size_t bx, by, gpx, gpy;             // backward region (overlaps the forward region)
+    size_t bx, by, bxl, byl, gpx, gpy;   // backward region
     size_t fwd_bytes, bwd_bytes, total;
 };
 
@@ -83,12 +96,26 @@ Layout layout(const pp_problem &P) {
     const size_t MM = (size_t)P.Mu * (size_t)P.Mp;
     Layout L{};
     size_t off = 0;
+    if (is_bf16(P.precision)) {
+        L.tx = off; off = align_up(off + (size_t)P.n * sizeof(PhaseRec));
+        L.ty = off; off = align_up(off + (size_t)P.n * sizeof(PhaseRec));
+    }
+    const size_t common = off;
     L.part = off;  off = align_up(off + (size_t)f.splits * MM * f.part_elem);
     L.epart = off; off = align_up(off + (size_t)reduce_scale_blocks(P.Mu, P.Mp) * sizeof(double));
     L.fwd_bytes = off;
-    off = 0;
-    L.bx = off;  off = align_up(off + MM * b.bmat_elem);
-    L.by = off;  off = align_up(off + MM * b.bmat_elem);
+    off = common;
+    if (is_bf16(P.precision)) {
+        const size_t ex = (size_t)b.tiles_nx * 256 * (size_t)(2 * bf16_kh(P.Mp)) * 2;  // gx operand, per hi/lo
+        const size_t ey = (size_t)b.tiles_ny * 256 * (size_t)(2 * bf16_kh(P.Mu)) * 2;  // gy operand
+        L.bx = off;  off = align_up(off + ex);
+        L.bxl = off; off = align_up(off + ex);
+        L.by = off;  off = align_up(off + ey);
+        L.byl = off; off = align_up(off + ey);
+    } else {
+        L.bx = off;  off = align_up(off + MM * b.bmat_elem);
+        L.by = off;  off = align_up(off + MM * b.bmat_elem);
+    }
     L.gpx = off; off = align_up(off + (size_t)b.tiles_nx * (size_t)P.n * sizeof(double));
     L.gpy = off; off = align_up(off + (size_t)b.tiles_ny * (size_t)P.n * sizeof(double));
     L.bwd_bytes = off;
@@ -110,7 +137,15 @@ int run_forward(const pp_problem &P, const double *x, const double *y, const dou
     char *base = (char *)ws;
     void *part = base + L.part;
     double *epart = (double *)(base + L.epart);
-    hipError_t err = launch_fwd_f64(f, P.n, P.Mu, P.Mp, P.W, P.H, x, y, w, h, (double *)part, s);
+    hipError_t err;
+    if (is_bf16(P.precision)) {
+        PhaseRec *tx = (PhaseRec *)(base + L.tx), *ty = (PhaseRec *)(base + L.ty);
+        err = launch_phase_tables(P.n, x, y, w, h, P.W, P.H, tx, ty, s);
+        if (err != hipSuccess) return PP_ERR_DEVICE;
+        err = launch_fwd_bf16(f, P.precision == PP_BF16X3, P.n, P.Mu, P.Mp, tx, ty, (float *)part, s);
+    } else {
+        err = launch_fwd_f64(f, P.n, P.Mu, P.Mp, P.W, P.H, x, y, w, h, (double *)part, s);
+    }
     if (err != hipSuccess) return PP_ERR_DEVICE;
     int nb = 0;
     err = launch_reduce_scale(part, f.part_elem == 4, f.splits, P.Mu, P.Mp, P.W, P.H, a, epart, &nb, s);
@@ -172,8 +207,28 @@ int pp_field(const pp_problem *P, const double *x, const double *y, const double
     hipStream_t s = (hipStream_t)stream;
     const BwdPlan b = bwd_plan(*P);
     char *base = (char *)ws;
-    double *bx = (double *)(base + L.bx), *by = (double *)(base + L.by);
     double *gpx = (double *)(base + L.gpx), *gpy = (double *)(base + L.gpy);
+    if (is_bf16(P->precision)) {
+        const bool x3 = P->precision == PP_BF16X3;
+        PhaseRec *tx = (PhaseRec *)(base + L.tx), *ty = (PhaseRec *)(base + L.ty);
+        unsigned short *bxh = (unsigned short *)(base + L.bx), *bxl = (unsigned short *)(base + L.bxl);
+        unsigned short *byh = (unsigned short *)(base + L.by), *byl = (unsigned short *)(base + L.byl);
+        const int khx = bf16_kh(P->Mp), khy = bf16_kh(P->Mu);
+        if (launch_phase_tables(P->n, x, y, w, h, P->W, P->H, tx, ty, s) != hipSuccess) return PP_ERR_DEVICE;
+        if (launch_prep_bwd_bf16(a, P->Mu, P->Mp, P->W, P->H, 0, b.tiles_nx * 256, khx, bxh, bxl, s) != hipSuccess)
+            return PP_ERR_DEVICE;
+        if (launch_prep_bwd_bf16(a, P->Mu, P->Mp, P->W, P->H, 1, b.tiles_ny * 256, khy, byh, byl, s) != hipSuccess)
+            return PP_ERR_DEVICE;
+        // gx: K = p (basis of y), epilogue over u (x);  gy: K = u (basis of x), epilogue over p (y).
+        BwdAxisBf16 axx{ty, tx, P->Mp, P->Mu, khx, bxh, bxl, gpx};
+        BwdAxisBf16 axy{tx, ty, P->Mu, P->Mp, khy, byh, byl, gpy};
+        if (launch_bwd_bf16(x3, P->n, axx, s) != hipSuccess) return PP_ERR_DEVICE;
+        if (launch_bwd_bf16(x3, P->n, axy, s) != hipSuccess) return PP_ERR_DEVICE;
+        if (launch_bwd_final(gpx, b.tiles_nx, gpy, b.tiles_ny, P->n, dE, gx, gy, s) != hipSuccess)
+            return PP_ERR_DEVICE;
+        return PP_OK;
+    }
+    double *bx = (double *)(base + L.bx), *by = (double *)(base + L.by);
     if (launch_prep_bwd_f64(a, P->Mu, P->Mp, P->W, P->H, bx, by, s) != hipSuccess) return PP_ERR_DEVICE;
     // gx: K = p (basis of y), epilogue over u (cosine differences of x), operand BxT[p][u].
     BwdAxis axx{y, h, P->H, P->Mp, x, w, P->W, P->Mu, bx, gpx};

@@ -49,11 +49,40 @@ struct BwdAxis {
     double *gpart;           // out: [tiles_n][n] partial gradients
 };
 
+// Per-block phase record of one axis, built once per call (80 bytes): for centre c, size sz and
+// axis length L, ta = c / L and tb = sz / (2L) are the phases of the centre and half size in half
+// turns per unit frequency; (ca, sa) = (cos, sin)(pi ta), c2a = 2 cos(pi ta) = c2ah + c2al, the
+// same for tb, the 32-frequency phasors (ca32, sa32) and (cb32, sb32), and the size itself.
+struct __attribute__((aligned(16))) PhaseRec {
+    double ta, tb;
+    float ca, sa, c2ah, c2al;
+    float cb, sb, c2bh, c2bl;
+    float ca32, sa32, cb32, sb32;
+    float size, pad0, pad1, pad2;
+};
+static_assert(sizeof(PhaseRec) == 80, "PhaseRec layout");
+
+// One backward contraction of the bf16 path (gx or gy).
+struct BwdAxisBf16 {
+    const PhaseRec *ta;          // K-axis records (basis generated along K)
+    const PhaseRec *te;          // epilogue-axis records (cosine differences)
+    int Ka, Nb, Kh;              // K frequencies, N frequencies, K half length (multiple of 16)
+    const unsigned short *Bh, *Bl;  // tiled operand, hi and lo bf16
+    double *gpart;               // out: [tiles_n][n]
+};
+
 // ---- launchers (each defined next to its kernels) ----
 hipError_t launch_fwd_f64(const FwdPlan &pl, int64_t n, int Mu, int Mp, double W, double H,
                           const double *x, const double *y, const double *w, const double *h,
                           double *part, hipStream_t s);
 hipError_t launch_bwd_f64(const BwdPlan &pl, int64_t n, const BwdAxis &ax, hipStream_t s);
+hipError_t launch_phase_tables(int64_t n, const double *x, const double *y, const double *w, const double *h,
+                               double W, double H, PhaseRec *tx, PhaseRec *ty, hipStream_t s);
+hipError_t launch_fwd_bf16(const FwdPlan &pl, bool x3, int64_t n, int Mu, int Mp, const PhaseRec *tx,
+                           const PhaseRec *ty, float *part, hipStream_t s);
+hipError_t launch_prep_bwd_bf16(const double *a, int Mu, int Mp, double W, double H, int trans, int Np, int Kh,
+                                unsigned short *Bh, unsigned short *Bl, hipStream_t s);
+hipError_t launch_bwd_bf16(bool x3, int64_t n, const BwdAxisBf16 &ax, hipStream_t s);
 
 // Sum split-K partials (FP64 or FP32), scale, write a, per-block energy partials.
 hipError_t launch_reduce_scale(const void *part, bool part_f32, int splits, int Mu, int Mp, double W,

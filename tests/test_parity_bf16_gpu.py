@@ -1,0 +1,106 @@
+"""GPU parity of the BF16 paths against the FP64 oracle.
+
+PP_BF16X3 (bf16 hi/lo split, three products, FP32 accumulation) must match the oracle within
+1e-3 relative for the coefficients, the energy and the gradient (the split-precision target of
+this method's GPU form); measured errors are ~1e-5.  Plain PP_BF16 is reported with a loose bar
+(single bf16 rounding of every basis value: ~1e-2)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import make_config, make_random
+
+torch = pytest.importorskip("torch")
+pp = pytest.importorskip("paper_2307_12041_amd")
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+TOL = {"bf16x3": 1e-3, "bf16": 3e-2}
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def dev(*arrs):
+    return [torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=DEV) for a in arrs]
+
+
+def rel(a, b):
+    nb = np.linalg.norm(np.ravel(b))
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / (nb if nb > 0 else 1.0)
+
+
+def run(wl, prec):
+    x, y, w, h = dev(*wl.arrays())
+    E, a = pp.energy(x, y, w, h, W=wl.W, H=wl.H, Mu=wl.Mu, Mp=wl.Mp, precision=prec)
+    gx, gy = pp.field(x, y, w, h, a, W=wl.W, H=wl.H, precision=prec)
+    torch.cuda.synchronize()
+    return float(E.cpu()), a.cpu().numpy(), gx.cpu().numpy(), gy.cpu().numpy()
+
+
+def check(wl, prec, grad_sample=None):
+    say(f"[parity] {wl.name} n={wl.n} Mu={wl.Mu} Mp={wl.Mp} prec={prec}")
+    E, a, gx, gy = run(wl, prec)
+    Eo, ao, _ = oracle.energy(wl.W, wl.H, *wl.arrays(), wl.Mu, wl.Mp)
+    if grad_sample is None:
+        gxo, gyo = oracle.grad(wl.W, wl.H, *wl.arrays(), ao)
+        g, go = np.concatenate([gx, gy]), np.concatenate([gxo, gyo])
+    else:
+        idx = np.random.default_rng(0).choice(wl.n, grad_sample, replace=False)
+        gxo, gyo = oracle.grad_sampled(wl.W, wl.H, *wl.arrays(), ao, idx)
+        g, go = np.concatenate([gx[idx], gy[idx]]), np.concatenate([gxo, gyo])
+    ea, eE, eg = rel(a, ao), abs(E - Eo) / abs(Eo), rel(g, go)
+    say(f"   rel err a={ea:.3e} E={eE:.3e} g={eg:.3e}")
+    tol = TOL[prec]
+    assert ea <= tol and eE <= tol and eg <= tol, (ea, eE, eg)
+    return ea, eE, eg
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16"])
+@pytest.mark.parametrize("n,Mu,Mp,W,H,seed", [
+    (1, 5, 3, 10.0, 7.0, 0),
+    (37, 24, 20, 100.0, 60.0, 1),
+    (1000, 64, 64, 1024.0, 1024.0, 2),
+    (3001, 300, 150, 500.0, 300.0, 3),
+    (5000, 257, 513, 300.0, 900.0, 4),
+    (700, 40, 600, 64.0, 800.0, 5),
+])
+def test_bf16_parity_shapes(prec, n, Mu, Mp, W, H, seed):
+    check(make_random(n, W, H, Mu, Mp, seed=seed), prec)
+
+
+def test_bf16x3_parity_overhanging_and_macros():
+    wl = make_random(800, 400.0, 300.0, 96, 80, seed=8, wmax=60.0, hmax=40.0, inside=False)
+    check(wl, "bf16x3")
+
+
+def test_bf16x3_parity_cells200k_macros50_M512():
+    wl = make_config(2)
+    check(wl, "bf16x3", grad_sample=3000)
+
+
+def test_bf16x3_zero_blocks_and_determinism():
+    say("[edge] n=0, determinism")
+    x = torch.empty(0, dtype=torch.float64, device=DEV)
+    E, a = pp.energy(x, x, x, x, W=10.0, H=10.0, Mu=17, Mp=9, precision="bf16x3")
+    assert float(E.cpu()) == 0.0 and float(a.abs().max().cpu()) == 0.0
+    wl = make_random(20000, 700.0, 500.0, 300, 280, seed=21, wmax=8, hmax=2)
+    outs = [run(wl, "bf16x3") for _ in range(2)]
+    for u, v in zip(*outs):
+        assert np.array_equal(u, v)
+
+
+def test_bf16x3_autograd_matches_field():
+    say("[autograd bf16x3]")
+    wl = make_random(500, 60.0, 40.0, 64, 48, seed=31)
+    x, y, w, h = dev(*wl.arrays())
+    xr = x.clone().requires_grad_(True)
+    yr = y.clone().requires_grad_(True)
+    E = pp.energy_autograd(xr, yr, w, h, W=wl.W, H=wl.H, Mu=wl.Mu, Mp=wl.Mp, precision="bf16x3")
+    E.backward()
+    _, a = pp.energy(x, y, w, h, W=wl.W, H=wl.H, Mu=wl.Mu, Mp=wl.Mp, precision="bf16x3")
+    gx, gy = pp.field(x, y, w, h, a, W=wl.W, H=wl.H, precision="bf16x3")
+    assert torch.equal(xr.grad, gx) and torch.equal(yr.grad, gy)
