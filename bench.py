@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""Benchmark of the truncated cosine-series Poisson solution (arXiv 2307.12041, Sec. III-A/III-C).
+
+One step = one full evaluation of the hot path on one batch of blocks: the coefficient
+contraction, reduction, spectral scale and energy (pp_energy) followed by the per-block
+energy gradient (pp_field).  Work unit: one (block, u, p) triple, n * Mu * Mp "pairs" per step.
+
+Default workload: 2,000,000 standard cells (width U[1,8], height 1) + 500 macros (sides U[50,400]),
+centres uniform in a 16384 x 16384 region, truncation Mu x Mp = 2048 x 2048, precision bf16x3.
+Inputs are synthetic (seeded, see workloads/), resident in HBM before the timed region.
+
+Printed: one JSON line with the throughput, the roofline of the dominant kernel (its average
+launch duration measured live with HIP events on the launching stream), the FP64 plain
+throughput on the same workload, accuracy figures, and the FP64 oracle timed on the host on a
+bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "block·freq² pairs/s for energy+forces, BF16-split vs FP64 plain, at rel err"
+PEAK_TFLOPS = {"bf16x3": 2500.0, "bf16": 2500.0, "fp64": 78.6}   # MI355X dense matrix peaks
+MFMA_MULT = {"bf16x3": 3, "bf16": 1, "fp64": 1}                   # executed MFMA products per algorithmic one
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rel(a, b):
+    nb = float(np.linalg.norm(np.ravel(b)))
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b))) / (nb if nb > 0 else 1.0)
+
+
+def timed_steps(pp, torch, t, wl, prec, steps, warmup, ws):
+    kw = dict(W=wl.W, H=wl.H, precision=prec, workspace=ws)
+    for _ in range(warmup):
+        E, a = pp.energy(*t, Mu=wl.Mu, Mp=wl.Mp, **kw)
+        pp.field(*t, a, **kw)
+    torch.cuda.synchronize()
+    pp.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        E, a = pp.energy(*t, Mu=wl.Mu, Mp=wl.Mp, **kw)
+        gx, gy = pp.field(*t, a, **kw)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = {}
+    for st in ("tables", "fwd", "reduce", "energy", "prep", "bwd", "final"):
+        ms, cnt = pp.timing_query(st)
+        if cnt:
+            stages[st] = (ms, cnt)
+    pp.timing_enable(False)
+    return (t1 - t0), stages, (E, a, gx, gy)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", type=int, default=4, help="workload index in workloads.CONFIGS")
+    ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "bf16", "fp64"])
+    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=12000, help="blocks in the oracle's timed sample")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus > 1 or world > 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
+              "the multi-GPU sharding (blocks split over GPUs, one all-reduce of the Mu x Mp moments) is a "
+              "design, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2307_12041_amd as pp
+    from workloads import make_config
+
+    dev = "cuda:0"
+    wl = make_config(args.workload)
+    pairs = wl.pairs
+    log(f"[bench] workload {wl.name}: n={wl.n} Mu={wl.Mu} Mp={wl.Mp} pairs/step={pairs:.3e}")
+    t = [torch.as_tensor(v, device=dev) for v in wl.arrays()]
+    need = max(pp.workspace_size(wl.W, wl.H, wl.n, wl.Mu, wl.Mp, precision=p) for p in (args.precision, "fp64"))
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    log(f"[bench] workspace {need / 2**20:.1f} MiB")
+
+    dt, stages, (E, a, gx, gy) = timed_steps(pp, torch, t, wl, args.precision, args.steps, args.warmup, ws)
+    value = pairs * args.steps / dt
+    log(f"[bench] {args.precision}: {dt / args.steps * 1e3:.2f} ms/step, {value:.4e} pairs/s; stages "
+        + ", ".join(f"{k}={v[0] / v[1]:.2f}ms x{v[1] // args.steps}" for k, v in stages.items()))
+
+    # Roofline of the dominant kernel: the stage with the largest total time.
+    dom = max(("fwd", "bwd"), key=lambda s: stages[s][0])
+    avg_ms = stages[dom][0] / stages[dom][1]
+    alg_flops = 2.0 * pairs                  # one contraction: 2 flops per (block, u, p)
+    achieved = alg_flops / (avg_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    kernel_name = {"fwd": "k_fwd_bf16<x3> (coefficient contraction)",
+                   "bwd": "k_bwd_bf16<x3> (gradient contraction, gx and gy launches)"}[dom]
+    if args.precision == "fp64":
+        kernel_name = {"fwd": "k_fwd_f64", "bwd": "k_bwd_f64"}[dom]
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": None,
+                "kernel": kernel_name, "avg_launch_ms": round(avg_ms, 3), "launches_per_step": stages[dom][1] // args.steps,
+                "algorithmic_flops_per_launch": alg_flops,
+                "executed_mfma_tflops": round(achieved * MFMA_MULT[args.precision], 2),
+                "executed_mfma_frac": round(achieved * MFMA_MULT[args.precision] / peak, 4)}
+
+    out = {"metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "bf16" if args.precision.startswith("bf16") else "f64",
+           "data": "synthetic",
+           "config": {"workload": wl.name, "n_blocks": wl.n, "Mu": wl.Mu, "Mp": wl.Mp, "W": wl.W, "H": wl.H,
+                      "precision": args.precision, "basis": "recompute", "pairs_per_step": pairs},
+           "stages_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stages.items()},
+           "roofline": roofline}
+
+    ref = None
+    if not args.no_fp64 and args.precision != "fp64":
+        dt64, st64, ref = timed_steps(pp, torch, t, wl, "fp64", args.fp64_steps, 1, ws)
+        v64 = pairs * args.fp64_steps / dt64
+        log(f"[bench] fp64 plain: {dt64 / args.fp64_steps * 1e3:.1f} ms/step, {v64:.4e} pairs/s")
+        out["fp64_plain"] = {"value": v64, "unit": "pairs/s", "ms_per_step": dt64 / args.fp64_steps * 1e3,
+                             "steps": args.fp64_steps,
+                             "stages_ms_per_step": {k: round(v[0] / args.fp64_steps, 3) for k, v in st64.items()}}
+        out["speedup_vs_fp64_plain"] = value / v64
+
+    if not args.no_accuracy:
+        import oracle
+        acc = {}
+        rng = np.random.default_rng(12345)
+        us = np.concatenate([[1, 0, 1, 2, 0], rng.integers(0, wl.Mu, 59)])
+        ps = np.concatenate([[0, 1, 1, 0, 2], rng.integers(0, wl.Mp, 59)])
+        t0 = time.perf_counter()
+        ao, _ = oracle.coeffs_sampled(wl.W, wl.H, *wl.arrays(), us, ps)
+        acc["oracle_sample"] = f"{len(us)} coefficients a_up over all {wl.n} blocks, FP64 oracle"
+        a_np = a.cpu().numpy()
+        acc["a_sampled_vs_oracle"] = rel(a_np[us, ps], ao)
+        log(f"[bench] oracle coefficient sample in {time.perf_counter() - t0:.1f} s")
+        if ref is not None:
+            E64, a64, gx64, gy64 = (v.cpu().numpy() for v in ref)
+            acc["fp64_a_sampled_vs_oracle"] = rel(a64[us, ps], ao)
+            acc["E_vs_fp64_gpu"] = abs(float(E.cpu()) - float(E64)) / abs(float(E64))
+            acc["a_vs_fp64_gpu"] = rel(a_np, a64)
+            g = np.concatenate([gx.cpu().numpy(), gy.cpu().numpy()])
+            g64 = np.concatenate([gx64, gy64])
+            acc["g_vs_fp64_gpu"] = rel(g, g64)
+            acc["g_max_block_vs_fp64_gpu"] = float(np.max(np.hypot(gx.cpu().numpy() - gx64, gy.cpu().numpy() - gy64))
+                                                   / np.max(np.hypot(gx64, gy64)))
+        out["rel_err"] = acc
+        log(f"[bench] rel err {acc}")
+
+    if not args.no_cpu_baseline:
+        import oracle
+        rng = np.random.default_rng(777)
+        idx = np.sort(rng.choice(wl.n, args.cpu_sample, replace=False))
+        xs, ys, wsz, hs = (v[idx] for v in wl.arrays())
+        t0 = time.perf_counter()
+        Eo, ao, _ = oracle.energy(wl.W, wl.H, xs, ys, wsz, hs, wl.Mu, wl.Mp)
+        oracle.grad(wl.W, wl.H, xs, ys, wsz, hs, ao)
+        tc = time.perf_counter() - t0
+        cp = args.cpu_sample * wl.Mu * wl.Mp
+        out["cpu_baseline"] = {"value": cp / tc, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": f"energy + gradient of {args.cpu_sample} blocks drawn (seeded) from the "
+                                         f"{wl.n}-block workload at the full {wl.Mu}x{wl.Mp} truncation, FP64 "
+                                         f"direct summation; {tc:.1f} s",
+                               "seconds": tc}
+        log(f"[bench] oracle: {tc:.1f} s for {cp:.3e} pairs on {oracle.num_threads()} threads")
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -110,6 +110,20 @@ int pp_field(const pp_problem *P, const double *x, const double *y, const double
 /* Static description of a status code. */
 const char *pp_strerror(int status);
 
+/* Measurement hooks (they do not change any result).
+ * pp_timing_enable(1) makes every later library call record a pair of HIP events around each
+ * kernel launch it enqueues, on the caller's stream; pp_timing_enable(0) stops recording.  Either
+ * call first discards all earlier records and their events.
+ * pp_timing_query(name, &ms, &count) waits for the recorded events of one stage and returns their
+ * summed duration in milliseconds and the number of launches.  Stage names: "tables" (per-block
+ * phase records), "fwd" (coefficient contraction), "reduce" (split-K sum, scale, energy
+ * partials), "energy" (final energy sum), "prep" (backward operands), "bwd" (the two gradient
+ * contractions, one record each), "final" (gradient partial sums).  Unknown names give count 0.
+ * Returns PP_OK, PP_ERR_ARG for NULL arguments, PP_ERR_DEVICE if an event query fails.  Recording
+ * is process wide and guarded by a lock; it is meant for benchmarks, not for production calls. */
+int pp_timing_enable(int on);
+int pp_timing_query(const char *name, double *total_ms, int *count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,7 +18,7 @@ import os
 import torch
 
 __all__ = ["PRECISIONS", "BASIS_MODES", "PPError", "library_path", "load", "workspace_size", "coeffs",
-           "energy", "field", "PPEnergy", "energy_autograd"]
+           "energy", "field", "PPEnergy", "energy_autograd", "timing_enable", "timing_query"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libpplace.so")
@@ -27,7 +27,8 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "fp8": 4, "fp8x3": 5
 BASIS_MODES = {"recompute": 0, "store": 1}
 
 PP_OK = 0
-EXPORTS = ("pp_workspace_size", "pp_coeffs", "pp_energy", "pp_field", "pp_strerror")
+EXPORTS = ("pp_workspace_size", "pp_coeffs", "pp_energy", "pp_field", "pp_strerror", "pp_timing_enable",
+           "pp_timing_query")
 
 
 class PPError(RuntimeError):
@@ -65,6 +66,10 @@ def load():
     lib.pp_field.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.pp_strerror.argtypes = [ctypes.c_int]
     lib.pp_strerror.restype = ctypes.c_char_p
+    lib.pp_timing_enable.argtypes = [ctypes.c_int]
+    lib.pp_timing_enable.restype = ctypes.c_int
+    lib.pp_timing_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
+    lib.pp_timing_query.restype = ctypes.c_int
     for f in ("pp_workspace_size", "pp_coeffs", "pp_energy", "pp_field"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
@@ -117,21 +122,26 @@ def _stream(dev):
     return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
 
 
-def _workspace(P, dev):
+def _workspace(P, dev, workspace=None):
+    """The caller's workspace if given (a uint8 device tensor, large enough), else a fresh one."""
     nbytes = ctypes.c_size_t(0)
     st = load().pp_workspace_size(ctypes.byref(P), ctypes.byref(nbytes))
     if st != PP_OK:
         raise PPError(st, "pp_workspace_size")
+    if workspace is not None:
+        if workspace.device != dev or workspace.dtype != torch.uint8 or not workspace.is_contiguous():
+            raise ValueError("workspace must be a contiguous uint8 tensor on the blocks' device")
+        return workspace, int(workspace.numel())
     ws = torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device=dev)
     return ws, int(nbytes.value)
 
 
-def coeffs(x, y, w, h, *, W, H, Mu, Mp, precision="fp64", basis="recompute"):
+def coeffs(x, y, w, h, *, W, H, Mu, Mp, precision="fp64", basis="recompute", workspace=None):
     """Series coefficients a [Mu, Mp] (FP64, on the device of x)."""
     dev, n = _blocks(x, y, w, h)
     P = _problem(W, H, n, Mu, Mp, precision, basis)
     a = torch.empty((Mu, Mp), dtype=torch.float64, device=dev)
-    ws, nb = _workspace(P, dev)
+    ws, nb = _workspace(P, dev, workspace)
     with torch.cuda.device(dev):
         st = load().pp_coeffs(ctypes.byref(P), _vp(x), _vp(y), _vp(w), _vp(h), _vp(a), _vp(ws), nb, _stream(dev))
     if st != PP_OK:
@@ -139,13 +149,13 @@ def coeffs(x, y, w, h, *, W, H, Mu, Mp, precision="fp64", basis="recompute"):
     return a
 
 
-def energy(x, y, w, h, *, W, H, Mu, Mp, precision="fp64", basis="recompute", want_coeffs=True):
+def energy(x, y, w, h, *, W, H, Mu, Mp, precision="fp64", basis="recompute", want_coeffs=True, workspace=None):
     """Energy E (0-d FP64 tensor) and, if asked, the coefficients a [Mu, Mp]."""
     dev, n = _blocks(x, y, w, h)
     P = _problem(W, H, n, Mu, Mp, precision, basis)
     E = torch.empty((), dtype=torch.float64, device=dev)
     a = torch.empty((Mu, Mp), dtype=torch.float64, device=dev) if want_coeffs else None
-    ws, nb = _workspace(P, dev)
+    ws, nb = _workspace(P, dev, workspace)
     with torch.cuda.device(dev):
         st = load().pp_energy(ctypes.byref(P), _vp(x), _vp(y), _vp(w), _vp(h), _vp(E), _vp(a), _vp(ws), nb,
                               _stream(dev))
@@ -154,7 +164,7 @@ def energy(x, y, w, h, *, W, H, Mu, Mp, precision="fp64", basis="recompute", wan
     return E, a
 
 
-def field(x, y, w, h, a, *, W, H, precision="fp64", basis="recompute", dE=None):
+def field(x, y, w, h, a, *, W, H, precision="fp64", basis="recompute", dE=None, workspace=None):
     """Per-block gradient (gx, gy) = dE * (dE/dx_i, dE/dy_i); the force on block i is -(gx, gy)."""
     dev, n = _blocks(x, y, w, h)
     if a.dtype != torch.float64 or a.dim() != 2 or not a.is_contiguous() or a.device != dev:
@@ -165,13 +175,28 @@ def field(x, y, w, h, a, *, W, H, precision="fp64", basis="recompute", dE=None):
         dE = dE.to(device=dev, dtype=torch.float64).contiguous()
     gx = torch.empty(n, dtype=torch.float64, device=dev)
     gy = torch.empty(n, dtype=torch.float64, device=dev)
-    ws, nb = _workspace(P, dev)
+    ws, nb = _workspace(P, dev, workspace)
     with torch.cuda.device(dev):
         st = load().pp_field(ctypes.byref(P), _vp(x), _vp(y), _vp(w), _vp(h), _vp(a), _vp(dE), _vp(gx), _vp(gy),
                              _vp(ws), nb, _stream(dev))
     if st != PP_OK:
         raise PPError(st, "pp_field")
     return gx, gy
+
+
+def timing_enable(on: bool) -> None:
+    """Start (or stop) HIP-event timing of every kernel launch of the library; clears records."""
+    load().pp_timing_enable(1 if on else 0)
+
+
+def timing_query(stage: str):
+    """(total_ms, launches) recorded for one stage since timing_enable (waits for the events)."""
+    ms = ctypes.c_double(0.0)
+    cnt = ctypes.c_int(0)
+    st = load().pp_timing_query(stage.encode(), ctypes.byref(ms), ctypes.byref(cnt))
+    if st != PP_OK:
+        raise PPError(st, "pp_timing_query")
+    return float(ms.value), int(cnt.value)
 
 
 class PPEnergy(torch.autograd.Function):

@@ -140,18 +140,19 @@ int run_forward(const pp_problem &P, const double *x, const double *y, const dou
     hipError_t err;
     if (is_bf16(P.precision)) {
         PhaseRec *tx = (PhaseRec *)(base + L.tx), *ty = (PhaseRec *)(base + L.ty);
-        err = launch_phase_tables(P.n, x, y, w, h, P.W, P.H, tx, ty, s);
+        { TimedLaunch t("tables", s); err = launch_phase_tables(P.n, x, y, w, h, P.W, P.H, tx, ty, s); }
         if (err != hipSuccess) return PP_ERR_DEVICE;
-        err = launch_fwd_bf16(f, P.precision == PP_BF16X3, P.n, P.Mu, P.Mp, tx, ty, (float *)part, s);
+        { TimedLaunch t("fwd", s); err = launch_fwd_bf16(f, P.precision == PP_BF16X3, P.n, P.Mu, P.Mp, tx, ty, (float *)part, s); }
     } else {
+        TimedLaunch t("fwd", s);
         err = launch_fwd_f64(f, P.n, P.Mu, P.Mp, P.W, P.H, x, y, w, h, (double *)part, s);
     }
     if (err != hipSuccess) return PP_ERR_DEVICE;
     int nb = 0;
-    err = launch_reduce_scale(part, f.part_elem == 4, f.splits, P.Mu, P.Mp, P.W, P.H, a, epart, &nb, s);
+    { TimedLaunch t("reduce", s); err = launch_reduce_scale(part, f.part_elem == 4, f.splits, P.Mu, P.Mp, P.W, P.H, a, epart, &nb, s); }
     if (err != hipSuccess) return PP_ERR_DEVICE;
     if (E) {
-        err = launch_energy_final(epart, nb, E, s);
+        { TimedLaunch t("energy", s); err = launch_energy_final(epart, nb, E, s); }
         if (err != hipSuccess) return PP_ERR_DEVICE;
     }
     return PP_OK;
@@ -214,29 +215,31 @@ int pp_field(const pp_problem *P, const double *x, const double *y, const double
         unsigned short *bxh = (unsigned short *)(base + L.bx), *bxl = (unsigned short *)(base + L.bxl);
         unsigned short *byh = (unsigned short *)(base + L.by), *byl = (unsigned short *)(base + L.byl);
         const int khx = bf16_kh(P->Mp), khy = bf16_kh(P->Mu);
-        if (launch_phase_tables(P->n, x, y, w, h, P->W, P->H, tx, ty, s) != hipSuccess) return PP_ERR_DEVICE;
-        if (launch_prep_bwd_bf16(a, P->Mu, P->Mp, P->W, P->H, 0, b.tiles_nx * 256, khx, bxh, bxl, s) != hipSuccess)
-            return PP_ERR_DEVICE;
-        if (launch_prep_bwd_bf16(a, P->Mu, P->Mp, P->W, P->H, 1, b.tiles_ny * 256, khy, byh, byl, s) != hipSuccess)
-            return PP_ERR_DEVICE;
+        { TimedLaunch t("tables", s); if (launch_phase_tables(P->n, x, y, w, h, P->W, P->H, tx, ty, s) != hipSuccess) return PP_ERR_DEVICE; }
+        {
+            TimedLaunch t("prep", s);
+            if (launch_prep_bwd_bf16(a, P->Mu, P->Mp, P->W, P->H, 0, b.tiles_nx * 256, khx, bxh, bxl, s) != hipSuccess)
+                return PP_ERR_DEVICE;
+            if (launch_prep_bwd_bf16(a, P->Mu, P->Mp, P->W, P->H, 1, b.tiles_ny * 256, khy, byh, byl, s) != hipSuccess)
+                return PP_ERR_DEVICE;
+        }
         // gx: K = p (basis of y), epilogue over u (x);  gy: K = u (basis of x), epilogue over p (y).
         BwdAxisBf16 axx{ty, tx, P->Mp, P->Mu, khx, bxh, bxl, gpx};
         BwdAxisBf16 axy{tx, ty, P->Mu, P->Mp, khy, byh, byl, gpy};
-        if (launch_bwd_bf16(x3, P->n, axx, s) != hipSuccess) return PP_ERR_DEVICE;
-        if (launch_bwd_bf16(x3, P->n, axy, s) != hipSuccess) return PP_ERR_DEVICE;
-        if (launch_bwd_final(gpx, b.tiles_nx, gpy, b.tiles_ny, P->n, dE, gx, gy, s) != hipSuccess)
-            return PP_ERR_DEVICE;
+        { TimedLaunch t("bwd", s); if (launch_bwd_bf16(x3, P->n, axx, s) != hipSuccess) return PP_ERR_DEVICE; }
+        { TimedLaunch t("bwd", s); if (launch_bwd_bf16(x3, P->n, axy, s) != hipSuccess) return PP_ERR_DEVICE; }
+        { TimedLaunch t("final", s); if (launch_bwd_final(gpx, b.tiles_nx, gpy, b.tiles_ny, P->n, dE, gx, gy, s) != hipSuccess) return PP_ERR_DEVICE; }
         return PP_OK;
     }
     double *bx = (double *)(base + L.bx), *by = (double *)(base + L.by);
-    if (launch_prep_bwd_f64(a, P->Mu, P->Mp, P->W, P->H, bx, by, s) != hipSuccess) return PP_ERR_DEVICE;
+    { TimedLaunch t("prep", s); if (launch_prep_bwd_f64(a, P->Mu, P->Mp, P->W, P->H, bx, by, s) != hipSuccess) return PP_ERR_DEVICE; }
     // gx: K = p (basis of y), epilogue over u (cosine differences of x), operand BxT[p][u].
     BwdAxis axx{y, h, P->H, P->Mp, x, w, P->W, P->Mu, bx, gpx};
     // gy: K = u (basis of x), epilogue over p (cosine differences of y), operand By[u][p].
     BwdAxis axy{x, w, P->W, P->Mu, y, h, P->H, P->Mp, by, gpy};
-    if (launch_bwd_f64(b, P->n, axx, s) != hipSuccess) return PP_ERR_DEVICE;
-    if (launch_bwd_f64(b, P->n, axy, s) != hipSuccess) return PP_ERR_DEVICE;
-    if (launch_bwd_final(gpx, b.tiles_nx, gpy, b.tiles_ny, P->n, dE, gx, gy, s) != hipSuccess) return PP_ERR_DEVICE;
+    { TimedLaunch t("bwd", s); if (launch_bwd_f64(b, P->n, axx, s) != hipSuccess) return PP_ERR_DEVICE; }
+    { TimedLaunch t("bwd", s); if (launch_bwd_f64(b, P->n, axy, s) != hipSuccess) return PP_ERR_DEVICE; }
+    { TimedLaunch t("final", s); if (launch_bwd_final(gpx, b.tiles_nx, gpy, b.tiles_ny, P->n, dE, gx, gy, s) != hipSuccess) return PP_ERR_DEVICE; }
     return PP_OK;
 }
 

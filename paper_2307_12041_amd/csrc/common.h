@@ -71,6 +71,18 @@ struct BwdAxisBf16 {
     double *gpart;               // out: [tiles_n][n]
 };
 
+// Brackets one kernel launch with HIP events when event timing is on (timing.hip).
+class TimedLaunch {
+  public:
+    TimedLaunch(const char *name, hipStream_t s);
+    ~TimedLaunch();
+  private:
+    const char *name_;
+    hipStream_t s_;
+    void *start_ = nullptr, *stop_ = nullptr;
+    bool active_ = false;
+};
+
 // ---- launchers (each defined next to its kernels) ----
 hipError_t launch_fwd_f64(const FwdPlan &pl, int64_t n, int Mu, int Mp, double W, double H,
                           const double *x, const double *y, const double *w, const double *h,
