@@ -78,15 +78,16 @@ BwdPlan bwd_plan(const pp_problem &P) {
     return pl;
 }
 
-// K half length of the bf16 backward (K frequencies split over the two lane halves, 16-aligned).
-int bf16_kh(int Ka) { return (Ka + 31) / 32 * 16; }
+// K half length of the bf16 backward (K frequencies split over the two lane halves; chunks of 32
+// per half).
+int bf16_kh(int Ka) { return (Ka + 63) / 64 * 32; }
 
 // Workspace layout.  The phase tables (bf16 path) sit at the start of both regions; the forward
 // region (partials, energy partials) and the backward region (operands, gradient partials) overlap.
 struct Layout {
     size_t tx, ty;                       // bf16 path: per-block phase records
     size_t part, epart;                  // forward region
-    size_t bx, by, bxl, byl, gpx, gpy;   // backward region
+    size_t bx, by, gpx, gpy;             // backward region
     size_t fwd_bytes, bwd_bytes, total;
 };
 
@@ -106,12 +107,10 @@ Layout layout(const pp_problem &P) {
     L.fwd_bytes = off;
     off = common;
     if (is_bf16(P.precision)) {
-        const size_t ex = (size_t)b.tiles_nx * 256 * (size_t)(2 * bf16_kh(P.Mp)) * 2;  // gx operand, per hi/lo
-        const size_t ey = (size_t)b.tiles_ny * 256 * (size_t)(2 * bf16_kh(P.Mu)) * 2;  // gy operand
+        const size_t ex = bwd_bf16_operand_elems(b.tiles_nx * 256, bf16_kh(P.Mp)) * 2;  // gx operand, bytes
+        const size_t ey = bwd_bf16_operand_elems(b.tiles_ny * 256, bf16_kh(P.Mu)) * 2;  // gy operand, bytes
         L.bx = off;  off = align_up(off + ex);
-        L.bxl = off; off = align_up(off + ex);
         L.by = off;  off = align_up(off + ey);
-        L.byl = off; off = align_up(off + ey);
     } else {
         L.bx = off;  off = align_up(off + MM * b.bmat_elem);
         L.by = off;  off = align_up(off + MM * b.bmat_elem);
@@ -212,20 +211,19 @@ int pp_field(const pp_problem *P, const double *x, const double *y, const double
     if (is_bf16(P->precision)) {
         const bool x3 = P->precision == PP_BF16X3;
         PhaseRec *tx = (PhaseRec *)(base + L.tx), *ty = (PhaseRec *)(base + L.ty);
-        unsigned short *bxh = (unsigned short *)(base + L.bx), *bxl = (unsigned short *)(base + L.bxl);
-        unsigned short *byh = (unsigned short *)(base + L.by), *byl = (unsigned short *)(base + L.byl);
+        unsigned short *bxt = (unsigned short *)(base + L.bx), *byt = (unsigned short *)(base + L.by);
         const int khx = bf16_kh(P->Mp), khy = bf16_kh(P->Mu);
         { TimedLaunch t("tables", s); if (launch_phase_tables(P->n, x, y, w, h, P->W, P->H, tx, ty, s) != hipSuccess) return PP_ERR_DEVICE; }
         {
             TimedLaunch t("prep", s);
-            if (launch_prep_bwd_bf16(a, P->Mu, P->Mp, P->W, P->H, 0, b.tiles_nx * 256, khx, bxh, bxl, s) != hipSuccess)
+            if (launch_prep_bwd_bf16(a, P->Mu, P->Mp, P->W, P->H, 0, b.tiles_nx * 256, khx, bxt, s) != hipSuccess)
                 return PP_ERR_DEVICE;
-            if (launch_prep_bwd_bf16(a, P->Mu, P->Mp, P->W, P->H, 1, b.tiles_ny * 256, khy, byh, byl, s) != hipSuccess)
+            if (launch_prep_bwd_bf16(a, P->Mu, P->Mp, P->W, P->H, 1, b.tiles_ny * 256, khy, byt, s) != hipSuccess)
                 return PP_ERR_DEVICE;
         }
         // gx: K = p (basis of y), epilogue over u (x);  gy: K = u (basis of x), epilogue over p (y).
-        BwdAxisBf16 axx{ty, tx, P->Mp, P->Mu, khx, bxh, bxl, gpx};
-        BwdAxisBf16 axy{tx, ty, P->Mu, P->Mp, khy, byh, byl, gpy};
+        BwdAxisBf16 axx{ty, tx, P->Mp, P->Mu, khx, bxt, gpx};
+        BwdAxisBf16 axy{tx, ty, P->Mu, P->Mp, khy, byt, gpy};
         { TimedLaunch t("bwd", s); if (launch_bwd_bf16(x3, P->n, axx, s) != hipSuccess) return PP_ERR_DEVICE; }
         { TimedLaunch t("bwd", s); if (launch_bwd_bf16(x3, P->n, axy, s) != hipSuccess) return PP_ERR_DEVICE; }
         { TimedLaunch t("final", s); if (launch_bwd_final(gpx, b.tiles_nx, gpy, b.tiles_ny, P->n, dE, gx, gy, s) != hipSuccess) return PP_ERR_DEVICE; }

@@ -66,8 +66,8 @@ static_assert(sizeof(PhaseRec) == 80, "PhaseRec layout");
 struct BwdAxisBf16 {
     const PhaseRec *ta;          // K-axis records (basis generated along K)
     const PhaseRec *te;          // epilogue-axis records (cosine differences)
-    int Ka, Nb, Kh;              // K frequencies, N frequencies, K half length (multiple of 16)
-    const unsigned short *Bh, *Bl;  // tiled operand, hi and lo bf16
+    int Ka, Nb, Kh;              // K frequencies, N frequencies, K half length (multiple of 32)
+    const unsigned short *B;     // tiled operand (hi and lo bf16, see k_prep_bwd_bf16)
     double *gpart;               // out: [tiles_n][n]
 };
 
@@ -93,7 +93,8 @@ hipError_t launch_phase_tables(int64_t n, const double *x, const double *y, cons
 hipError_t launch_fwd_bf16(const FwdPlan &pl, bool x3, int64_t n, int Mu, int Mp, const PhaseRec *tx,
                            const PhaseRec *ty, float *part, hipStream_t s);
 hipError_t launch_prep_bwd_bf16(const double *a, int Mu, int Mp, double W, double H, int trans, int Np, int Kh,
-                                unsigned short *Bh, unsigned short *Bl, hipStream_t s);
+                                unsigned short *B, hipStream_t s);
+size_t bwd_bf16_operand_elems(int Np, int Kh);   // bf16 elements of one tiled backward operand
 hipError_t launch_bwd_bf16(bool x3, int64_t n, const BwdAxisBf16 &ax, hipStream_t s);
 
 // Sum split-K partials (FP64 or FP32), scale, write a, per-block energy partials.

@@ -33,10 +33,29 @@ typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ double reduce_half_turns(double t) { return t - 2.0 * rint(0.5 * t); }
 
-// cos/sin of pi*(k*t) for integer k, with the product reduced in FP64.
+// sin(pi r), cos(pi r) for |r| <= 1 in fp32: quarter-turn reduction f = r - q/2, |f| <= 1/4, then
+// odd/even polynomials in f^2 (coefficients fitted by csrc/fit_sincospi.py; max error < 9e-8).
+__device__ __forceinline__ void sincospi_seed(float r, float &s, float &c) {
+    const float q = rintf(2.0f * r);
+    const float f = fmaf(-0.5f, q, r);
+    const float x = f * f;
+    const float sp = f * fmaf(x, fmaf(x, fmaf(x, -5.893013400e-01f, 2.549791082e+00f), -5.167708535e+00f),
+                              3.141592649e+00f);
+    const float cp = fmaf(x, fmaf(x, fmaf(x, fmaf(x, 2.314641957e-01f, -1.335062776e+00f), 4.058708069e+00f),
+                                  -4.934802175e+00f), 1.0f);
+    const int iq = (int)q;
+    const bool sw = iq & 1;
+    const float s0 = sw ? cp : sp, c0 = sw ? sp : cp;
+    // quadrant signs: q = 0: (s, c); 1: (c, -s); 2: (-s, -c); 3 (= -1): (-c, s)
+    const unsigned ns = ((unsigned)iq & 2u) << 30, nc = ((unsigned)(iq + 1) & 2u) << 30;
+    s = __builtin_bit_cast(float, __builtin_bit_cast(unsigned, s0) ^ ns);
+    c = __builtin_bit_cast(float, __builtin_bit_cast(unsigned, c0) ^ nc);
+}
+
+// cos/sin of pi*(k*t) for integer k, with the product reduced in FP64 to [-1, 1] half turns.
 __device__ __forceinline__ void seed_phasor(int k, double t, float &c, float &s) {
     const float r = (float)reduce_half_turns((double)k * t);
-    sincospif(r, &s, &c);
+    sincospi_seed(r, s, c);
 }
 
 __device__ __forceinline__ unsigned pack_bf16(float a, float b) {
@@ -99,109 +118,168 @@ namespace {
 // (u-half w / 4, p-quarter w % 4); waves w and w + 4 share a SIMD.  Per chunk of 32 blocks the
 // group of waves 0-3 generates the X tile, the group of waves 4-7 the Y tile; while one group
 // contracts chunk c from one LDS buffer the other generates chunk c + 1 into the other buffer.
-// LDS tile layout: [block][frequency] bf16, rows padded to 544 bytes; MFMA operands are read
-// with the transpose read.
+// LDS tile layout: [block][frequency] bf16, 512-byte rows with XOR-swizzled 16-byte segments;
+// MFMA operands are read with the transpose read.
 // ================================================================================================
 constexpr int FT = 256;              // output tile (u and p)
 constexpr int FKB = 32;              // blocks per chunk
-constexpr int FROW = FT * 2 + 32;    // bytes per LDS row
+constexpr int FROW = FT * 2;         // bytes per LDS row
 constexpr int FARR = FKB * FROW;     // bytes per array
 constexpr int FBUF = 4 * FARR;       // Xh, Xl, Yh, Yl
 
-template <bool X3>
-__device__ __forceinline__ void fwd_gen(const PhaseRec *__restrict__ tab, int64_t n, int64_t chunk, int f0,
-                                        char *arr_h, char *arr_l, int gt) {
-    const int k = gt >> 3, r = gt & 7;
+// Byte offset of 16-byte segment `seg` of row `k` in an LDS tile.  The segment index is XORed with
+// g(k) = 2 (k % 4) + (k / 4) % 2, a permutation of 0..7 over any 8 consecutive rows whose halves
+// 2 (k % 4) differ within every aligned group of 4 rows.  The 64 lanes of a b128 store (8 rows x 8
+// runs) then spread evenly over all banks, and a 16-lane transpose read (4 rows x 32 bytes) hits
+// 8 distinct 16-byte bank groups.
+__device__ __forceinline__ int fswz(int k, int seg) {
+    const int g = ((k & 3) << 1) | ((k >> 2) & 1);
+    return k * FROW + ((seg ^ g) << 4);
+}
+
+// The fields of a phase record that a generating thread needs, held in registers so that the
+// record can be fetched one phase ahead of its use.
+struct GenRec {
+    double ta, tb;
+    float ca, sa, c2ah, c2al, cb, sb, c2bh, c2bl, size;
+};
+
+__device__ __forceinline__ GenRec load_rec(const PhaseRec *__restrict__ tab, int64_t n, int64_t chunk, int k) {
     const int64_t ib = chunk * FKB + k;
-    const bool valid = ib < n;
+    GenRec g;
+    if (ib < n) {
+        const PhaseRec *p = tab + ib;
+        g.ta = p->ta; g.tb = p->tb;
+        g.ca = p->ca; g.sa = p->sa; g.c2ah = p->c2ah; g.c2al = p->c2al;
+        g.cb = p->cb; g.sb = p->sb; g.c2bh = p->c2bh; g.c2bl = p->c2bl;
+        g.size = p->size;
+    } else {
+        // An absent block: every basis value is zero (the sine factor and the size vanish).
+        g.ta = g.tb = 0.0;
+        g.ca = g.sa = g.c2ah = g.c2al = g.cb = g.sb = g.c2bh = g.c2bl = g.size = 0.0f;
+    }
+    return g;
+}
+
+// 32 consecutive frequencies f0 + 32 r .. + 31 of block k of the chunk, split hi/lo and stored.
+template <bool X3>
+__device__ __forceinline__ void fwd_gen(const GenRec &R, int f0, char *arr_h, char *arr_l, int gt) {
+    const int k = gt >> 3, r = gt & 7;
     const int u0 = f0 + 32 * r;
     Cheb ca, sb;
-    float size = 0.0f;
-    if (valid) {
-        const PhaseRec R = tab[ib];
-        float c0, s0, cb0, sb0;
-        seed_phasor(u0, R.ta, c0, s0);
-        seed_phasor(u0, R.tb, cb0, sb0);
-        ca.f = c0;
-        ca.fm = c0 * R.ca + s0 * R.sa;            // cos((u0 - 1) alpha)
-        ca.ch = R.c2ah; ca.cl = R.c2al;
-        sb.f = 2.0f * sb0;                         // 2 sin(u0 beta)
-        sb.fm = 2.0f * (sb0 * R.cb - cb0 * R.sb);  // 2 sin((u0 - 1) beta)
-        sb.ch = R.c2bh; sb.cl = R.c2bl;
-        size = R.size;
-    } else {
-        ca.f = ca.fm = ca.ch = ca.cl = 0.0f;
-        sb.f = sb.fm = sb.ch = sb.cl = 0.0f;
-    }
+    float c0, s0, cb0, sb0;
+    seed_phasor(u0, R.ta, c0, s0);
+    seed_phasor(u0, R.tb, cb0, sb0);
+    ca.f = c0;
+    ca.fm = c0 * R.ca + s0 * R.sa;            // cos((u0 - 1) alpha)
+    ca.ch = R.c2ah; ca.cl = R.c2al;
+    sb.f = 2.0f * sb0;                         // 2 sin(u0 beta); an all-zero record gives 0 throughout
+    sb.fm = 2.0f * (sb0 * R.cb - cb0 * R.sb);  // 2 sin((u0 - 1) beta)
+    sb.ch = R.c2bh; sb.cl = R.c2bl;
     float v[32];
     v[0] = ca.f * sb.f;
 #pragma unroll
     for (int j = 1; j < 32; ++j) v[j] = ca.next() * sb.next();
-    if (u0 == 0) v[0] = size;
-    unsigned h[16], l[16];
+    if (u0 == 0) v[0] = R.size;
+    // Split and store one 16-byte segment (8 frequencies) at a time.
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-        if (X3) {
-            split2(v[2 * m], v[2 * m + 1], h[m], l[m]);
-        } else {
-            h[m] = pack_bf16(v[2 * m], v[2 * m + 1]);
+    for (int m = 0; m < 4; ++m) {
+        unsigned h[4], l[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (X3) split2(v[8 * m + 2 * e], v[8 * m + 2 * e + 1], h[e], l[e]);
+            else h[e] = pack_bf16(v[8 * m + 2 * e], v[8 * m + 2 * e + 1]);
         }
-    }
-    char *ph = arr_h + k * FROW + r * 64;
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-        *(u32x4 *)(ph + 16 * m) = u32x4{h[4 * m], h[4 * m + 1], h[4 * m + 2], h[4 * m + 3]};
-    if (X3) {
-        char *pl = arr_l + k * FROW + r * 64;
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-            *(u32x4 *)(pl + 16 * m) = u32x4{l[4 * m], l[4 * m + 1], l[4 * m + 2], l[4 * m + 3]};
+        *(u32x4 *)(arr_h + fswz(k, 4 * r + m)) = u32x4{h[0], h[1], h[2], h[3]};
+        if (X3) *(u32x4 *)(arr_l + fswz(k, 4 * r + m)) = u32x4{l[0], l[1], l[2], l[3]};
     }
 }
 
-// One 32 x 16 MFMA operand (rows f_base..f_base+31 of the frequency axis, blocks kbase..kbase+15)
-// from an LDS [block][frequency] array, with two transpose reads.
-__device__ __forceinline__ bf16x8 load_opT(const char *arr, int f_base, int kbase, int lane) {
-    const int q = lane >> 4, i = lane & 15;
-    const int row = kbase + 8 * (q >> 1) + (i >> 2);
-    const int col = f_base + 16 * (q & 1) + 4 * (i & 3);
+// Lane-dependent byte offsets for the transpose reads of one wave's operands.  An operand covers
+// frequencies f_base + 32 a .. + 31 (a = subtile) and blocks 16 ks .. + 15; lane (q = lane / 16,
+// i = lane % 16) reads 8 bytes at row r = 8 (q / 2) + i / 4 (+4 for the second read, +16 ks) and
+// frequency f = f_base + 32 a + 16 (q % 2) + 4 (i % 4).  Because g(r + 4) = g(r) ^ 1 and rows + 16
+// keep g, the swizzled offset is one of four bases (subtile parity x read half) plus
+// 64 (a - a % 2) + 8192 ks.
+struct OpBase {
+    int b[2][2];   // [subtile parity][read half]
+    __device__ __forceinline__ void init(int f_base, int lane) {
+        const int q = lane >> 4, i = lane & 15;
+        const int r0 = 8 * (q >> 1) + (i >> 2);
+        const int col = f_base + 16 * (q & 1) + 4 * (i & 3);
+        const int s0 = col >> 3, within = (col & 7) * 2;
+        const int g0 = ((r0 & 3) << 1) | ((r0 >> 2) & 1);
+#pragma unroll
+        for (int par = 0; par < 2; ++par)
+#pragma unroll
+            for (int rd = 0; rd < 2; ++rd)
+                b[par][rd] = (r0 + 4 * rd) * FROW + (((s0 + 4 * par) ^ (g0 ^ rd)) << 4) + within;
+    }
+};
+
+// One 32 x 16 MFMA operand from an LDS [block][frequency] array: two transpose reads.
+__device__ __forceinline__ bf16x8 load_opT(const char *arr, const OpBase &ob, int a, int ks) {
     typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
-    const lds_s16x4 *p0 = (const lds_s16x4 *)(arr + row * FROW + col * 2);
-    const lds_s16x4 *p1 = (const lds_s16x4 *)(arr + (row + 4) * FROW + col * 2);
-    const s16x4 a = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4 *)p0);
-    const s16x4 b = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4 *)p1);
+    const int off = 64 * (a & ~1) + 8192 * ks;
+    const s16x4 x = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4 *)(arr + ob.b[a & 1][0] + off));
+    const s16x4 y = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4 *)(arr + ob.b[a & 1][1] + off));
     typedef short s16x8 __attribute__((ext_vector_type(8)));
-    const s16x8 c = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+    const s16x8 c = {x[0], x[1], x[2], x[3], y[0], y[1], y[2], y[3]};
     return __builtin_bit_cast(bf16x8, c);
 }
 
+// Operands of one K step of a wave's 128 x 64 sub-tile: 4 u-subtiles and 2 p-subtiles, hi and lo.
+struct FwdOps {
+    bf16x8 ah[4], al[4], bh[2], bl[2];
+};
+
 template <bool X3>
-__device__ __forceinline__ void fwd_mma(const char *buf, int wu, int wp, int lane, f32x16 (&acc)[4][2]) {
+__device__ __forceinline__ void fwd_load(const char *buf, const OpBase &ox, const OpBase &oy, int ks, FwdOps &o) {
     const char *xh = buf, *xl = buf + FARR, *yh = buf + 2 * FARR, *yl = buf + 3 * FARR;
 #pragma unroll
-    for (int ks = 0; ks < FKB / 16; ++ks) {
-        bf16x8 ah[4], al[4], bh[2], bl[2];
+    for (int a = 0; a < 4; ++a) {
+        o.ah[a] = load_opT(xh, ox, a, ks);
+        if (X3) o.al[a] = load_opT(xl, ox, a, ks);
+    }
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            ah[a] = load_opT(xh, wu + 32 * a, 16 * ks, lane);
-            if (X3) al[a] = load_opT(xl, wu + 32 * a, 16 * ks, lane);
-        }
+    for (int b = 0; b < 2; ++b) {
+        o.bh[b] = load_opT(yh, oy, b, ks);
+        if (X3) o.bl[b] = load_opT(yl, oy, b, ks);
+    }
+}
+
+// Three passes over the 8 accumulators, so consecutive MFMAs never share an accumulator.
+template <bool X3>
+__device__ __forceinline__ void fwd_mfma(const FwdOps &o, f32x16 (&acc)[4][2]) {
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            bh[b] = load_opT(yh, wp + 32 * b, 16 * ks, lane);
-            if (X3) bl[b] = load_opT(yl, wp + 32 * b, 16 * ks, lane);
-        }
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.ah[a], o.bh[b], acc[a][b], 0, 0, 0);
+    if (X3) {
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
-                if (X3) {
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
-                }
-            }
+            for (int b = 0; b < 2; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.ah[a], o.bl[b], acc[a][b], 0, 0, 0);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.al[a], o.bh[b], acc[a][b], 0, 0, 0);
     }
+}
+
+// Both K steps of a chunk; the second step's operand reads are issued before the first step's
+// MFMAs so their LDS latency hides behind the matrix work.
+template <bool X3>
+__device__ __forceinline__ void fwd_mma(const char *buf, const OpBase &ox, const OpBase &oy, f32x16 (&acc)[4][2]) {
+    static_assert(FKB == 32 && FROW * 16 == 8192, "two K steps per chunk, 16 rows per step");
+    FwdOps o0, o1;
+    fwd_load<X3>(buf, ox, oy, 0, o0);
+    fwd_load<X3>(buf, ox, oy, 1, o1);
+    fwd_mfma<X3>(o0, acc);
+    fwd_mfma<X3>(o1, acc);
 }
 
 template <bool X3>
@@ -223,10 +301,20 @@ __global__ __launch_bounds__(512) void k_fwd_bf16(int64_t n, int Mu, int Mp, con
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+    OpBase ox, oy;
+    ox.init(wu, lane);
+    oy.init(wp, lane);
 
+    // Group 0 generates the X tile (u), group 1 the Y tile (p).
+    const PhaseRec *tab = group == 0 ? tx : ty;
+    const int f0 = group == 0 ? tu0 : tp0;
+    const int aoff = group == 0 ? 0 : 2 * FARR;
+    const int kk = gt >> 3;
+    GenRec rec;
     if (c_begin < c_end) {
-        if (group == 0) fwd_gen<X3>(tx, n, c_begin, tu0, smem, smem + FARR, gt);
-        else fwd_gen<X3>(ty, n, c_begin, tp0, smem + 2 * FARR, smem + 3 * FARR, gt);
+        rec = load_rec(tab, n, c_begin, kk);
+        fwd_gen<X3>(rec, f0, smem + aoff, smem + aoff + FARR, gt);
+        if (group == 1 && c_begin + 1 < c_end) rec = load_rec(tab, n, c_begin + 1, kk);
     }
     __syncthreads();
     for (int64_t c = c_begin; c < c_end; ++c) {
@@ -234,11 +322,15 @@ __global__ __launch_bounds__(512) void k_fwd_bf16(int64_t n, int Mu, int Mp, con
         char *cur = smem + bsel * FBUF, *nxt = smem + (bsel ^ 1) * FBUF;
         const bool more = c + 1 < c_end;
         if (group == 0) {
-            fwd_mma<X3>(cur, wu, wp, lane, acc);
-            if (more) fwd_gen<X3>(tx, n, c + 1, tu0, nxt, nxt + FARR, gt);
+            // fetch the next chunk's records before the MFMAs; generate after them
+            if (more) rec = load_rec(tab, n, c + 1, kk);
+            fwd_mma<X3>(cur, ox, oy, acc);
+            if (more) fwd_gen<X3>(rec, f0, nxt + aoff, nxt + aoff + FARR, gt);
         } else {
-            if (more) fwd_gen<X3>(ty, n, c + 1, tp0, nxt + 2 * FARR, nxt + 3 * FARR, gt);
-            fwd_mma<X3>(cur, wu, wp, lane, acc);
+            // generate first; fetch the records of the chunk after next before the MFMAs
+            if (more) fwd_gen<X3>(rec, f0, nxt + aoff, nxt + aoff + FARR, gt);
+            if (c + 2 < c_end) rec = load_rec(tab, n, c + 2, kk);
+            fwd_mma<X3>(cur, ox, oy, acc);
         }
         __syncthreads();
     }
@@ -260,32 +352,30 @@ __global__ __launch_bounds__(512) void k_fwd_bf16(int64_t n, int Mu, int Mp, con
 // Backward: G[i][nn] = sum_k A_ik B[k][nn], g_i = sum_nn E_i,nn G[i][nn].
 // 512 threads = 8 waves; wave w owns blocks i0 + 32 w .. + 31 and all 256 columns of the N tile.
 // A (sine differences along the K axis) is generated in registers directly in MFMA operand
-// layout: the lane half h = lane / 32 walks frequencies h * Kh + 8 t (t = 0, 1, ...), so each
-// lane's frequencies are contiguous and its recurrence never restarts except to reseed.
-// B is staged per chunk of 16 + 16 frequencies in LDS ([column][32] bf16, rows of 80 bytes).
-// Global B is pre-tiled: tile (n_tile, q) is a contiguous [256][32] block, hi and lo separately.
+// layout: lane half h = lane / 32 walks frequencies h * Kh + 8 t (t = 0, 1, ...), so each lane's
+// recurrence runs over contiguous frequencies.  B is staged per chunk of 32 + 32 frequencies
+// (4 K steps) in LDS by direct global->LDS copies: the global operand is pre-tiled in exactly the
+// LDS byte order, one contiguous 64 KB block (hi then lo) per (N tile, chunk), rows of 128 bytes
+// whose 16-byte segments are XOR-swizzled by (row / 2) % 8: any 16 consecutive rows then cover all
+// 16 bank groups of 16 bytes, so the b128 operand reads are conflict free.
 // ================================================================================================
-constexpr int BTN = 256;           // N tile (columns)
-constexpr int BROW = 80;           // LDS bytes per column row (32 bf16 + pad)
-constexpr int BARR = BTN * BROW;   // bytes per hi or lo array
-constexpr int BBUF = 2 * BARR;
+constexpr int BTN = 256;                 // N tile (columns)
+constexpr int BKC = 64;                  // K values per chunk (32 from each half)
+constexpr int BROW = BKC * 2;            // bytes per LDS row (128)
+constexpr int BARR = BTN * BROW;         // bytes per hi or lo array (32 KB)
+constexpr int BBUF = 2 * BARR;           // one chunk, hi + lo (64 KB)
 
-template <bool X3>
-__device__ __forceinline__ void bwd_load_b(const unsigned short *__restrict__ gh, const unsigned short *__restrict__ gl,
-                                           char *buf, int tid) {
-    // 256 rows x 32 bf16 = 16 KB per array: thread t copies 32 bytes of row t/2.
-    const int row = tid >> 1, half = tid & 1;
-    const u32x4 *sh = (const u32x4 *)(gh + row * 32 + half * 16);
-    const u32x4 v0 = sh[0], v1 = sh[1];
-    *(u32x4 *)(buf + row * BROW + half * 32) = v0;
-    *(u32x4 *)(buf + row * BROW + half * 32 + 16) = v1;
-    if (X3) {
-        const u32x4 *sl = (const u32x4 *)(gl + row * 32 + half * 16);
-        const u32x4 w0 = sl[0], w1 = sl[1];
-        *(u32x4 *)(buf + BARR + row * BROW + half * 32) = w0;
-        *(u32x4 *)(buf + BARR + row * BROW + half * 32 + 16) = w1;
-    }
+// Issue the direct copies of one 64 KB chunk tile: 8 slices of 8 KB, each wave 1 KB per slice.
+__device__ __forceinline__ void bwd_copy_b(const unsigned short *__restrict__ gtile, char *buf, int tid) {
+    const int wave = tid >> 6;
+    typedef __attribute__((address_space(3))) void lds_void;
+#pragma unroll
+    for (int i = 0; i < BBUF / 8192; ++i)
+        __builtin_amdgcn_global_load_lds((const void *)((const char *)gtile + i * 8192 + tid * 16),
+                                         (lds_void *)(buf + i * 8192 + wave * 1024), 16, 0, 0);
 }
+
+__device__ __forceinline__ void wait_copies() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 template <bool X3>
 __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
@@ -296,24 +386,43 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
     const int ntile = blockIdx.y, n0 = ntile * BTN;
     const int64_t ib = i0 + j;        // this lane's block for the A operand
     const bool valid = ib < n;
-    const int Q = ax.Kh / 16;         // chunks along K
+    const int Q = ax.Kh / 32;         // chunks along K
 
-    // A-operand recurrence state (basis along the K axis).
-    PhaseRec RA;
-    if (valid) RA = ax.ta[ib];
+    // A-operand recurrence state (basis along the K axis).  Two fp32 phasors of the current
+    // frequency, e^{i pi kcur ta} and e^{i pi kcur tb}, are seeded once in FP64 and advanced by the
+    // 32-frequency phasors of the phase record at every reseed, so the K loop makes no memory
+    // access and no FP64 reduction for its seeds (drift after 64 jumps ~1e-6).
     Cheb ca, sb;
     int kcur = h * ax.Kh;             // next frequency this lane generates
+    float pac, pas, pbc, pbs;         // phasors at kcur
+    float jac, jas, jbc, jbs;         // 32-frequency jumps
+    float sac, sas, sbc, sbs;         // one-frequency steps (for the k - 1 terms)
+    float size0 = 0.0f;
+    if (valid) {
+        const PhaseRec RA = ax.ta[ib];
+        seed_phasor(kcur, RA.ta, pac, pas);
+        seed_phasor(kcur, RA.tb, pbc, pbs);
+        jac = RA.ca32; jas = RA.sa32; jbc = RA.cb32; jbs = RA.sb32;
+        sac = RA.ca; sas = RA.sa; sbc = RA.cb; sbs = RA.sb;
+        ca.ch = RA.c2ah; ca.cl = RA.c2al; sb.ch = RA.c2bh; sb.cl = RA.c2bl;
+        size0 = RA.size;
+    } else {
+        pac = pas = pbc = pbs = jac = jas = jbc = jbs = sac = sas = sbc = sbs = 0.0f;
+        ca.ch = ca.cl = sb.ch = sb.cl = 0.0f;
+    }
     auto reseed = [&]() {
-        if (valid) {
-            float c0, s0, cb0, sb0;
-            seed_phasor(kcur, RA.ta, c0, s0);
-            seed_phasor(kcur, RA.tb, cb0, sb0);
-            ca.f = c0; ca.fm = c0 * RA.ca + s0 * RA.sa; ca.ch = RA.c2ah; ca.cl = RA.c2al;
-            sb.f = 2.0f * sb0; sb.fm = 2.0f * (sb0 * RA.cb - cb0 * RA.sb); sb.ch = RA.c2bh; sb.cl = RA.c2bl;
-        } else {
-            ca.f = ca.fm = ca.ch = ca.cl = 0.0f;
-            sb.f = sb.fm = sb.ch = sb.cl = 0.0f;
-        }
+        ca.f = pac;
+        ca.fm = pac * sac + pas * sas;                // cos((k - 1) alpha)
+        sb.f = 2.0f * pbs;                            // 2 sin(k beta)
+        sb.fm = 2.0f * (pbs * sbc - pbc * sbs);       // 2 sin((k - 1) beta)
+    };
+    auto jump = [&]() {
+        float t = pac * jac - pas * jas;
+        pas = pas * jac + pac * jas;
+        pac = t;
+        t = pbc * jbc - pbs * jbs;
+        pbs = pbs * jbc + pbc * jbs;
+        pbc = t;
     };
     reseed();
     int since = 0;
@@ -324,50 +433,88 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[b][r] = 0.0f;
 
-    const size_t tile_elems = (size_t)BTN * 32;
-    const unsigned short *gbh = ax.Bh + (size_t)ntile * Q * tile_elems;
-    const unsigned short *gbl = X3 ? ax.Bl + (size_t)ntile * Q * tile_elems : nullptr;
+    const size_t tile_elems = (size_t)BBUF / 2;      // bf16 elements per chunk tile (hi + lo)
+    const unsigned short *gb = ax.B + (size_t)ntile * Q * tile_elems;
 
-    bwd_load_b<X3>(gbh, gbl, smem, tid);
+    // A operand of the next K step (8 consecutive frequencies of this lane's block), split hi/lo.
+    bf16x8 ah, al;
+    auto gen_a = [&]() {
+        if (since == 4) { jump(); reseed(); since = 0; }
+        float v[8];
+        v[0] = ca.f * sb.f;
+#pragma unroll
+        for (int e = 1; e < 8; ++e) v[e] = ca.next() * sb.next();
+        ca.next(); sb.next();
+        if (kcur == 0) v[0] = size0;
+        kcur += 8;
+        ++since;
+        unsigned hh[4], ll[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            if (X3) split2(v[2 * m], v[2 * m + 1], hh[m], ll[m]);
+            else hh[m] = pack_bf16(v[2 * m], v[2 * m + 1]);
+        }
+        ah = __builtin_bit_cast(bf16x8, u32x4{hh[0], hh[1], hh[2], hh[3]});
+        if (X3) al = __builtin_bit_cast(bf16x8, u32x4{ll[0], ll[1], ll[2], ll[3]});
+    };
+    // B hi operands of K step s of the chunk (8 column subtiles), read ahead of the MFMAs; the lo
+    // operands are read inside the last MFMA pass (fewer live registers).  Row 32 b + j, logical
+    // segment 4 h + s, physical segment XORed with (j / 2) % 8.
+    bf16x8 bh[8];
+    const char *bcur = smem;
+    int bseg = 0;
+    auto load_b = [&](const char *cur, int s) {
+        bcur = cur;
+        bseg = ((4 * h + s) ^ ((j >> 1) & 7)) * 16;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) bh[b] = *(const bf16x8 *)(cur + (32 * b + j) * BROW + bseg);
+    };
+    // Three passes over the 8 accumulators (consecutive MFMAs never share one).
+    auto mma = [&]() {
+#pragma unroll
+        for (int b = 0; b < 8; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[b], acc[b], 0, 0, 0);
+        if (X3) {
+#pragma unroll
+            for (int b = 0; b < 8; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[b], acc[b], 0, 0, 0);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bf16x8 bl = *(const bf16x8 *)(bcur + BARR + (32 * b + j) * BROW + bseg);
+                acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[b], 0, 0, 0);
+            }
+        }
+    };
+
+    // Ping-pong between the wave groups 0-3 and 4-7 (one of each per SIMD): group 0 reads its B
+    // operands, generates A and runs its MFMAs; group 1 runs the MFMAs of a step whose A it
+    // generated before, then generates the next.  Each SIMD's matrix unit thus runs one group's
+    // MFMAs while the other group's VALU work proceeds.
+    const int group = wave >> 2;
+    if (group == 1) gen_a();
+    bwd_copy_b(gb, smem, tid);
+    wait_copies();
     __syncthreads();
     for (int q = 0; q < Q; ++q) {
         char *cur = smem + (q & 1) * BBUF, *nxt = smem + ((q & 1) ^ 1) * BBUF;
-        if (q + 1 < Q)
-            bwd_load_b<X3>(gbh + (size_t)(q + 1) * tile_elems, X3 ? gbl + (size_t)(q + 1) * tile_elems : nullptr,
-                           nxt, tid);
+        if (q + 1 < Q) bwd_copy_b(gb + (size_t)(q + 1) * tile_elems, nxt, tid);
+        if (group == 0) {
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            // 8 consecutive basis values of this lane's block.
-            if (since == 4) { reseed(); since = 0; }
-            float v[8];
-            v[0] = ca.f * sb.f;
-#pragma unroll
-            for (int e = 1; e < 8; ++e) v[e] = ca.next() * sb.next();
-            ca.next(); sb.next();
-            if (kcur == 0) v[0] = valid ? RA.size : 0.0f;
-            kcur += 8;
-            ++since;
-            unsigned hh[4], ll[4];
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                if (X3) split2(v[2 * m], v[2 * m + 1], hh[m], ll[m]);
-                else hh[m] = pack_bf16(v[2 * m], v[2 * m + 1]);
+            for (int s = 0; s < 4; ++s) {
+                load_b(cur, s);
+                gen_a();
+                mma();
             }
-            const bf16x8 ah = __builtin_bit_cast(bf16x8, u32x4{hh[0], hh[1], hh[2], hh[3]});
-            bf16x8 al;
-            if (X3) al = __builtin_bit_cast(bf16x8, u32x4{ll[0], ll[1], ll[2], ll[3]});
+        } else {
+            load_b(cur, 0);
+            mma();
 #pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                const int off = (32 * b + j) * BROW + h * 32 + s * 16;
-                const bf16x8 bh = *(const bf16x8 *)(cur + off);
-                acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[b], 0, 0, 0);
-                if (X3) {
-                    const bf16x8 bl = *(const bf16x8 *)(cur + BARR + off);
-                    acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[b], 0, 0, 0);
-                    acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[b], 0, 0, 0);
-                }
+            for (int s = 1; s < 4; ++s) {
+                load_b(cur, s);
+                gen_a();
+                mma();
             }
+            gen_a();
         }
+        wait_copies();
         __syncthreads();
     }
 
@@ -418,37 +565,40 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
 }
 
 // Backward operand preparation for the bf16 path: BT[nn][k] = a_up / (scale of the K axis),
-// split into bf16 hi and lo, zero padded to [Np][2 Kh] and tiled as
-// [n_tile][q][row][half * 16 + j] (k = half * Kh + 16 q + j).
+// split into bf16 hi and lo, zero padded, and tiled exactly in the LDS byte order of k_bwd_bf16:
+// tile (n_tile, q) = [hi | lo][256 rows][8 segments of 8 values], the 16-byte segment of logical
+// index seg stored at seg ^ ((row / 2) % 8); logical segment seg = 4 half + s holds
+// k = half * Kh + 32 q + 8 s + e (e = 0..7).
 // trans = 0: nn = u, k = p (gx operand, a_up / vt_p);  trans = 1: nn = p, k = u (gy, a_up / wt_u).
 __global__ void k_prep_bwd_bf16(const double *__restrict__ a, int Mu, int Mp, double W, double H, int trans,
-                                int Np, int Kh, unsigned short *__restrict__ Bh, unsigned short *__restrict__ Bl) {
-    const size_t total = (size_t)Np * (size_t)(2 * Kh);
+                                int Np, int Kh, unsigned short *__restrict__ B) {
+    const int Q = Kh / 32;
+    const size_t per_tile = (size_t)BBUF / 2;
+    const size_t total = (size_t)(Np / BTN) * (size_t)Q * per_tile;
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
-    // decode the tiled position
-    const int Q = Kh / 16;
-    const size_t tile = idx / (256 * 32);
-    const int within = (int)(idx % (256 * 32));
-    const int row = within / 32, col = within % 32;
+    const size_t tile = idx / per_tile;
+    const int within = (int)(idx % per_tile);
+    const int hl = within / (BARR / 2);
+    const int r = within % (BARR / 2);
+    const int row = r / BKC, pseg = (r % BKC) / 8, e = r % 8;
+    const int seg = pseg ^ ((row >> 1) & 7);
+    const int half = seg >> 2, st = seg & 3;
     const int nt = (int)(tile / Q), q = (int)(tile % Q);
-    const int nn = nt * 256 + row;
-    const int half = col / 16, jj = col % 16;
-    const int k = half * Kh + 16 * q + jj;
-    float hv = 0.0f, lv = 0.0f;
+    const int nn = nt * BTN + row;
+    const int k = half * Kh + 32 * q + 8 * st + e;
     const int Nb = trans ? Mp : Mu, Ka = trans ? Mu : Mp;
+    float out = 0.0f;
     if (nn < Nb && k < Ka) {
         const int u = trans ? k : nn, p = trans ? nn : k;
-        const double av = a[(size_t)u * Mp + p];
         double sc;
         if (trans) sc = u ? (double)u * kPi / W : 1.0;
         else sc = p ? (double)p * kPi / H : 1.0;
-        const double v = av / sc;
-        hv = (float)(__bf16)(float)v;
-        lv = (float)(__bf16)(float)(v - (double)hv);
+        const double v = a[(size_t)u * Mp + p] / sc;
+        const float hv = (float)(__bf16)(float)v;
+        out = hl == 0 ? hv : (float)(__bf16)(float)(v - (double)hv);
     }
-    Bh[idx] = __builtin_bit_cast(unsigned short, (__bf16)hv);
-    Bl[idx] = __builtin_bit_cast(unsigned short, (__bf16)lv);
+    B[idx] = __builtin_bit_cast(unsigned short, (__bf16)out);
 }
 
 }  // namespace
@@ -476,12 +626,14 @@ hipError_t launch_fwd_bf16(const FwdPlan &pl, bool x3, int64_t n, int Mu, int Mp
 }
 
 hipError_t launch_prep_bwd_bf16(const double *a, int Mu, int Mp, double W, double H, int trans, int Np, int Kh,
-                                unsigned short *Bh, unsigned short *Bl, hipStream_t s) {
-    const size_t total = (size_t)Np * (size_t)(2 * Kh);
+                                unsigned short *B, hipStream_t s) {
+    const size_t total = bwd_bf16_operand_elems(Np, Kh);
     hipLaunchKernelGGL(k_prep_bwd_bf16, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a, Mu, Mp, W, H,
-                       trans, Np, Kh, Bh, Bl);
+                       trans, Np, Kh, B);
     return hipGetLastError();
 }
+
+size_t bwd_bf16_operand_elems(int Np, int Kh) { return (size_t)(Np / BTN) * (size_t)(Kh / 32) * (size_t)(BBUF / 2); }
 
 hipError_t launch_bwd_bf16(bool x3, int64_t n, const BwdAxisBf16 &ax, hipStream_t s) {
     dim3 grid((unsigned)((n + 255) / 256), (unsigned)((ax.Nb + BTN - 1) / BTN));
