@@ -425,7 +425,6 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
         pbc = t;
     };
     reseed();
-    int since = 0;
 
     f32x16 acc[8];
 #pragma unroll
@@ -436,18 +435,16 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
     const size_t tile_elems = (size_t)BBUF / 2;      // bf16 elements per chunk tile (hi + lo)
     const unsigned short *gb = ax.B + (size_t)ntile * Q * tile_elems;
 
-    // A operand of the next K step (8 consecutive frequencies of this lane's block), split hi/lo.
-    bf16x8 ah, al;
-    auto gen_a = [&]() {
-        if (since == 4) { jump(); reseed(); since = 0; }
+    // A operand of one K step (8 consecutive frequencies of this lane's block), split hi/lo.  Branch
+    // free, so that it can be scheduled between the MFMAs of the previous step.
+    auto gen_a = [&](bf16x8 &ah, bf16x8 &al) {
         float v[8];
         v[0] = ca.f * sb.f;
 #pragma unroll
         for (int e = 1; e < 8; ++e) v[e] = ca.next() * sb.next();
         ca.next(); sb.next();
-        if (kcur == 0) v[0] = size0;
+        v[0] = kcur == 0 ? size0 : v[0];
         kcur += 8;
-        ++since;
         unsigned hh[4], ll[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
@@ -457,63 +454,52 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
         ah = __builtin_bit_cast(bf16x8, u32x4{hh[0], hh[1], hh[2], hh[3]});
         if (X3) al = __builtin_bit_cast(bf16x8, u32x4{ll[0], ll[1], ll[2], ll[3]});
     };
-    // B hi operands of K step s of the chunk (8 column subtiles), read ahead of the MFMAs; the lo
-    // operands are read inside the last MFMA pass (fewer live registers).  Row 32 b + j, logical
-    // segment 4 h + s, physical segment XORed with (j / 2) % 8.
-    bf16x8 bh[8];
-    const char *bcur = smem;
-    int bseg = 0;
-    auto load_b = [&](const char *cur, int s) {
-        bcur = cur;
-        bseg = ((4 * h + s) ^ ((j >> 1) & 7)) * 16;
+
+    // One K step: B operands (row 32 b + j, logical segment 4 h + s, physical segment XORed with
+    // (j / 2) % 8) and the three MFMA passes over the 8 accumulators, with the next step's A operand
+    // generated in between (software pipelining inside the wave).
+    auto step = [&](const char *cur, int s, const bf16x8 &ah, const bf16x8 &al, bf16x8 &nah, bf16x8 &nal) {
+        const int bseg = ((4 * h + s) ^ ((j >> 1) & 7)) * 16;
+        bf16x8 bh[8], bl[8];
 #pragma unroll
         for (int b = 0; b < 8; ++b) bh[b] = *(const bf16x8 *)(cur + (32 * b + j) * BROW + bseg);
-    };
-    // Three passes over the 8 accumulators (consecutive MFMAs never share one).
-    auto mma = [&]() {
+        if (X3) {
+#pragma unroll
+            for (int b = 0; b < 8; ++b) bl[b] = *(const bf16x8 *)(cur + BARR + (32 * b + j) * BROW + bseg);
+        }
+        gen_a(nah, nal);
 #pragma unroll
         for (int b = 0; b < 8; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[b], acc[b], 0, 0, 0);
         if (X3) {
 #pragma unroll
             for (int b = 0; b < 8; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[b], acc[b], 0, 0, 0);
 #pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                const bf16x8 bl = *(const bf16x8 *)(bcur + BARR + (32 * b + j) * BROW + bseg);
-                acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[b], 0, 0, 0);
-            }
+            for (int b = 0; b < 8; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[b], acc[b], 0, 0, 0);
+        }
+        // Schedule: the B reads first, then each MFMA followed by a few VALU ops of the generator.
+        __builtin_amdgcn_sched_group_barrier(0x100, X3 ? 16 : 8, 0);
+#pragma unroll
+        for (int i = 0; i < (X3 ? 24 : 8); ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, X3 ? 3 : 8, 0);
         }
     };
 
-    // Ping-pong between the wave groups 0-3 and 4-7 (one of each per SIMD): group 0 reads its B
-    // operands, generates A and runs its MFMAs; group 1 runs the MFMAs of a step whose A it
-    // generated before, then generates the next.  Each SIMD's matrix unit thus runs one group's
-    // MFMAs while the other group's VALU work proceeds.
-    const int group = wave >> 2;
-    if (group == 1) gen_a();
+    bf16x8 ah0, al0, ah1, al1;
+    gen_a(ah0, al0);                  // A of the first step
     bwd_copy_b(gb, smem, tid);
     wait_copies();
     __syncthreads();
     for (int q = 0; q < Q; ++q) {
         char *cur = smem + (q & 1) * BBUF, *nxt = smem + ((q & 1) ^ 1) * BBUF;
         if (q + 1 < Q) bwd_copy_b(gb + (size_t)(q + 1) * tile_elems, nxt, tid);
-        if (group == 0) {
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                load_b(cur, s);
-                gen_a();
-                mma();
-            }
-        } else {
-            load_b(cur, 0);
-            mma();
-#pragma unroll
-            for (int s = 1; s < 4; ++s) {
-                load_b(cur, s);
-                gen_a();
-                mma();
-            }
-            gen_a();
-        }
+        step(cur, 0, ah0, al0, ah1, al1);
+        step(cur, 1, ah1, al1, ah0, al0);
+        step(cur, 2, ah0, al0, ah1, al1);
+        // The next step is the first of the next chunk: 32 frequencies later, reseed first.
+        jump();
+        reseed();
+        step(cur, 3, ah1, al1, ah0, al0);
         wait_copies();
         __syncthreads();
     }
