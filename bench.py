@@ -39,6 +39,30 @@ def rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b))) / (nb if nb > 0 else 1.0)
 
 
+def kernel_source_hash():
+    """sha256 of the HIP sources; traffic figures are reported only for the kernels they were taken on."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2307_12041_amd", "csrc")
+    hs = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            hs.update(open(os.path.join(d, f), "rb").read())
+    return hs.hexdigest()
+
+
+def measured_traffic(workload, precision, stage):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary (profiles/traffic_<precision>_<workload>.json), or None if absent or taken on other sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{precision}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    st = rec.get("stages", {}).get(stage)
+    return None if st is None else st.get("hbm_bytes_per_launch")
+
+
 def timed_steps(pp, torch, t, wl, prec, steps, warmup, ws):
     kw = dict(W=wl.W, H=wl.H, precision=prec, workspace=ws)
     for _ in range(warmup):
@@ -73,6 +97,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=12000, help="blocks in the oracle's timed sample")
+    ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
+                    help="run one device copy of this many GiB first (reference kernel for HBM byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -94,6 +120,14 @@ def main():
     need = max(pp.workspace_size(wl.W, wl.H, wl.n, wl.Mu, wl.Mp, precision=p) for p in (args.precision, "fp64"))
     ws = torch.empty(need, dtype=torch.uint8, device=dev)
     log(f"[bench] workspace {need / 2**20:.1f} MiB")
+    if args.copy_calibration_gib > 0:
+        nb = int(args.copy_calibration_gib * 2**30)
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {nb} bytes read, {nb} bytes written")
+        del src, dst
 
     dt, stages, (E, a, gx, gy) = timed_steps(pp, torch, t, wl, args.precision, args.steps, args.warmup, ws)
     value = pairs * args.steps / dt
@@ -111,7 +145,7 @@ def main():
     if args.precision == "fp64":
         kernel_name = {"fwd": "k_fwd_f64", "bwd": "k_bwd_f64"}[dom]
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None,
+                "frac": round(achieved / peak, 4), "traffic": measured_traffic(wl.name, args.precision, dom),
                 "kernel": kernel_name, "avg_launch_ms": round(avg_ms, 3), "launches_per_step": stages[dom][1] // args.steps,
                 "algorithmic_flops_per_launch": alg_flops,
                 "executed_mfma_tflops": round(achieved * MFMA_MULT[args.precision], 2),
