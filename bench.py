@@ -63,17 +63,26 @@ def measured_traffic(workload, precision, stage):
     return None if st is None else st.get("hbm_bytes_per_launch")
 
 
-def timed_steps(pp, torch, t, wl, prec, steps, warmup, ws):
+def timed_steps(pp, torch, t, wl, prec, steps, warmup, ws, positions=None):
+    """Warm up, then time `steps` evaluations (energy + gradient).  With `positions` (a list of
+    (x, y) device tensors) step k evaluates positions[k % len]."""
     kw = dict(W=wl.W, H=wl.H, precision=prec, workspace=ws)
-    for _ in range(warmup):
-        E, a = pp.energy(*t, Mu=wl.Mu, Mp=wl.Mp, **kw)
-        pp.field(*t, a, **kw)
+
+    def args(k):
+        if positions is None:
+            return t
+        x, y = positions[k % len(positions)]
+        return [x, y, t[2], t[3]]
+
+    for k in range(warmup):
+        E, a = pp.energy(*args(k), Mu=wl.Mu, Mp=wl.Mp, **kw)
+        pp.field(*args(k), a, **kw)
     torch.cuda.synchronize()
     pp.timing_enable(True)
     t0 = time.perf_counter()
-    for _ in range(steps):
-        E, a = pp.energy(*t, Mu=wl.Mu, Mp=wl.Mp, **kw)
-        gx, gy = pp.field(*t, a, **kw)
+    for k in range(steps):
+        E, a = pp.energy(*args(k), Mu=wl.Mu, Mp=wl.Mp, **kw)
+        gx, gy = pp.field(*args(k), a, **kw)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stages = {}
@@ -97,6 +106,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=12000, help="blocks in the oracle's timed sample")
+    ap.add_argument("--jitter", action="store_true",
+                    help="each timed step evaluates new positions: the base positions plus N(0,1) jitter, prepared "
+                         "on the device before the timed region (the repeated-evaluation workload)")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="run one device copy of this many GiB first (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -129,7 +141,15 @@ def main():
         log(f"[bench] calibration copy: {nb} bytes read, {nb} bytes written")
         del src, dst
 
-    dt, stages, (E, a, gx, gy) = timed_steps(pp, torch, t, wl, args.precision, args.steps, args.warmup, ws)
+    positions = None
+    if args.jitter:
+        from workloads import jitter
+        positions = []
+        for k in range(args.steps):
+            j = jitter(wl, k)
+            positions.append((torch.as_tensor(j.x, device=dev), torch.as_tensor(j.y, device=dev)))
+        log(f"[bench] {args.steps} jittered position sets resident on the device")
+    dt, stages, (E, a, gx, gy) = timed_steps(pp, torch, t, wl, args.precision, args.steps, args.warmup, ws, positions)
     value = pairs * args.steps / dt
     log(f"[bench] {args.precision}: {dt / args.steps * 1e3:.2f} ms/step, {value:.4e} pairs/s; stages "
         + ", ".join(f"{k}={v[0] / v[1]:.2f}ms x{v[1] // args.steps}" for k, v in stages.items()))
@@ -155,8 +175,9 @@ def main():
            "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "bf16" if args.precision.startswith("bf16") else "f64",
            "data": "synthetic",
-           "config": {"workload": wl.name, "n_blocks": wl.n, "Mu": wl.Mu, "Mp": wl.Mp, "W": wl.W, "H": wl.H,
-                      "precision": args.precision, "basis": "recompute", "pairs_per_step": pairs},
+           "config": {"workload": wl.name + ("_jittered" if args.jitter else ""), "n_blocks": wl.n, "Mu": wl.Mu,
+                      "Mp": wl.Mp, "W": wl.W, "H": wl.H, "precision": args.precision, "basis": "recompute",
+                      "pairs_per_step": pairs},
            "stages_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stages.items()},
            "roofline": roofline}
 

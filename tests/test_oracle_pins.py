@@ -386,3 +386,27 @@ def test_golden_oracle_cases_unchanged():
         assert np.allclose(a[:4, :4], c["a_corner"], rtol=1e-13, atol=1e-15 * np.abs(a).max())
         assert np.allclose(gx, c["gx"], rtol=1e-12, atol=1e-13 * np.abs(gx).max())
         assert np.allclose(gy, c["gy"], rtol=1e-12, atol=1e-13 * np.abs(gy).max())
+
+
+# ---------------------------------------------------------------------------------------------
+# The rank-one central-difference helper used by the large-workload GPU tests agrees with the
+# oracle's gradient (and with brute-force central differences of the oracle's energy).
+# ---------------------------------------------------------------------------------------------
+def test_rank1_central_difference_helper():
+    from tests.fd_rank1 import central_difference
+    wl = make_random(400, 300.0, 200.0, 48, 40, seed=41, wmax=8.0, hmax=2.0)
+    W, H = wl.W, wl.H
+    x, y, w, h = wl.arrays()
+    E, a, _ = oracle.energy(W, H, x, y, w, h, wl.Mu, wl.Mp)
+    gx, gy = oracle.grad(W, H, x, y, w, h, a)
+    idx = np.array([0, 7, 123, 399])
+    fx, fy = central_difference(W, H, x, y, w, h, a, idx, 1e-3)
+    sc = max(np.abs(gx).max(), np.abs(gy).max())
+    assert np.abs(fx - gx[idx]).max() < 1e-6 * sc
+    assert np.abs(fy - gy[idx]).max() < 1e-6 * sc
+    # brute force for one block
+    i = 7
+    xp = x.copy(); xp[i] += 1e-3
+    xm = x.copy(); xm[i] -= 1e-3
+    bf = (_E(W, H, xp, y, w, h, wl.Mu, wl.Mp) - _E(W, H, xm, y, w, h, wl.Mu, wl.Mp)) / 2e-3
+    assert abs(bf - fx[1]) < 1e-7 * sc
