@@ -26,8 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "block·freq² pairs/s for energy+forces, BF16-split vs FP64 plain, at rel err"
-PEAK_TFLOPS = {"bf16x3": 2500.0, "bf16": 2500.0, "fp64": 78.6}   # MI355X dense matrix peaks
-MFMA_MULT = {"bf16x3": 3, "bf16": 1, "fp64": 1}                   # executed MFMA products per algorithmic one
+PEAK_TFLOPS = {"bf16x3": 2500.0, "bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}   # MI355X dense matrix peaks
+MFMA_MULT = {"bf16x3": 3, "bf16": 1, "fp32": 1, "fp64": 1}   # executed MFMA products per algorithmic one
 
 
 def log(*a):
@@ -100,9 +100,10 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", type=int, default=4, help="workload index in workloads.CONFIGS")
-    ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "bf16", "fp64"])
+    ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "bf16", "fp32", "fp64"])
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--fp32-steps", type=int, default=2, help="steps of the FP32 path on the same workload (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=12000, help="blocks in the oracle's timed sample")
@@ -129,7 +130,8 @@ def main():
     pairs = wl.pairs
     log(f"[bench] workload {wl.name}: n={wl.n} Mu={wl.Mu} Mp={wl.Mp} pairs/step={pairs:.3e}")
     t = [torch.as_tensor(v, device=dev) for v in wl.arrays()]
-    need = max(pp.workspace_size(wl.W, wl.H, wl.n, wl.Mu, wl.Mp, precision=p) for p in (args.precision, "fp64"))
+    need = max(pp.workspace_size(wl.W, wl.H, wl.n, wl.Mu, wl.Mp, precision=p)
+               for p in (args.precision, "fp32", "fp64"))
     ws = torch.empty(need, dtype=torch.uint8, device=dev)
     log(f"[bench] workspace {need / 2**20:.1f} MiB")
     if args.copy_calibration_gib > 0:
@@ -162,8 +164,9 @@ def main():
     peak = PEAK_TFLOPS[args.precision]
     kernel_name = {"fwd": "k_fwd_bf16<x3> (coefficient contraction)",
                    "bwd": "k_bwd_bf16<x3> (gradient contraction, gx and gy launches)"}[dom]
-    if args.precision == "fp64":
-        kernel_name = {"fwd": "k_fwd_f64", "bwd": "k_bwd_f64"}[dom]
+    if args.precision in ("fp64", "fp32"):
+        T = "double" if args.precision == "fp64" else "float"
+        kernel_name = {"fwd": f"k_fwd_mat<{T}>", "bwd": f"k_bwd_mat<{T}>"}[dom]
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": measured_traffic(wl.name, args.precision, dom),
                 "kernel": kernel_name, "avg_launch_ms": round(avg_ms, 3), "launches_per_step": stages[dom][1] // args.steps,
@@ -173,7 +176,8 @@ def main():
 
     out = {"metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "bf16" if args.precision.startswith("bf16") else "f64",
+           "scaling": "weak", "vs_baseline": None,
+           "dtype": {"bf16x3": "bf16", "bf16": "bf16", "fp32": "f32", "fp64": "f64"}[args.precision],
            "data": "synthetic",
            "config": {"workload": wl.name + ("_jittered" if args.jitter else ""), "n_blocks": wl.n, "Mu": wl.Mu,
                       "Mp": wl.Mp, "W": wl.W, "H": wl.H, "precision": args.precision, "basis": "recompute",
@@ -190,6 +194,21 @@ def main():
                              "steps": args.fp64_steps,
                              "stages_ms_per_step": {k: round(v[0] / args.fp64_steps, 3) for k, v in st64.items()}}
         out["speedup_vs_fp64_plain"] = value / v64
+
+    if args.fp32_steps > 0 and args.precision != "fp32":
+        dt32, st32, r32 = timed_steps(pp, torch, t, wl, "fp32", args.fp32_steps, 1, ws)
+        v32 = pairs * args.fp32_steps / dt32
+        log(f"[bench] fp32: {dt32 / args.fp32_steps * 1e3:.1f} ms/step, {v32:.4e} pairs/s")
+        out["fp32_plain"] = {"value": v32, "unit": "pairs/s", "ms_per_step": dt32 / args.fp32_steps * 1e3,
+                             "steps": args.fp32_steps,
+                             "stages_ms_per_step": {k: round(v[0] / args.fp32_steps, 3) for k, v in st32.items()}}
+        if ref is not None:
+            E32, a32, gx32, gy32 = (v.cpu().numpy() for v in r32)
+            E64, a64, gx64, gy64 = (v.cpu().numpy() for v in ref)
+            out["fp32_plain"]["rel_err_vs_fp64_gpu"] = {
+                "E": abs(float(E32) - float(E64)) / abs(float(E64)), "a": rel(a32, a64),
+                "g": rel(np.concatenate([gx32, gy32]), np.concatenate([gx64, gy64]))}
+        out["speedup_vs_fp32"] = value / v32
 
     if not args.no_accuracy:
         import oracle

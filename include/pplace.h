@@ -63,16 +63,16 @@ typedef enum pp_status {
  * are always FP64. */
 typedef enum pp_precision {
     PP_FP64 = 0,    /* FP64 tables, FP64 MFMA */
-    PP_FP32 = 1,    /* FP32 tables, FP32 MFMA */
+    PP_FP32 = 1,    /* FP32 tables (FP64 values rounded once), FP32 MFMA, FP32 accumulation */
     PP_BF16 = 2,    /* BF16 tables, BF16 MFMA, FP32 accumulation */
     PP_BF16X3 = 3,  /* BF16 hi/lo split of FP32 tables: hi*hi + hi*lo + lo*hi, FP32 accumulation */
-    PP_FP8 = 4,     /* reserved */
-    PP_FP8X3 = 5    /* reserved */
+    PP_FP8 = 4,     /* reserved: PP_ERR_UNSUPPORTED */
+    PP_FP8X3 = 5    /* reserved: PP_ERR_UNSUPPORTED */
 } pp_precision;
 
 typedef enum pp_basis_mode {
     PP_BASIS_RECOMPUTE = 0,  /* basis tiles regenerated on chip, never stored */
-    PP_BASIS_STORE = 1       /* reserved */
+    PP_BASIS_STORE = 1       /* reserved: PP_ERR_UNSUPPORTED */
 } pp_basis_mode;
 
 /* Problem description (Sec. II-A: region and blocks; truncation of the series, Sec. III-B/C). */

@@ -14,7 +14,9 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-bool supported_precision(int prec) { return prec == PP_FP64 || prec == PP_BF16 || prec == PP_BF16X3; }
+bool supported_precision(int prec) {
+    return prec == PP_FP64 || prec == PP_FP32 || prec == PP_BF16 || prec == PP_BF16X3;
+}
 bool is_bf16(int prec) { return prec == PP_BF16 || prec == PP_BF16X3; }
 
 int validate_problem(const pp_problem *P) {
@@ -60,7 +62,7 @@ FwdPlan fwd_plan(const pp_problem &P) {
     if (pl.chunks_per_split < 1) pl.chunks_per_split = 1;
     pl.splits = (int)((pl.chunks + pl.chunks_per_split - 1) / pl.chunks_per_split);
     if (pl.splits < 1) pl.splits = 1;
-    pl.part_elem = is_bf16(P.precision) ? 4 : 8;
+    pl.part_elem = P.precision == PP_FP64 ? 8 : 4;
     return pl;
 }
 
@@ -74,7 +76,7 @@ BwdPlan bwd_plan(const pp_problem &P) {
     pl.tiles_b = (P.n + pl.tb - 1) / pl.tb;
     pl.tiles_nx = (P.Mu + pl.tn - 1) / pl.tn;
     pl.tiles_ny = (P.Mp + pl.tn - 1) / pl.tn;
-    pl.bmat_elem = 8;
+    pl.bmat_elem = P.precision == PP_FP32 ? 4 : 8;
     return pl;
 }
 
@@ -142,6 +144,9 @@ int run_forward(const pp_problem &P, const double *x, const double *y, const dou
         { TimedLaunch t("tables", s); err = launch_phase_tables(P.n, x, y, w, h, P.W, P.H, tx, ty, s); }
         if (err != hipSuccess) return PP_ERR_DEVICE;
         { TimedLaunch t("fwd", s); err = launch_fwd_bf16(f, P.precision == PP_BF16X3, P.n, P.Mu, P.Mp, tx, ty, (float *)part, s); }
+    } else if (P.precision == PP_FP32) {
+        TimedLaunch t("fwd", s);
+        err = launch_fwd_f32(f, P.n, P.Mu, P.Mp, P.W, P.H, x, y, w, h, (float *)part, s);
     } else {
         TimedLaunch t("fwd", s);
         err = launch_fwd_f64(f, P.n, P.Mu, P.Mp, P.W, P.H, x, y, w, h, (double *)part, s);
@@ -229,14 +234,21 @@ int pp_field(const pp_problem *P, const double *x, const double *y, const double
         { TimedLaunch t("final", s); if (launch_bwd_final(gpx, b.tiles_nx, gpy, b.tiles_ny, P->n, dE, gx, gy, s) != hipSuccess) return PP_ERR_DEVICE; }
         return PP_OK;
     }
-    double *bx = (double *)(base + L.bx), *by = (double *)(base + L.by);
-    { TimedLaunch t("prep", s); if (launch_prep_bwd_f64(a, P->Mu, P->Mp, P->W, P->H, bx, by, s) != hipSuccess) return PP_ERR_DEVICE; }
+    void *bx = base + L.bx, *by = base + L.by;
+    const bool f32 = P->precision == PP_FP32;
+    {
+        TimedLaunch t("prep", s);
+        const hipError_t e = f32 ? launch_prep_bwd_f32(a, P->Mu, P->Mp, P->W, P->H, (float *)bx, (float *)by, s)
+                                 : launch_prep_bwd_f64(a, P->Mu, P->Mp, P->W, P->H, (double *)bx, (double *)by, s);
+        if (e != hipSuccess) return PP_ERR_DEVICE;
+    }
     // gx: K = p (basis of y), epilogue over u (cosine differences of x), operand BxT[p][u].
     BwdAxis axx{y, h, P->H, P->Mp, x, w, P->W, P->Mu, bx, gpx};
     // gy: K = u (basis of x), epilogue over p (cosine differences of y), operand By[u][p].
     BwdAxis axy{x, w, P->W, P->Mu, y, h, P->H, P->Mp, by, gpy};
-    { TimedLaunch t("bwd", s); if (launch_bwd_f64(b, P->n, axx, s) != hipSuccess) return PP_ERR_DEVICE; }
-    { TimedLaunch t("bwd", s); if (launch_bwd_f64(b, P->n, axy, s) != hipSuccess) return PP_ERR_DEVICE; }
+    auto bwd = f32 ? launch_bwd_f32 : launch_bwd_f64;
+    { TimedLaunch t("bwd", s); if (bwd(b, P->n, axx, s) != hipSuccess) return PP_ERR_DEVICE; }
+    { TimedLaunch t("bwd", s); if (bwd(b, P->n, axy, s) != hipSuccess) return PP_ERR_DEVICE; }
     { TimedLaunch t("final", s); if (launch_bwd_final(gpx, b.tiles_nx, gpy, b.tiles_ny, P->n, dE, gx, gy, s) != hipSuccess) return PP_ERR_DEVICE; }
     return PP_OK;
 }

@@ -88,6 +88,12 @@ hipError_t launch_fwd_f64(const FwdPlan &pl, int64_t n, int Mu, int Mp, double W
                           const double *x, const double *y, const double *w, const double *h,
                           double *part, hipStream_t s);
 hipError_t launch_bwd_f64(const BwdPlan &pl, int64_t n, const BwdAxis &ax, hipStream_t s);
+// FP32 operands on v_mfma_f32_16x16x4f32 (basis generated in FP64, rounded when stored; FP32
+// accumulation inside a tile, FP64 across tiles).
+hipError_t launch_fwd_f32(const FwdPlan &pl, int64_t n, int Mu, int Mp, double W, double H,
+                          const double *x, const double *y, const double *w, const double *h,
+                          float *part, hipStream_t s);
+hipError_t launch_bwd_f32(const BwdPlan &pl, int64_t n, const BwdAxis &ax, hipStream_t s);
 hipError_t launch_phase_tables(int64_t n, const double *x, const double *y, const double *w, const double *h,
                                double W, double H, PhaseRec *tx, PhaseRec *ty, hipStream_t s);
 hipError_t launch_fwd_bf16(const FwdPlan &pl, bool x3, int64_t n, int Mu, int Mp, const PhaseRec *tx,
@@ -106,6 +112,8 @@ int reduce_scale_blocks(int Mu, int Mp);
 // Backward operand preparation from FP64 a:  BxT[p][u] = a_up / vt_p,  By[u][p] = a_up / wt_u.
 hipError_t launch_prep_bwd_f64(const double *a, int Mu, int Mp, double W, double H, double *BxT,
                                double *By, hipStream_t s);
+hipError_t launch_prep_bwd_f32(const double *a, int Mu, int Mp, double W, double H, float *BxT,
+                               float *By, hipStream_t s);
 // gx[i] = dE * sum_t gpart_x[t][i], gy likewise.
 hipError_t launch_bwd_final(const double *gpx, int tx, const double *gpy, int ty, int64_t n,
                             const double *dE, double *gx, double *gy, hipStream_t s);

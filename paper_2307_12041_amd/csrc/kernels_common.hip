@@ -66,16 +66,17 @@ __global__ __launch_bounds__(kRedThreads) void k_energy_final(const double *__re
 }
 
 // BxT[p][u] = a_up / vt_p  (operand of gx, K = p),  By[u][p] = a_up / wt_u  (operand of gy, K = u).
-__global__ void k_prep_bwd_f64(const double *__restrict__ a, int Mu, int Mp, double W, double H,
-                               double *__restrict__ BxT, double *__restrict__ By) {
+template <typename T>
+__global__ void k_prep_bwd_mat(const double *__restrict__ a, int Mu, int Mp, double W, double H,
+                               T *__restrict__ BxT, T *__restrict__ By) {
     const size_t MM = (size_t)Mu * (size_t)Mp;
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= MM) return;
     const int u = (int)(idx / (size_t)Mp), p = (int)(idx % (size_t)Mp);
     const double wt = u ? (double)u * kPi / W : 1.0, vt = p ? (double)p * kPi / H : 1.0;
     const double av = a[idx];
-    BxT[(size_t)p * Mu + u] = av / vt;
-    By[idx] = av / wt;
+    BxT[(size_t)p * Mu + u] = (T)(av / vt);
+    By[idx] = (T)(av / wt);
 }
 
 __global__ void k_bwd_final(const double *__restrict__ gpx, int tx, const double *__restrict__ gpy, int ty,
@@ -115,8 +116,16 @@ hipError_t launch_energy_final(const double *epart, int nblocks, double *E, hipS
 hipError_t launch_prep_bwd_f64(const double *a, int Mu, int Mp, double W, double H, double *BxT, double *By,
                                hipStream_t s) {
     const size_t MM = (size_t)Mu * (size_t)Mp;
-    hipLaunchKernelGGL(k_prep_bwd_f64, dim3((unsigned)((MM + 255) / 256)), dim3(256), 0, s, a, Mu, Mp, W, H, BxT,
-                       By);
+    hipLaunchKernelGGL(k_prep_bwd_mat<double>, dim3((unsigned)((MM + 255) / 256)), dim3(256), 0, s, a, Mu, Mp, W,
+                       H, BxT, By);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_bwd_f32(const double *a, int Mu, int Mp, double W, double H, float *BxT, float *By,
+                               hipStream_t s) {
+    const size_t MM = (size_t)Mu * (size_t)Mp;
+    hipLaunchKernelGGL(k_prep_bwd_mat<float>, dim3((unsigned)((MM + 255) / 256)), dim3(256), 0, s, a, Mu, Mp, W,
+                       H, BxT, By);
     return hipGetLastError();
 }
 

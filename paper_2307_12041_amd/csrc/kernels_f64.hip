@@ -1,12 +1,15 @@
-// kernels_f64.hip -- FP64 path: basis tiles generated on chip, contractions on v_mfma_f64_16x16x4.
+// kernels_f64.hip -- FP64 and FP32 paths: basis tiles generated on chip in FP64 (rounded to the
+// operand type when stored), contractions on v_mfma_f64_16x16x4 (FP64) or v_mfma_f32_16x16x4 (FP32).
 //
 // Forward (coefficients, Sec. III-A closed forms): At[u][p] = sum_i S_iu T_ip over a K range of
 // blocks, one FP64 partial per split.  Backward (field of eq. ksi integrated over each block):
 // G[i][n] = sum_k A_ik B[k][n] with the sine-difference basis A generated along the K frequency
 // axis, then the row dot  g_i = sum_n E_in G[i][n]  with the cosine-difference basis E.
 //
-// Lane layouts of v_mfma_f64_16x16x4 (16x16 output, K = 4, one double per lane for A and B):
-//   A[i][k] in lane i + 16k,  B[k][j] in lane j + 16k,  D[i][j] in lane j + 16 (i % 4), element i / 4.
+// Lane layouts (16x16 output, K = 4, one value per lane for A and B): A[i][k] in lane i + 16k and
+// B[k][j] in lane j + 16k for both; the output differs:
+//   v_mfma_f64_16x16x4: D[i][j] in lane j + 16 (i % 4), element i / 4;
+//   v_mfma_f32_16x16x4: D[i][j] in lane j + 16 (i / 4), element i % 4.
 //
 // Basis generation: for a block edge e and frequency k, the phase k*pi*e/L is carried in half
 // turns.  A run of consecutive frequencies starts from an FP64 seed, reduced to [-1, 1] half
@@ -17,7 +20,22 @@
 namespace pp {
 namespace {
 
-typedef double v4d __attribute__((ext_vector_type(4)));
+// Operand type T: the MFMA and its output row for (lane, element).
+template <typename T> struct Mat;
+template <> struct Mat<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mfma(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+template <> struct Mat<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mfma(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
 
 __device__ __forceinline__ double reduce_half_turns(double t) { return t - 2.0 * rint(0.5 * t); }
 
@@ -42,38 +60,37 @@ struct EdgeRot {
     }
 };
 
-// R consecutive sine-difference values (size at frequency 0) of one block, written at dst[k*stride].
-template <int R>
-__device__ __forceinline__ void gen_sin_run(double c, double sz, double L, int k0, bool valid, double *dst,
-                                            int stride) {
+// R consecutive sine-difference values (size at frequency 0) of one block, written at dst[k*stride]
+// (generated in FP64, rounded to T when stored).
+template <int R, typename T>
+__device__ __forceinline__ void gen_sin_run(double c, double sz, double L, int k0, bool valid, T *dst, int stride) {
     if (!valid) {
 #pragma unroll
-        for (int k = 0; k < R; ++k) dst[k * stride] = 0.0;
+        for (int k = 0; k < R; ++k) dst[k * stride] = (T)0;
         return;
     }
     EdgeRot r;
     r.init(c, sz, L, k0);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-        dst[k * stride] = (k0 + k == 0) ? sz : (r.sp - r.sm);
+        dst[k * stride] = (T)((k0 + k == 0) ? sz : (r.sp - r.sm));
         r.step();
     }
 }
 
 // R consecutive cosine-difference values (0 at frequency 0) of one block.
-template <int R>
-__device__ __forceinline__ void gen_cos_run(double c, double sz, double L, int k0, bool valid, double *dst,
-                                            int stride) {
+template <int R, typename T>
+__device__ __forceinline__ void gen_cos_run(double c, double sz, double L, int k0, bool valid, T *dst, int stride) {
     if (!valid) {
 #pragma unroll
-        for (int k = 0; k < R; ++k) dst[k * stride] = 0.0;
+        for (int k = 0; k < R; ++k) dst[k * stride] = (T)0;
         return;
     }
     EdgeRot r;
     r.init(c, sz, L, k0);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-        dst[k * stride] = r.cp - r.cm;
+        dst[k * stride] = (T)(r.cp - r.cm);
         r.step();
     }
 }
@@ -82,15 +99,16 @@ __device__ __forceinline__ void gen_cos_run(double c, double sz, double L, int k
 // Forward: grid (tiles_u * tiles_p, splits), 256 threads as 2 x 2 waves over a TU x TP tile.
 // LDS holds the K chunk of the two basis tiles, k-major: Xs[kb][u], Ys[kb][p].
 // ------------------------------------------------------------------------------------------------
-template <int TU, int TP, int KB>
-__global__ __launch_bounds__(256) void k_fwd_f64(int64_t n, int Mu, int Mp, double W, double H,
+template <typename T, int TU, int TP, int KB>
+__global__ __launch_bounds__(256) void k_fwd_mat(int64_t n, int Mu, int Mp, double W, double H,
                                                  const double *__restrict__ x, const double *__restrict__ y,
                                                  const double *__restrict__ w, const double *__restrict__ h,
-                                                 double *__restrict__ part, int tiles_p, int64_t chunks,
+                                                 T *__restrict__ part, int tiles_p, int64_t chunks,
                                                  int64_t chunks_per_split) {
+    typedef typename Mat<T>::v4 v4;
     constexpr int LU = TU + 1, LP = TP + 1;
-    __shared__ double Xs[KB * LU];
-    __shared__ double Ys[KB * LP];
+    __shared__ T Xs[KB * LU];
+    __shared__ T Ys[KB * LP];
     constexpr int WU = TU / 2, WP = TP / 2, SU = WU / 16, SP = WP / 16;
     constexpr int RX = TU * KB / 128, RY = TP * KB / 128;
     static_assert(RX * 128 == TU * KB && RY * 128 == TP * KB, "tile/thread mismatch");
@@ -103,11 +121,11 @@ __global__ __launch_bounds__(256) void k_fwd_f64(int64_t n, int Mu, int Mp, doub
 
     const int side = tid >> 7, j = tid & 127, kb = j % KB, run = j / KB;
 
-    v4d acc[SU][SP];
+    v4 acc[SU][SP];
 #pragma unroll
     for (int a = 0; a < SU; ++a)
 #pragma unroll
-        for (int b = 0; b < SP; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < SP; ++b) acc[a][b] = v4{(T)0, (T)0, (T)0, (T)0};
 
     for (int64_t c = c_begin; c < c_end; ++c) {
         const int64_t ib = c * KB + kb;
@@ -124,7 +142,7 @@ __global__ __launch_bounds__(256) void k_fwd_f64(int64_t n, int Mu, int Mp, doub
 #pragma unroll
         for (int ks = 0; ks < KB / 4; ++ks) {
             const int kr = ks * 4 + (lane >> 4);
-            double av[SU], bv[SP];
+            T av[SU], bv[SP];
 #pragma unroll
             for (int a = 0; a < SU; ++a) av[a] = Xs[kr * LU + wu0 + a * 16 + (lane & 15)];
 #pragma unroll
@@ -132,19 +150,18 @@ __global__ __launch_bounds__(256) void k_fwd_f64(int64_t n, int Mu, int Mp, doub
 #pragma unroll
             for (int a = 0; a < SU; ++a)
 #pragma unroll
-                for (int b = 0; b < SP; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+                for (int b = 0; b < SP; ++b) acc[a][b] = Mat<T>::mfma(av[a], bv[b], acc[a][b]);
         }
     }
 
-    double *out = part + (size_t)blockIdx.y * (size_t)Mu * (size_t)Mp;
+    T *out = part + (size_t)blockIdx.y * (size_t)Mu * (size_t)Mp;
 #pragma unroll
     for (int a = 0; a < SU; ++a)
 #pragma unroll
         for (int b = 0; b < SP; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int u = tu0 + wu0 + a * 16 + 4 * r + (lane >> 4);
+                const int u = tu0 + wu0 + a * 16 + Mat<T>::row(lane, r);
                 const int p = tp0 + wp0 + b * 16 + (lane & 15);
                 if (u < Mu && p < Mp) out[(size_t)u * Mp + p] = acc[a][b][r];
             }
@@ -156,15 +173,16 @@ __global__ __launch_bounds__(256) void k_fwd_f64(int64_t n, int Mu, int Mp, doub
 // LDS: As[k][i] (generated sine differences), Bs[k][n] (prepared operand); after the K loop the
 // same space holds the cosine differences of one half of the N tile, Es[n][i].
 // ------------------------------------------------------------------------------------------------
-template <int TB, int TN, int KK>
-__global__ __launch_bounds__(256) void k_bwd_f64(int64_t n, BwdAxis ax) {
+template <typename T, int TB, int TN, int KK>
+__global__ __launch_bounds__(256) void k_bwd_mat(int64_t n, BwdAxis ax) {
+    typedef typename Mat<T>::v4 v4;
     constexpr int LB = TB + 1, LN = TN + 1;
     constexpr int HALF = TN / 2;
     static_assert(TB == 128 && TN == 128 && KK == 32, "LDS reuse below assumes this tile");
     constexpr int SMEM = (KK * LB + KK * LN) > (HALF * LB) ? (KK * LB + KK * LN) : (HALF * LB);
-    __shared__ double smem[SMEM];
+    __shared__ T smem[SMEM];
     __shared__ double red[2 * TB];
-    double *As = smem, *Bs = smem + KK * LB, *Es = smem;
+    T *As = smem, *Bs = smem + KK * LB, *Es = smem;
     constexpr int WI = TB / 2, WJ = TN / 2, SI = WI / 16, SJ = WJ / 16;
     constexpr int RA = KK * TB / 256;   // sine run per thread per chunk
     constexpr int RE = HALF * TB / 256; // cosine run per thread per half
@@ -178,13 +196,13 @@ __global__ __launch_bounds__(256) void k_bwd_f64(int64_t n, BwdAxis ax) {
     const bool valid = ib < n;
     const double ca = valid ? ax.ca[ib] : 0.0, sa = valid ? ax.sa[ib] : 0.0;
     const double cb = valid ? ax.cb[ib] : 0.0, sb = valid ? ax.sb[ib] : 0.0;
-    const double *__restrict__ B = (const double *)ax.B;
+    const T *__restrict__ B = (const T *)ax.B;
 
-    v4d acc[SI][SJ];
+    v4 acc[SI][SJ];
 #pragma unroll
     for (int a = 0; a < SI; ++a)
 #pragma unroll
-        for (int b = 0; b < SJ; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < SJ; ++b) acc[a][b] = v4{(T)0, (T)0, (T)0, (T)0};
 
     for (int k0 = 0; k0 < ax.Ka; k0 += KK) {
         __syncthreads();
@@ -192,13 +210,13 @@ __global__ __launch_bounds__(256) void k_bwd_f64(int64_t n, BwdAxis ax) {
         for (int idx = tid; idx < KK * TN; idx += 256) {
             const int k = idx / TN, jj = idx % TN;
             const bool in = (k0 + k < ax.Ka) && (n0 + jj < ax.Nb);
-            Bs[k * LN + jj] = in ? B[(size_t)(k0 + k) * ax.Nb + n0 + jj] : 0.0;
+            Bs[k * LN + jj] = in ? B[(size_t)(k0 + k) * ax.Nb + n0 + jj] : (T)0;
         }
         __syncthreads();
 #pragma unroll
         for (int ks = 0; ks < KK / 4; ++ks) {
             const int kr = ks * 4 + (lane >> 4);
-            double av[SI], bv[SJ];
+            T av[SI], bv[SJ];
 #pragma unroll
             for (int a = 0; a < SI; ++a) av[a] = As[kr * LB + wi0 + a * 16 + (lane & 15)];
 #pragma unroll
@@ -206,8 +224,7 @@ __global__ __launch_bounds__(256) void k_bwd_f64(int64_t n, BwdAxis ax) {
 #pragma unroll
             for (int a = 0; a < SI; ++a)
 #pragma unroll
-                for (int b = 0; b < SJ; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+                for (int b = 0; b < SJ; ++b) acc[a][b] = Mat<T>::mfma(av[a], bv[b], acc[a][b]);
         }
     }
 
@@ -228,9 +245,9 @@ __global__ __launch_bounds__(256) void k_bwd_f64(int64_t n, BwdAxis ax) {
                 for (int b = 0; b < SJ; ++b)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int il = wi0 + a * 16 + 4 * r + (lane >> 4);
+                        const int il = wi0 + a * 16 + Mat<T>::row(lane, r);
                         const int jl = b * 16 + (lane & 15);
-                        rs[a][r] += acc[a][b][r] * Es[jl * LB + il];
+                        rs[a][r] += (double)acc[a][b][r] * (double)Es[jl * LB + il];
                     }
         }
     }
@@ -250,35 +267,52 @@ __global__ __launch_bounds__(256) void k_bwd_f64(int64_t n, BwdAxis ax) {
 #pragma unroll
         for (int a = 0; a < SI; ++a)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) red[wc * TB + wi0 + a * 16 + 4 * r + (lane >> 4)] = rs[a][r];
+            for (int r = 0; r < 4; ++r) red[wc * TB + wi0 + a * 16 + Mat<T>::row(lane, r)] = rs[a][r];
     }
     __syncthreads();
     if (tid < TB && ib0 + tid < n)
         ax.gpart[(size_t)blockIdx.y * (size_t)n + (size_t)(ib0 + tid)] = red[tid] + red[TB + tid];
 }
 
-}  // namespace
-
-hipError_t launch_fwd_f64(const FwdPlan &pl, int64_t n, int Mu, int Mp, double W, double H, const double *x,
-                          const double *y, const double *w, const double *h, double *part, hipStream_t s) {
+template <typename T>
+hipError_t launch_fwd_mat(const FwdPlan &pl, int64_t n, int Mu, int Mp, double W, double H, const double *x,
+                          const double *y, const double *w, const double *h, T *part, hipStream_t s) {
     dim3 grid(pl.tiles_u * pl.tiles_p, pl.splits);
     if (pl.tu == 128 && pl.tp == 128 && pl.kb == 16)
-        hipLaunchKernelGGL((k_fwd_f64<128, 128, 16>), grid, dim3(256), 0, s, n, Mu, Mp, W, H, x, y, w, h, part,
+        hipLaunchKernelGGL((k_fwd_mat<T, 128, 128, 16>), grid, dim3(256), 0, s, n, Mu, Mp, W, H, x, y, w, h, part,
                            pl.tiles_p, pl.chunks, pl.chunks_per_split);
     else if (pl.tu == 64 && pl.tp == 64 && pl.kb == 32)
-        hipLaunchKernelGGL((k_fwd_f64<64, 64, 32>), grid, dim3(256), 0, s, n, Mu, Mp, W, H, x, y, w, h, part,
+        hipLaunchKernelGGL((k_fwd_mat<T, 64, 64, 32>), grid, dim3(256), 0, s, n, Mu, Mp, W, H, x, y, w, h, part,
                            pl.tiles_p, pl.chunks, pl.chunks_per_split);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-hipError_t launch_bwd_f64(const BwdPlan &pl, int64_t n, const BwdAxis &ax, hipStream_t s) {
+template <typename T>
+hipError_t launch_bwd_mat(const BwdPlan &pl, int64_t n, const BwdAxis &ax, hipStream_t s) {
     if (!(pl.tb == 128 && pl.tn == 128 && pl.kk == 32)) return hipErrorInvalidValue;
     const int tiles_n = (ax.Nb + pl.tn - 1) / pl.tn;
     dim3 grid((unsigned)pl.tiles_b, tiles_n);
-    hipLaunchKernelGGL((k_bwd_f64<128, 128, 32>), grid, dim3(256), 0, s, n, ax);
+    hipLaunchKernelGGL((k_bwd_mat<T, 128, 128, 32>), grid, dim3(256), 0, s, n, ax);
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fwd_f64(const FwdPlan &pl, int64_t n, int Mu, int Mp, double W, double H, const double *x,
+                          const double *y, const double *w, const double *h, double *part, hipStream_t s) {
+    return launch_fwd_mat<double>(pl, n, Mu, Mp, W, H, x, y, w, h, part, s);
+}
+hipError_t launch_fwd_f32(const FwdPlan &pl, int64_t n, int Mu, int Mp, double W, double H, const double *x,
+                          const double *y, const double *w, const double *h, float *part, hipStream_t s) {
+    return launch_fwd_mat<float>(pl, n, Mu, Mp, W, H, x, y, w, h, part, s);
+}
+hipError_t launch_bwd_f64(const BwdPlan &pl, int64_t n, const BwdAxis &ax, hipStream_t s) {
+    return launch_bwd_mat<double>(pl, n, ax, s);
+}
+hipError_t launch_bwd_f32(const BwdPlan &pl, int64_t n, const BwdAxis &ax, hipStream_t s) {
+    return launch_bwd_mat<float>(pl, n, ax, s);
 }
 
 }  // namespace pp

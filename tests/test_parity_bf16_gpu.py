@@ -77,11 +77,6 @@ def test_bf16x3_parity_overhanging_and_macros():
     check(wl, "bf16x3")
 
 
-def test_bf16x3_parity_cells200k_macros50_M512():
-    wl = make_config(2)
-    check(wl, "bf16x3", grad_sample=3000)
-
-
 def test_bf16x3_zero_blocks_and_determinism():
     say("[edge] n=0, determinism")
     x = torch.empty(0, dtype=torch.float64, device=DEV)
