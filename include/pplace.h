@@ -84,8 +84,9 @@ typedef struct pp_problem {
     int32_t basis_mode;  /* pp_basis_mode */
 } pp_problem;
 
-/* Bytes of device workspace that pp_coeffs, pp_energy and pp_field need for problem P (one size
- * serves all three).  Host only: makes no HIP call. */
+/* Bytes of device workspace that pp_coeffs, pp_energy, pp_field, pp_point_field and
+ * pp_block_potential need for problem P (one size serves all of them).  Host only: makes no HIP
+ * call. */
 int pp_workspace_size(const pp_problem *P, size_t *bytes);
 
 /* Series coefficients a_up (Sec. III-A closed forms; a_00 = 0).
@@ -107,6 +108,29 @@ int pp_field(const pp_problem *P, const double *x, const double *y, const double
              const double *a, const double *dE, double *gx, double *gy, void *ws, size_t ws_bytes,
              void *stream);
 
+/* Point values of the potential and the field at npts = P->n points (Sec. III-A, eq. psi and
+ * eq. ksi; the force of a point charge, Sec. II-B): at (px[k], py[k]),
+ *   psi[k] = sum_up a_up cos(w_u px) cos(v_p py),
+ *   xix[k] = sum_up a_up w_u sin(w_u px) cos(v_p py)  (= -d psi / dx),
+ *   xiy[k] = sum_up a_up v_p cos(w_u px) sin(v_p py)  (= -d psi / dy).
+ * Evaluation points may be the block centres or any other points (a grid for a picture of psi).
+ * px, py: in [npts] FP64 device arrays.  a: in [Mu * Mp] FP64 coefficients (pp_coeffs).
+ * psi, xix, xiy: out [npts] FP64, each may be NULL (not computed).
+ * P->precision: PP_FP64 or PP_FP32 (operand type of the contractions; FP64 sums per point), others
+ * give PP_ERR_UNSUPPORTED.  ws: at least pp_workspace_size(P) bytes, P->n = npts.
+ * Errors as for pp_field. */
+int pp_point_field(const pp_problem *P, const double *px, const double *py, const double *a, double *psi,
+                   double *xix, double *xiy, void *ws, size_t ws_bytes, void *stream);
+
+/* Potential energy of each block against the whole density (Sec. II-B, N_i with the exact block
+ * density, so that E = 1/2 sum_i N_i): N_i = integral of psi over block i
+ *   = sum_up a_up Xbar_iu Ybar_ip,  Xbar_iu the sine-difference integral of block i (w_i at u = 0).
+ * x, y, w, h: in [n] FP64 blocks.  a: in [Mu * Mp] FP64 coefficients of the same problem.
+ * N: out [n] FP64.  P->precision: PP_FP64 or PP_FP32, others give PP_ERR_UNSUPPORTED.
+ * Errors as for pp_field. */
+int pp_block_potential(const pp_problem *P, const double *x, const double *y, const double *w, const double *h,
+                       const double *a, double *N, void *ws, size_t ws_bytes, void *stream);
+
 /* Static description of a status code. */
 const char *pp_strerror(int status);
 
@@ -117,8 +141,9 @@ const char *pp_strerror(int status);
  * pp_timing_query(name, &ms, &count) waits for the recorded events of one stage and returns their
  * summed duration in milliseconds and the number of launches.  Stage names: "tables" (per-block
  * phase records), "fwd" (coefficient contraction), "reduce" (split-K sum, scale, energy
- * partials), "energy" (final energy sum), "prep" (backward operands), "bwd" (the two gradient
- * contractions, one record each), "final" (gradient partial sums).  Unknown names give count 0.
+ * partials), "energy" (final energy sum), "prep" (row-form operands), "bwd" (the two gradient
+ * contractions, one record each), "final" (per-block partial sums), "point" (pp_point_field
+ * contractions), "potential" (pp_block_potential contraction).  Unknown names give count 0.
  * Returns PP_OK, PP_ERR_ARG for NULL arguments, PP_ERR_DEVICE if an event query fails.  Recording
  * is process wide and guarded by a lock; it is meant for benchmarks, not for production calls. */
 int pp_timing_enable(int on);

@@ -18,7 +18,8 @@ import os
 import torch
 
 __all__ = ["PRECISIONS", "BASIS_MODES", "PPError", "library_path", "load", "workspace_size", "coeffs",
-           "energy", "field", "PPEnergy", "energy_autograd", "timing_enable", "timing_query"]
+           "energy", "field", "point_field", "block_potential", "PPEnergy", "energy_autograd", "timing_enable",
+           "timing_query"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libpplace.so")
@@ -27,8 +28,8 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "fp8": 4, "fp8x3": 5
 BASIS_MODES = {"recompute": 0, "store": 1}
 
 PP_OK = 0
-EXPORTS = ("pp_workspace_size", "pp_coeffs", "pp_energy", "pp_field", "pp_strerror", "pp_timing_enable",
-           "pp_timing_query")
+EXPORTS = ("pp_workspace_size", "pp_coeffs", "pp_energy", "pp_field", "pp_point_field", "pp_block_potential",
+           "pp_strerror", "pp_timing_enable", "pp_timing_query")
 
 
 class PPError(RuntimeError):
@@ -64,13 +65,15 @@ def load():
     lib.pp_coeffs.argtypes = [P, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.pp_energy.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.pp_field.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.pp_point_field.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.pp_block_potential.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.pp_strerror.argtypes = [ctypes.c_int]
     lib.pp_strerror.restype = ctypes.c_char_p
     lib.pp_timing_enable.argtypes = [ctypes.c_int]
     lib.pp_timing_enable.restype = ctypes.c_int
     lib.pp_timing_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
     lib.pp_timing_query.restype = ctypes.c_int
-    for f in ("pp_workspace_size", "pp_coeffs", "pp_energy", "pp_field"):
+    for f in ("pp_workspace_size", "pp_coeffs", "pp_energy", "pp_field", "pp_point_field", "pp_block_potential"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -182,6 +185,50 @@ def field(x, y, w, h, a, *, W, H, precision="fp64", basis="recompute", dE=None, 
     if st != PP_OK:
         raise PPError(st, "pp_field")
     return gx, gy
+
+
+def _coeff_arg(a, dev):
+    if not isinstance(a, torch.Tensor) or a.dtype != torch.float64 or a.dim() != 2 or not a.is_contiguous() \
+            or a.device != dev:
+        raise ValueError("a must be a contiguous [Mu, Mp] float64 tensor on the points' device")
+    return a.shape
+
+
+def point_field(px, py, a, *, W, H, precision="fp64", want=("psi", "xix", "xiy"), workspace=None):
+    """Point values (psi, xix, xiy) of the potential and the field xi = -grad psi at (px[k], py[k]);
+    an output not named in `want` is None."""
+    for t in (px, py):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.dim() != 1 or not t.is_contiguous():
+            raise TypeError("px, py must be contiguous 1-D float64 tensors")
+    dev, n = px.device, px.shape[0]
+    if py.device != dev or py.shape[0] != n or dev.type != "cuda":
+        raise ValueError("px, py must be of equal length on one GPU (HIP) device")
+    Mu, Mp = _coeff_arg(a, dev)
+    P = _problem(W, H, n, Mu, Mp, precision, "recompute")
+    outs = {k: (torch.empty(n, dtype=torch.float64, device=dev) if k in want else None)
+            for k in ("psi", "xix", "xiy")}
+    ws, nb = _workspace(P, dev, workspace)
+    with torch.cuda.device(dev):
+        st = load().pp_point_field(ctypes.byref(P), _vp(px), _vp(py), _vp(a), _vp(outs["psi"]), _vp(outs["xix"]),
+                                   _vp(outs["xiy"]), _vp(ws), nb, _stream(dev))
+    if st != PP_OK:
+        raise PPError(st, "pp_point_field")
+    return outs["psi"], outs["xix"], outs["xiy"]
+
+
+def block_potential(x, y, w, h, a, *, W, H, precision="fp64", workspace=None):
+    """Per-block potential energies N_i = integral of psi over block i (E = 1/2 sum_i N_i)."""
+    dev, n = _blocks(x, y, w, h)
+    Mu, Mp = _coeff_arg(a, dev)
+    P = _problem(W, H, n, Mu, Mp, precision, "recompute")
+    N = torch.empty(n, dtype=torch.float64, device=dev)
+    ws, nb = _workspace(P, dev, workspace)
+    with torch.cuda.device(dev):
+        st = load().pp_block_potential(ctypes.byref(P), _vp(x), _vp(y), _vp(w), _vp(h), _vp(a), _vp(N), _vp(ws),
+                                       nb, _stream(dev))
+    if st != PP_OK:
+        raise PPError(st, "pp_block_potential")
+    return N
 
 
 def timing_enable(on: bool) -> None:

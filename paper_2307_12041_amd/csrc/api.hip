@@ -89,7 +89,7 @@ int bf16_kh(int Ka) { return (Ka + 63) / 64 * 32; }
 struct Layout {
     size_t tx, ty;                       // bf16 path: per-block phase records
     size_t part, epart;                  // forward region
-    size_t bx, by, gpx, gpy;             // backward region
+    size_t bx, by, gpx, gpy, gpz;        // backward region (gpz: FP64 / FP32 point field only)
     size_t fwd_bytes, bwd_bytes, total;
 };
 
@@ -119,6 +119,9 @@ Layout layout(const pp_problem &P) {
     }
     L.gpx = off; off = align_up(off + (size_t)b.tiles_nx * (size_t)P.n * sizeof(double));
     L.gpy = off; off = align_up(off + (size_t)b.tiles_ny * (size_t)P.n * sizeof(double));
+    if (!is_bf16(P.precision)) {
+        L.gpz = off; off = align_up(off + (size_t)b.tiles_nx * (size_t)P.n * sizeof(double));
+    }
     L.bwd_bytes = off;
     L.total = L.fwd_bytes > L.bwd_bytes ? L.fwd_bytes : L.bwd_bytes;
     return L;
@@ -161,6 +164,20 @@ int run_forward(const pp_problem &P, const double *x, const double *y, const dou
     }
     return PP_OK;
 }
+
+// FP64 / FP32 row-form contractions (FP32 operands for PP_FP32, FP64 otherwise).
+hipError_t prep_rowform(const pp_problem &P, RowForm f, const double *a, void *bx, void *by, hipStream_t s) {
+    TimedLaunch t("prep", s);
+    if (P.precision == PP_FP32)
+        return launch_prep_rowform_f32(f, a, P.Mu, P.Mp, P.W, P.H, (float *)bx, (float *)by, s);
+    return launch_prep_rowform_f64(f, a, P.Mu, P.Mp, P.W, P.H, (double *)bx, (double *)by, s);
+}
+
+hipError_t rowform(const pp_problem &P, RowForm f, const BwdPlan &b, const BwdAxis &ax, hipStream_t s) {
+    return P.precision == PP_FP32 ? launch_rowform_f32(f, b, P.n, ax, s) : launch_rowform_f64(f, b, P.n, ax, s);
+}
+
+bool rowform_precision(int prec) { return prec == PP_FP64 || prec == PP_FP32; }
 
 }  // namespace
 }  // namespace pp
@@ -235,21 +252,81 @@ int pp_field(const pp_problem *P, const double *x, const double *y, const double
         return PP_OK;
     }
     void *bx = base + L.bx, *by = base + L.by;
-    const bool f32 = P->precision == PP_FP32;
-    {
-        TimedLaunch t("prep", s);
-        const hipError_t e = f32 ? launch_prep_bwd_f32(a, P->Mu, P->Mp, P->W, P->H, (float *)bx, (float *)by, s)
-                                 : launch_prep_bwd_f64(a, P->Mu, P->Mp, P->W, P->H, (double *)bx, (double *)by, s);
-        if (e != hipSuccess) return PP_ERR_DEVICE;
-    }
+    if (prep_rowform(*P, ROW_FIELD, a, bx, by, s) != hipSuccess) return PP_ERR_DEVICE;
     // gx: K = p (basis of y), epilogue over u (cosine differences of x), operand BxT[p][u].
-    BwdAxis axx{y, h, P->H, P->Mp, x, w, P->W, P->Mu, bx, gpx};
+    BwdAxis axx{y, h, P->H, P->Mp, x, w, P->W, P->Mu, bx, gpx, nullptr};
     // gy: K = u (basis of x), epilogue over p (cosine differences of y), operand By[u][p].
-    BwdAxis axy{x, w, P->W, P->Mu, y, h, P->H, P->Mp, by, gpy};
-    auto bwd = f32 ? launch_bwd_f32 : launch_bwd_f64;
-    { TimedLaunch t("bwd", s); if (bwd(b, P->n, axx, s) != hipSuccess) return PP_ERR_DEVICE; }
-    { TimedLaunch t("bwd", s); if (bwd(b, P->n, axy, s) != hipSuccess) return PP_ERR_DEVICE; }
+    BwdAxis axy{x, w, P->W, P->Mu, y, h, P->H, P->Mp, by, gpy, nullptr};
+    { TimedLaunch t("bwd", s); if (rowform(*P, ROW_FIELD, b, axx, s) != hipSuccess) return PP_ERR_DEVICE; }
+    { TimedLaunch t("bwd", s); if (rowform(*P, ROW_FIELD, b, axy, s) != hipSuccess) return PP_ERR_DEVICE; }
     { TimedLaunch t("final", s); if (launch_bwd_final(gpx, b.tiles_nx, gpy, b.tiles_ny, P->n, dE, gx, gy, s) != hipSuccess) return PP_ERR_DEVICE; }
+    return PP_OK;
+}
+
+int pp_point_field(const pp_problem *P, const double *px, const double *py, const double *a, double *psi,
+                   double *xix, double *xiy, void *ws, size_t ws_bytes, void *stream) {
+    int st = validate_problem(P);
+    if (st != PP_OK) return st;
+    if (!rowform_precision(P->precision)) return PP_ERR_UNSUPPORTED;
+    if (P->n > 0 && (!px || !py || !aligned8(px) || !aligned8(py))) return PP_ERR_ARG;
+    if (!a || !aligned8(a)) return PP_ERR_ARG;
+    if ((psi && !aligned8(psi)) || (xix && !aligned8(xix)) || (xiy && !aligned8(xiy))) return PP_ERR_ARG;
+    const Layout L = layout(*P);
+    if ((st = check_ws(L, ws, ws_bytes)) != PP_OK) return st;
+    if (P->n == 0 || (!psi && !xix && !xiy)) return PP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const BwdPlan b = bwd_plan(*P);
+    char *base = (char *)ws;
+    double *gp1 = (double *)(base + L.gpx), *gp2 = (double *)(base + L.gpz), *gpy = (double *)(base + L.gpy);
+    void *bx = base + L.bx, *by = base + L.by;
+    if (prep_rowform(*P, ROW_POINT_DUAL, a, bx, xiy ? by : nullptr, s) != hipSuccess) return PP_ERR_DEVICE;
+    // psi and xi_x share Z_iu = sum_p a_up cos(v_p y_i) (K = p, operand a^T); epilogues over u with
+    // cos(w_u x_i) and w_u sin(w_u x_i).
+    if (psi || xix) {
+        TimedLaunch t("point", s);
+        const RowForm f = psi ? ROW_POINT_DUAL : ROW_POINT_WSIN;
+        BwdAxis ax{py, nullptr, P->H, P->Mp, px, nullptr, P->W, P->Mu, bx, psi ? gp1 : gp2, psi ? gp2 : nullptr};
+        if (rowform(*P, f, b, ax, s) != hipSuccess) return PP_ERR_DEVICE;
+    }
+    // xi_y: K = u with cos(w_u x_i), operand a[u][p], epilogue over p with v_p sin(v_p y_i).
+    if (xiy) {
+        TimedLaunch t("point", s);
+        BwdAxis ax{px, nullptr, P->W, P->Mu, py, nullptr, P->H, P->Mp, by, gpy, nullptr};
+        if (rowform(*P, ROW_POINT_WSIN, b, ax, s) != hipSuccess) return PP_ERR_DEVICE;
+    }
+    TimedLaunch t("final", s);
+    if (launch_bwd_final(gp1, b.tiles_nx, gpy, b.tiles_ny, P->n, nullptr, psi, xiy, s) != hipSuccess)
+        return PP_ERR_DEVICE;
+    if (xix && launch_bwd_final(gp2, b.tiles_nx, gp2, 0, P->n, nullptr, xix, nullptr, s) != hipSuccess)
+        return PP_ERR_DEVICE;
+    return PP_OK;
+}
+
+int pp_block_potential(const pp_problem *P, const double *x, const double *y, const double *w, const double *h,
+                       const double *a, double *N, void *ws, size_t ws_bytes, void *stream) {
+    int st = validate_problem(P);
+    if (st != PP_OK) return st;
+    if (!rowform_precision(P->precision)) return PP_ERR_UNSUPPORTED;
+    if ((st = validate_blocks(P, x, y, w, h)) != PP_OK) return st;
+    if (!a || !aligned8(a)) return PP_ERR_ARG;
+    if (P->n > 0 && (!N || !aligned8(N))) return PP_ERR_ARG;
+    const Layout L = layout(*P);
+    if ((st = check_ws(L, ws, ws_bytes)) != PP_OK) return st;
+    if (P->n == 0) return PP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const BwdPlan b = bwd_plan(*P);
+    char *base = (char *)ws;
+    double *gp = (double *)(base + L.gpx);
+    void *bx = base + L.bx;
+    if (prep_rowform(*P, ROW_POTENTIAL, a, bx, nullptr, s) != hipSuccess) return PP_ERR_DEVICE;
+    // N_i = sum_u S_iu sum_p T_ip a_up / (vt_p wt_u): K = p, epilogue over u, both sine differences.
+    {
+        TimedLaunch t("potential", s);
+        BwdAxis ax{y, h, P->H, P->Mp, x, w, P->W, P->Mu, bx, gp, nullptr};
+        if (rowform(*P, ROW_POTENTIAL, b, ax, s) != hipSuccess) return PP_ERR_DEVICE;
+    }
+    TimedLaunch t("final", s);
+    if (launch_bwd_final(gp, b.tiles_nx, gp, 0, P->n, nullptr, N, nullptr, s) != hipSuccess) return PP_ERR_DEVICE;
     return PP_OK;
 }
 

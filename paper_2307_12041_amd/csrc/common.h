@@ -46,7 +46,16 @@ struct BwdAxis {
     double Lb;               // epilogue region length
     int Nb;                  // epilogue frequency count (Mu for gx, Mp for gy)
     const void *B;           // prepared operand [Ka][Nb] (layout depends on precision)
-    double *gpart;           // out: [tiles_n][n] partial gradients
+    double *gpart;           // out: [tiles_n][n] partial row sums (first epilogue)
+    double *gpart2;          // out: [tiles_n][n] partial row sums of the second epilogue, if any
+};
+
+// Which row-form contraction (kernels_f64.hip): K-side basis / epilogue basis.
+enum RowForm {
+    ROW_FIELD = 0,       // sine differences / cosine differences: the energy gradient (eq. ksi over a block)
+    ROW_POTENTIAL = 1,   // sine differences / sine differences: block potentials (integral of eq. psi)
+    ROW_POINT_DUAL = 2,  // cos / cos and w sin: point psi and xi along the epilogue axis
+    ROW_POINT_WSIN = 3   // cos / w sin: point xi along the epilogue axis alone
 };
 
 // Per-block phase record of one axis, built once per call (80 bytes): for centre c, size sz and
@@ -87,13 +96,13 @@ class TimedLaunch {
 hipError_t launch_fwd_f64(const FwdPlan &pl, int64_t n, int Mu, int Mp, double W, double H,
                           const double *x, const double *y, const double *w, const double *h,
                           double *part, hipStream_t s);
-hipError_t launch_bwd_f64(const BwdPlan &pl, int64_t n, const BwdAxis &ax, hipStream_t s);
+hipError_t launch_rowform_f64(RowForm f, const BwdPlan &pl, int64_t n, const BwdAxis &ax, hipStream_t s);
 // FP32 operands on v_mfma_f32_16x16x4f32 (basis generated in FP64, rounded when stored; FP32
 // accumulation inside a tile, FP64 across tiles).
 hipError_t launch_fwd_f32(const FwdPlan &pl, int64_t n, int Mu, int Mp, double W, double H,
                           const double *x, const double *y, const double *w, const double *h,
                           float *part, hipStream_t s);
-hipError_t launch_bwd_f32(const BwdPlan &pl, int64_t n, const BwdAxis &ax, hipStream_t s);
+hipError_t launch_rowform_f32(RowForm f, const BwdPlan &pl, int64_t n, const BwdAxis &ax, hipStream_t s);
 hipError_t launch_phase_tables(int64_t n, const double *x, const double *y, const double *w, const double *h,
                                double W, double H, PhaseRec *tx, PhaseRec *ty, hipStream_t s);
 hipError_t launch_fwd_bf16(const FwdPlan &pl, bool x3, int64_t n, int Mu, int Mp, const PhaseRec *tx,
@@ -109,12 +118,16 @@ hipError_t launch_reduce_scale(const void *part, bool part_f32, int splits, int 
 hipError_t launch_energy_final(const double *epart, int nblocks, double *E, hipStream_t s);
 int reduce_scale_blocks(int Mu, int Mp);
 
-// Backward operand preparation from FP64 a:  BxT[p][u] = a_up / vt_p,  By[u][p] = a_up / wt_u.
-hipError_t launch_prep_bwd_f64(const double *a, int Mu, int Mp, double W, double H, double *BxT,
-                               double *By, hipStream_t s);
-hipError_t launch_prep_bwd_f32(const double *a, int Mu, int Mp, double W, double H, float *BxT,
-                               float *By, hipStream_t s);
-// gx[i] = dE * sum_t gpart_x[t][i], gy likewise.
+// Row-form operand preparation from FP64 a (wt_u = w_u for u >= 1 and 1 at u = 0, vt_p likewise):
+//   ROW_FIELD:      BxT[p][u] = a_up / vt_p,          By[u][p] = a_up / wt_u;
+//   ROW_POTENTIAL:  BxT[p][u] = a_up / (vt_p wt_u),   By unused (may be NULL);
+//   ROW_POINT_*:    BxT[p][u] = a_up,                 By[u][p] = a_up.
+// A NULL output is skipped.
+hipError_t launch_prep_rowform_f64(RowForm f, const double *a, int Mu, int Mp, double W, double H, double *BxT,
+                                   double *By, hipStream_t s);
+hipError_t launch_prep_rowform_f32(RowForm f, const double *a, int Mu, int Mp, double W, double H, float *BxT,
+                                   float *By, hipStream_t s);
+// gx[i] = dE * sum_t gpart_x[t][i], gy likewise (dE NULL: 1; a NULL output is skipped).
 hipError_t launch_bwd_final(const double *gpx, int tx, const double *gpy, int ty, int64_t n,
                             const double *dE, double *gx, double *gy, hipStream_t s);
 

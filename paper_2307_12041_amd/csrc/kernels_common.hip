@@ -65,9 +65,10 @@ __global__ __launch_bounds__(kRedThreads) void k_energy_final(const double *__re
     if (threadIdx.x == 0) *E = 0.5 * s;
 }
 
-// BxT[p][u] = a_up / vt_p  (operand of gx, K = p),  By[u][p] = a_up / wt_u  (operand of gy, K = u).
+// Operands of the row-form contractions: BxT[p][u] (K = p, epilogue over u) and By[u][p] (K = u,
+// epilogue over p), a times the frequency factors of the chosen form.
 template <typename T>
-__global__ void k_prep_bwd_mat(const double *__restrict__ a, int Mu, int Mp, double W, double H,
+__global__ void k_prep_rowform(int form, const double *__restrict__ a, int Mu, int Mp, double W, double H,
                                T *__restrict__ BxT, T *__restrict__ By) {
     const size_t MM = (size_t)Mu * (size_t)Mp;
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -75,8 +76,15 @@ __global__ void k_prep_bwd_mat(const double *__restrict__ a, int Mu, int Mp, dou
     const int u = (int)(idx / (size_t)Mp), p = (int)(idx % (size_t)Mp);
     const double wt = u ? (double)u * kPi / W : 1.0, vt = p ? (double)p * kPi / H : 1.0;
     const double av = a[idx];
-    BxT[(size_t)p * Mu + u] = (T)(av / vt);
-    By[idx] = (T)(av / wt);
+    double bx = av, by = av;
+    if (form == ROW_FIELD) {
+        bx = av / vt;
+        by = av / wt;
+    } else if (form == ROW_POTENTIAL) {
+        bx = av / (vt * wt);
+    }
+    if (BxT) BxT[(size_t)p * Mu + u] = (T)bx;
+    if (By) By[idx] = (T)by;
 }
 
 __global__ void k_bwd_final(const double *__restrict__ gpx, int tx, const double *__restrict__ gpy, int ty,
@@ -85,11 +93,16 @@ __global__ void k_bwd_final(const double *__restrict__ gpx, int tx, const double
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double d = dE ? *dE : 1.0;
-    double sx = 0.0, sy = 0.0;
-    for (int t = 0; t < tx; ++t) sx += gpx[(size_t)t * n + i];
-    for (int t = 0; t < ty; ++t) sy += gpy[(size_t)t * n + i];
-    gx[i] = d * sx;
-    gy[i] = d * sy;
+    if (gx) {
+        double sx = 0.0;
+        for (int t = 0; t < tx; ++t) sx += gpx[(size_t)t * n + i];
+        gx[i] = d * sx;
+    }
+    if (gy) {
+        double sy = 0.0;
+        for (int t = 0; t < ty; ++t) sy += gpy[(size_t)t * n + i];
+        gy[i] = d * sy;
+    }
 }
 
 }  // namespace
@@ -113,19 +126,19 @@ hipError_t launch_energy_final(const double *epart, int nblocks, double *E, hipS
     return hipGetLastError();
 }
 
-hipError_t launch_prep_bwd_f64(const double *a, int Mu, int Mp, double W, double H, double *BxT, double *By,
-                               hipStream_t s) {
+hipError_t launch_prep_rowform_f64(RowForm f, const double *a, int Mu, int Mp, double W, double H, double *BxT,
+                                   double *By, hipStream_t s) {
     const size_t MM = (size_t)Mu * (size_t)Mp;
-    hipLaunchKernelGGL(k_prep_bwd_mat<double>, dim3((unsigned)((MM + 255) / 256)), dim3(256), 0, s, a, Mu, Mp, W,
-                       H, BxT, By);
+    hipLaunchKernelGGL(k_prep_rowform<double>, dim3((unsigned)((MM + 255) / 256)), dim3(256), 0, s, (int)f, a, Mu,
+                       Mp, W, H, BxT, By);
     return hipGetLastError();
 }
 
-hipError_t launch_prep_bwd_f32(const double *a, int Mu, int Mp, double W, double H, float *BxT, float *By,
-                               hipStream_t s) {
+hipError_t launch_prep_rowform_f32(RowForm f, const double *a, int Mu, int Mp, double W, double H, float *BxT,
+                                   float *By, hipStream_t s) {
     const size_t MM = (size_t)Mu * (size_t)Mp;
-    hipLaunchKernelGGL(k_prep_bwd_mat<float>, dim3((unsigned)((MM + 255) / 256)), dim3(256), 0, s, a, Mu, Mp, W,
-                       H, BxT, By);
+    hipLaunchKernelGGL(k_prep_rowform<float>, dim3((unsigned)((MM + 255) / 256)), dim3(256), 0, s, (int)f, a, Mu,
+                       Mp, W, H, BxT, By);
     return hipGetLastError();
 }
 

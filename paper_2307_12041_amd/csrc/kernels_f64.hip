@@ -15,6 +15,8 @@
 // turns.  A run of consecutive frequencies starts from an FP64 seed, reduced to [-1, 1] half
 // turns before sincospi, and continues by rotating the (cos, sin) pair by the one-step phasor.
 // Runs are at most 32 long, so the rotation error stays at a few ulp.
+#include <type_traits>
+
 #include "common.h"
 
 namespace pp {
@@ -60,38 +62,62 @@ struct EdgeRot {
     }
 };
 
-// R consecutive sine-difference values (size at frequency 0) of one block, written at dst[k*stride]
-// (generated in FP64, rounded to T when stored).
-template <int R, typename T>
-__device__ __forceinline__ void gen_sin_run(double c, double sz, double L, int k0, bool valid, T *dst, int stride) {
-    if (!valid) {
-#pragma unroll
-        for (int k = 0; k < R; ++k) dst[k * stride] = (T)0;
-        return;
+// One phasor of a point (centre) coordinate: cos and sin of w_k c for consecutive k.
+struct PointRot {
+    double c, s, c1, s1;
+    __device__ __forceinline__ void init(double x, double L, int k0) {
+        const double t = x / L;
+        sincospi(reduce_half_turns((double)k0 * t), &s, &c);
+        sincospi(reduce_half_turns(t), &s1, &c1);
     }
-    EdgeRot r;
-    r.init(c, sz, L, k0);
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-        dst[k * stride] = (T)((k0 + k == 0) ? sz : (r.sp - r.sm));
-        r.step();
+    __device__ __forceinline__ void step() {
+        const double t = c * c1 - s * s1;
+        s = s * c1 + c * s1;
+        c = t;
     }
-}
+};
 
-// R consecutive cosine-difference values (0 at frequency 0) of one block.
-template <int R, typename T>
-__device__ __forceinline__ void gen_cos_run(double c, double sz, double L, int k0, bool valid, T *dst, int stride) {
+// Kinds of per-block basis runs along one axis (frequency k, w_k = k pi / L, block centre c, size sz):
+//   RUN_SINDIFF  sin(w_k (c + sz/2)) - sin(w_k (c - sz/2)), and sz at k = 0 (the sine-difference
+//                integral times w_k, Sec. III-A coefficient closed forms);
+//   RUN_COSDIFF  cos(w_k (c + sz/2)) - cos(w_k (c - sz/2)), 0 at k = 0 (its derivative, the field of
+//                eq. ksi integrated over the block);
+//   RUN_COS      cos(w_k c)  (point value of the eq. psi basis);
+//   RUN_WSIN     w_k sin(w_k c)  (point value of the eq. ksi basis).
+enum RunKind { RUN_SINDIFF = 0, RUN_COSDIFF = 1, RUN_COS = 2, RUN_WSIN = 3 };
+
+// R consecutive values of one kind for one block, written at dst[k*stride] (generated in FP64,
+// rounded to T when stored).
+template <int KIND, int R, typename T>
+__device__ __forceinline__ void gen_run(double c, double sz, double L, int k0, bool valid, T *dst, int stride) {
     if (!valid) {
 #pragma unroll
         for (int k = 0; k < R; ++k) dst[k * stride] = (T)0;
         return;
     }
-    EdgeRot r;
-    r.init(c, sz, L, k0);
+    if constexpr (KIND == RUN_SINDIFF || KIND == RUN_COSDIFF) {
+        EdgeRot r;
+        r.init(c, sz, L, k0);
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-        dst[k * stride] = (T)(r.cp - r.cm);
-        r.step();
+        for (int k = 0; k < R; ++k) {
+            if constexpr (KIND == RUN_SINDIFF)
+                dst[k * stride] = (T)((k0 + k == 0) ? sz : (r.sp - r.sm));
+            else
+                dst[k * stride] = (T)(r.cp - r.cm);
+            r.step();
+        }
+    } else {
+        PointRot r;
+        r.init(c, L, k0);
+        const double pil = kPi / L;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            if constexpr (KIND == RUN_COS)
+                dst[k * stride] = (T)r.c;
+            else
+                dst[k * stride] = (T)((double)(k0 + k) * pil * r.s);
+            r.step();
+        }
     }
 }
 
@@ -133,10 +159,10 @@ __global__ __launch_bounds__(256) void k_fwd_mat(int64_t n, int Mu, int Mp, doub
         __syncthreads();
         if (side == 0) {
             const double cx = valid ? x[ib] : 0.0, sx = valid ? w[ib] : 0.0;
-            gen_sin_run<RX>(cx, sx, W, tu0 + run * RX, valid, &Xs[kb * LU + run * RX], 1);
+            gen_run<RUN_SINDIFF, RX>(cx, sx, W, tu0 + run * RX, valid, &Xs[kb * LU + run * RX], 1);
         } else {
             const double cy = valid ? y[ib] : 0.0, sy = valid ? h[ib] : 0.0;
-            gen_sin_run<RY>(cy, sy, H, tp0 + run * RY, valid, &Ys[kb * LP + run * RY], 1);
+            gen_run<RUN_SINDIFF, RY>(cy, sy, H, tp0 + run * RY, valid, &Ys[kb * LP + run * RY], 1);
         }
         __syncthreads();
 #pragma unroll
@@ -168,12 +194,16 @@ __global__ __launch_bounds__(256) void k_fwd_mat(int64_t n, int Mu, int Mp, doub
 }
 
 // ------------------------------------------------------------------------------------------------
-// Backward: grid (tiles_b, tiles_n), 256 threads as 2 x 2 waves over a TB (blocks) x TN
-// (epilogue frequencies) tile; K loop over the Ka frequencies of the other axis in chunks of KK.
-// LDS: As[k][i] (generated sine differences), Bs[k][n] (prepared operand); after the K loop the
-// same space holds the cosine differences of one half of the N tile, Es[n][i].
+// Row-form contraction (the backward and the evaluation entry points): for each block (or point)
+// i of a TB tile and each epilogue frequency j of a TN tile,
+//     Z_ij = sum_k Bas_ik B[k][j]          (K loop over the Ka frequencies of one axis, MFMA),
+//     out_i += sum_j E_ij Z_ij             (fused row-dot epilogue, FP64),
+// with Bas of kind KK_KIND along the K axis and E of kind EP1 (and, if EP2 >= 0, a second
+// epilogue of kind EP2 on the same Z into gpart2).  Grid (tiles_b, tiles_n), 256 threads as 2 x 2
+// waves.  LDS: As[k][i] (generated basis), Bs[k][j] (prepared operand); after the K loop the same
+// space holds the epilogue basis of one half of the N tile, Es[j][i].
 // ------------------------------------------------------------------------------------------------
-template <typename T, int TB, int TN, int KK>
+template <typename T, int TB, int TN, int KK, int KA_KIND, int EP1, int EP2>
 __global__ __launch_bounds__(256) void k_bwd_mat(int64_t n, BwdAxis ax) {
     typedef typename Mat<T>::v4 v4;
     constexpr int LB = TB + 1, LN = TN + 1;
@@ -184,8 +214,8 @@ __global__ __launch_bounds__(256) void k_bwd_mat(int64_t n, BwdAxis ax) {
     __shared__ double red[2 * TB];
     T *As = smem, *Bs = smem + KK * LB, *Es = smem;
     constexpr int WI = TB / 2, WJ = TN / 2, SI = WI / 16, SJ = WJ / 16;
-    constexpr int RA = KK * TB / 256;   // sine run per thread per chunk
-    constexpr int RE = HALF * TB / 256; // cosine run per thread per half
+    constexpr int RA = KK * TB / 256;   // K-side run per thread per chunk
+    constexpr int RE = HALF * TB / 256; // epilogue run per thread per half
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t ib0 = (int64_t)blockIdx.x * TB;
@@ -194,8 +224,8 @@ __global__ __launch_bounds__(256) void k_bwd_mat(int64_t n, BwdAxis ax) {
     const int gi = tid % TB, grun = tid / TB;
     const int64_t ib = ib0 + gi;
     const bool valid = ib < n;
-    const double ca = valid ? ax.ca[ib] : 0.0, sa = valid ? ax.sa[ib] : 0.0;
-    const double cb = valid ? ax.cb[ib] : 0.0, sb = valid ? ax.sb[ib] : 0.0;
+    const double ca = valid ? ax.ca[ib] : 0.0, sa = (valid && ax.sa) ? ax.sa[ib] : 0.0;
+    const double cb = valid ? ax.cb[ib] : 0.0, sb = (valid && ax.sb) ? ax.sb[ib] : 0.0;
     const T *__restrict__ B = (const T *)ax.B;
 
     v4 acc[SI][SJ];
@@ -206,7 +236,7 @@ __global__ __launch_bounds__(256) void k_bwd_mat(int64_t n, BwdAxis ax) {
 
     for (int k0 = 0; k0 < ax.Ka; k0 += KK) {
         __syncthreads();
-        gen_sin_run<RA>(ca, sa, ax.La, k0 + grun * RA, valid, &As[(grun * RA) * LB + gi], LB);
+        gen_run<KA_KIND, RA>(ca, sa, ax.La, k0 + grun * RA, valid, &As[(grun * RA) * LB + gi], LB);
         for (int idx = tid; idx < KK * TN; idx += 256) {
             const int k = idx / TN, jj = idx % TN;
             const bool in = (k0 + k < ax.Ka) && (n0 + jj < ax.Nb);
@@ -228,50 +258,55 @@ __global__ __launch_bounds__(256) void k_bwd_mat(int64_t n, BwdAxis ax) {
         }
     }
 
-    // Epilogue: row dot with the cosine differences, one N half at a time.
-    double rs[SI][4];
-#pragma unroll
-    for (int a = 0; a < SI; ++a)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) rs[a][r] = 0.0;
-    for (int hf = 0; hf < 2; ++hf) {
-        __syncthreads();
-        gen_cos_run<RE>(cb, sb, ax.Lb, n0 + hf * HALF + grun * RE, valid, &Es[(grun * RE) * LB + gi], LB);
-        __syncthreads();
-        if (wc == hf) {
-#pragma unroll
-            for (int a = 0; a < SI; ++a)
-#pragma unroll
-                for (int b = 0; b < SJ; ++b)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int il = wi0 + a * 16 + Mat<T>::row(lane, r);
-                        const int jl = b * 16 + (lane & 15);
-                        rs[a][r] += (double)acc[a][b][r] * (double)Es[jl * LB + il];
-                    }
-        }
-    }
-    // Sum over the 16 lanes that share a row (fixed order: butterfly).
-#pragma unroll
-    for (int a = 0; a < SI; ++a)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            double v = rs[a][r];
-            v += __shfl_xor(v, 1);
-            v += __shfl_xor(v, 2);
-            v += __shfl_xor(v, 4);
-            v += __shfl_xor(v, 8);
-            rs[a][r] = v;
-        }
-    if ((lane & 15) == 0) {
+    // Epilogue(s): row dot with the epilogue basis, one N half at a time; the 16 lanes that share
+    // a row are summed by a fixed butterfly, the two column waves in fixed order.
+    auto epilogue = [&](auto kind_tag, double *__restrict__ gpart) {
+        constexpr int EK = decltype(kind_tag)::value;
+        double rs[SI][4];
 #pragma unroll
         for (int a = 0; a < SI; ++a)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) red[wc * TB + wi0 + a * 16 + Mat<T>::row(lane, r)] = rs[a][r];
-    }
-    __syncthreads();
-    if (tid < TB && ib0 + tid < n)
-        ax.gpart[(size_t)blockIdx.y * (size_t)n + (size_t)(ib0 + tid)] = red[tid] + red[TB + tid];
+            for (int r = 0; r < 4; ++r) rs[a][r] = 0.0;
+        for (int hf = 0; hf < 2; ++hf) {
+            __syncthreads();
+            gen_run<EK, RE>(cb, sb, ax.Lb, n0 + hf * HALF + grun * RE, valid, &Es[(grun * RE) * LB + gi], LB);
+            __syncthreads();
+            if (wc == hf) {
+#pragma unroll
+                for (int a = 0; a < SI; ++a)
+#pragma unroll
+                    for (int b = 0; b < SJ; ++b)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int il = wi0 + a * 16 + Mat<T>::row(lane, r);
+                            const int jl = b * 16 + (lane & 15);
+                            rs[a][r] += (double)acc[a][b][r] * (double)Es[jl * LB + il];
+                        }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < SI; ++a)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double v = rs[a][r];
+                v += __shfl_xor(v, 1);
+                v += __shfl_xor(v, 2);
+                v += __shfl_xor(v, 4);
+                v += __shfl_xor(v, 8);
+                rs[a][r] = v;
+            }
+        if ((lane & 15) == 0) {
+#pragma unroll
+            for (int a = 0; a < SI; ++a)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) red[wc * TB + wi0 + a * 16 + Mat<T>::row(lane, r)] = rs[a][r];
+        }
+        __syncthreads();
+        if (tid < TB && ib0 + tid < n)
+            gpart[(size_t)blockIdx.y * (size_t)n + (size_t)(ib0 + tid)] = red[tid] + red[TB + tid];
+    };
+    epilogue(std::integral_constant<int, EP1>{}, ax.gpart);
+    if constexpr (EP2 >= 0) epilogue(std::integral_constant<int, (EP2 >= 0 ? EP2 : 0)>{}, ax.gpart2);
 }
 
 template <typename T>
@@ -289,13 +324,26 @@ hipError_t launch_fwd_mat(const FwdPlan &pl, int64_t n, int Mu, int Mp, double W
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_bwd_mat(const BwdPlan &pl, int64_t n, const BwdAxis &ax, hipStream_t s) {
+template <typename T, int KA_KIND, int EP1, int EP2>
+hipError_t launch_rowform(const BwdPlan &pl, int64_t n, const BwdAxis &ax, hipStream_t s) {
     if (!(pl.tb == 128 && pl.tn == 128 && pl.kk == 32)) return hipErrorInvalidValue;
+    if (n == 0) return hipSuccess;
     const int tiles_n = (ax.Nb + pl.tn - 1) / pl.tn;
-    dim3 grid((unsigned)pl.tiles_b, tiles_n);
-    hipLaunchKernelGGL((k_bwd_mat<T, 128, 128, 32>), grid, dim3(256), 0, s, n, ax);
+    const int64_t tiles_b = (n + pl.tb - 1) / pl.tb;
+    dim3 grid((unsigned)tiles_b, tiles_n);
+    hipLaunchKernelGGL((k_bwd_mat<T, 128, 128, 32, KA_KIND, EP1, EP2>), grid, dim3(256), 0, s, n, ax);
     return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rowform_kind(RowForm f, const BwdPlan &pl, int64_t n, const BwdAxis &ax, hipStream_t s) {
+    switch (f) {
+        case ROW_FIELD: return launch_rowform<T, RUN_SINDIFF, RUN_COSDIFF, -1>(pl, n, ax, s);
+        case ROW_POTENTIAL: return launch_rowform<T, RUN_SINDIFF, RUN_SINDIFF, -1>(pl, n, ax, s);
+        case ROW_POINT_DUAL: return launch_rowform<T, RUN_COS, RUN_COS, RUN_WSIN>(pl, n, ax, s);
+        case ROW_POINT_WSIN: return launch_rowform<T, RUN_COS, RUN_WSIN, -1>(pl, n, ax, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -308,11 +356,11 @@ hipError_t launch_fwd_f32(const FwdPlan &pl, int64_t n, int Mu, int Mp, double W
                           const double *y, const double *w, const double *h, float *part, hipStream_t s) {
     return launch_fwd_mat<float>(pl, n, Mu, Mp, W, H, x, y, w, h, part, s);
 }
-hipError_t launch_bwd_f64(const BwdPlan &pl, int64_t n, const BwdAxis &ax, hipStream_t s) {
-    return launch_bwd_mat<double>(pl, n, ax, s);
+hipError_t launch_rowform_f64(RowForm f, const BwdPlan &pl, int64_t n, const BwdAxis &ax, hipStream_t s) {
+    return launch_rowform_kind<double>(f, pl, n, ax, s);
 }
-hipError_t launch_bwd_f32(const BwdPlan &pl, int64_t n, const BwdAxis &ax, hipStream_t s) {
-    return launch_bwd_mat<float>(pl, n, ax, s);
+hipError_t launch_rowform_f32(RowForm f, const BwdPlan &pl, int64_t n, const BwdAxis &ax, hipStream_t s) {
+    return launch_rowform_kind<float>(f, pl, n, ax, s);
 }
 
 }  // namespace pp

@@ -107,6 +107,29 @@ def test_entry_points_validate_before_launch(lib):
     assert lib.pp_energy(ctypes.byref(bad), fake, fake, fake, fake, fake, fake, fake, need, nul) == -1
 
 
+def test_evaluation_entry_points_validate_before_launch(lib):
+    prob = P()
+    st, need = ws_size(lib, prob)
+    assert st == 0
+    fake = ctypes.c_void_p(1 << 20)
+    odd = ctypes.c_void_p((1 << 20) + 4)
+    nul = None
+    pf, bp = lib.pp_point_field, lib.pp_block_potential
+    assert pf(None, fake, fake, fake, fake, fake, fake, fake, need, nul) == -1
+    assert pf(ctypes.byref(prob), nul, fake, fake, fake, fake, fake, fake, need, nul) == -1
+    assert pf(ctypes.byref(prob), fake, fake, nul, fake, fake, fake, fake, need, nul) == -1
+    assert pf(ctypes.byref(prob), fake, fake, fake, odd, fake, fake, fake, need, nul) == -1
+    assert pf(ctypes.byref(prob), fake, fake, fake, fake, fake, fake, fake, need - 1, nul) == -2
+    assert bp(ctypes.byref(prob), fake, fake, fake, nul, fake, fake, fake, need, nul) == -1
+    assert bp(ctypes.byref(prob), fake, fake, fake, fake, fake, nul, fake, need, nul) == -1
+    assert bp(ctypes.byref(prob), fake, fake, fake, fake, fake, fake, fake, need - 1, nul) == -2
+    # only the FP64 and FP32 operand types are offered for these two calls
+    for prec in (2, 3):
+        q = P(precision=prec)
+        assert pf(ctypes.byref(q), fake, fake, fake, fake, fake, fake, fake, need, nul) == -3
+        assert bp(ctypes.byref(q), fake, fake, fake, fake, fake, fake, fake, need, nul) == -3
+
+
 def test_unsupported_modes_reported(lib):
     st, _ = ws_size(lib, P(precision=4))
     assert st == -3
