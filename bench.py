@@ -63,10 +63,10 @@ def measured_traffic(workload, precision, stage):
     return None if st is None else st.get("hbm_bytes_per_launch")
 
 
-def timed_steps(pp, torch, t, wl, prec, steps, warmup, ws, positions=None):
+def timed_steps(pp, torch, t, wl, prec, steps, warmup, ws, positions=None, basis="recompute"):
     """Warm up, then time `steps` evaluations (energy + gradient).  With `positions` (a list of
     (x, y) device tensors) step k evaluates positions[k % len]."""
-    kw = dict(W=wl.W, H=wl.H, precision=prec, workspace=ws)
+    kw = dict(W=wl.W, H=wl.H, precision=prec, workspace=ws, basis=basis)
 
     def args(k):
         if positions is None:
@@ -86,7 +86,7 @@ def timed_steps(pp, torch, t, wl, prec, steps, warmup, ws, positions=None):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stages = {}
-    for st in ("tables", "fwd", "reduce", "energy", "prep", "bwd", "final"):
+    for st in ("tables", "build", "fwd", "reduce", "energy", "prep", "bwd", "final"):
         ms, cnt = pp.timing_query(st)
         if cnt:
             stages[st] = (ms, cnt)
@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", type=int, default=4, help="workload index in workloads.CONFIGS")
     ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "bf16", "fp32", "fp64"])
+    ap.add_argument("--basis", default="recompute", choices=["recompute", "store"],
+                    help="basis tables regenerated on chip, or built in HBM once per step")
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--fp32-steps", type=int, default=2, help="steps of the FP32 path on the same workload (0: skip)")
@@ -130,8 +132,8 @@ def main():
     pairs = wl.pairs
     log(f"[bench] workload {wl.name}: n={wl.n} Mu={wl.Mu} Mp={wl.Mp} pairs/step={pairs:.3e}")
     t = [torch.as_tensor(v, device=dev) for v in wl.arrays()]
-    need = max(pp.workspace_size(wl.W, wl.H, wl.n, wl.Mu, wl.Mp, precision=p)
-               for p in (args.precision, "fp32", "fp64"))
+    need = max([pp.workspace_size(wl.W, wl.H, wl.n, wl.Mu, wl.Mp, precision=p) for p in ("fp32", "fp64")]
+               + [pp.workspace_size(wl.W, wl.H, wl.n, wl.Mu, wl.Mp, precision=args.precision, basis=args.basis)])
     ws = torch.empty(need, dtype=torch.uint8, device=dev)
     log(f"[bench] workspace {need / 2**20:.1f} MiB")
     if args.copy_calibration_gib > 0:
@@ -151,7 +153,8 @@ def main():
             j = jitter(wl, k)
             positions.append((torch.as_tensor(j.x, device=dev), torch.as_tensor(j.y, device=dev)))
         log(f"[bench] {args.steps} jittered position sets resident on the device")
-    dt, stages, (E, a, gx, gy) = timed_steps(pp, torch, t, wl, args.precision, args.steps, args.warmup, ws, positions)
+    dt, stages, (E, a, gx, gy) = timed_steps(pp, torch, t, wl, args.precision, args.steps, args.warmup, ws, positions,
+                                             basis=args.basis)
     value = pairs * args.steps / dt
     log(f"[bench] {args.precision}: {dt / args.steps * 1e3:.2f} ms/step, {value:.4e} pairs/s; stages "
         + ", ".join(f"{k}={v[0] / v[1]:.2f}ms x{v[1] // args.steps}" for k, v in stages.items()))
@@ -180,7 +183,7 @@ def main():
            "dtype": {"bf16x3": "bf16", "bf16": "bf16", "fp32": "f32", "fp64": "f64"}[args.precision],
            "data": "synthetic",
            "config": {"workload": wl.name + ("_jittered" if args.jitter else ""), "n_blocks": wl.n, "Mu": wl.Mu,
-                      "Mp": wl.Mp, "W": wl.W, "H": wl.H, "precision": args.precision, "basis": "recompute",
+                      "Mp": wl.Mp, "W": wl.W, "H": wl.H, "precision": args.precision, "basis": args.basis,
                       "pairs_per_step": pairs},
            "stages_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stages.items()},
            "roofline": roofline}

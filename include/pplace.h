@@ -70,9 +70,18 @@ typedef enum pp_precision {
     PP_FP8X3 = 5    /* reserved: PP_ERR_UNSUPPORTED */
 } pp_precision;
 
+/* Where the basis values (the sine-difference factors of the Sec. III-A closed forms) live.
+ * PP_BASIS_RECOMPUTE: generated on chip inside every contraction tile, never stored.
+ * PP_BASIS_STORE (PP_BF16 and PP_BF16X3 only; other precisions give PP_ERR_UNSUPPORTED):
+ *   pp_coeffs / pp_energy build the n x Mu and n x Mp tables (bf16 hi and lo) in the workspace and
+ *   contract them from HBM; pp_field then READS the tables that the last pp_coeffs / pp_energy call
+ *   left in the same workspace, so in this mode the workspace doubles as reserve space: pp_field
+ *   must get the same problem, the same blocks and the same, unmodified workspace.  The tables
+ *   take 2 (x3: 4) bytes per block and frequency of each axis (rows rounded up to 256 blocks,
+ *   frequencies to 256). */
 typedef enum pp_basis_mode {
-    PP_BASIS_RECOMPUTE = 0,  /* basis tiles regenerated on chip, never stored */
-    PP_BASIS_STORE = 1       /* reserved: PP_ERR_UNSUPPORTED */
+    PP_BASIS_RECOMPUTE = 0,
+    PP_BASIS_STORE = 1
 } pp_basis_mode;
 
 /* Problem description (Sec. II-A: region and blocks; truncation of the series, Sec. III-B/C). */
@@ -142,7 +151,8 @@ const char *pp_strerror(int status);
  * summed duration in milliseconds and the number of launches.  Stage names: "tables" (per-block
  * phase records), "fwd" (coefficient contraction), "reduce" (split-K sum, scale, energy
  * partials), "energy" (final energy sum), "prep" (row-form operands), "bwd" (the two gradient
- * contractions, one record each), "final" (per-block partial sums), "point" (pp_point_field
+ * contractions, one record each), "final" (per-block partial sums), "build" (store-mode basis
+ * tables), "point" (pp_point_field
  * contractions), "potential" (pp_block_potential contraction).  Unknown names give count 0.
  * Returns PP_OK, PP_ERR_ARG for NULL arguments, PP_ERR_DEVICE if an event query fails.  Recording
  * is process wide and guarded by a lock; it is meant for benchmarks, not for production calls. */

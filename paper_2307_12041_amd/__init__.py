@@ -168,7 +168,12 @@ def energy(x, y, w, h, *, W, H, Mu, Mp, precision="fp64", basis="recompute", wan
 
 
 def field(x, y, w, h, a, *, W, H, precision="fp64", basis="recompute", dE=None, workspace=None):
-    """Per-block gradient (gx, gy) = dE * (dE/dx_i, dE/dy_i); the force on block i is -(gx, gy)."""
+    """Per-block gradient (gx, gy) = dE * (dE/dx_i, dE/dy_i); the force on block i is -(gx, gy).
+
+    With basis "store", `workspace` must be the one that the energy (or coeffs) call of the same
+    blocks filled: the gradient reads the basis tables that call left in it."""
+    if basis == "store" and workspace is None:
+        raise ValueError("basis='store': pass the workspace that energy()/coeffs() of the same blocks filled")
     dev, n = _blocks(x, y, w, h)
     if a.dtype != torch.float64 or a.dim() != 2 or not a.is_contiguous() or a.device != dev:
         raise ValueError("a must be a contiguous [Mu, Mp] float64 tensor on the blocks' device")
@@ -249,14 +254,20 @@ def timing_query(stage: str):
 class PPEnergy(torch.autograd.Function):
     """E(x, y) with a backward that maps dE to per-block gradients through pp_field.
 
-    The forward keeps only the coefficients a (Mu*Mp FP64); the backward regenerates every basis
-    tile on chip rather than storing n x M tables.  w and h are not differentiated."""
+    With basis "recompute" the forward keeps only the coefficients a (Mu*Mp FP64) and the backward
+    regenerates every basis tile on chip.  With basis "store" the forward's workspace, which holds
+    the n x M basis tables, is kept until the backward reads them.  w and h are not differentiated."""
 
     @staticmethod
     def forward(ctx, x, y, w, h, W, H, Mu, Mp, precision, basis):
-        E, a = energy(x, y, w, h, W=W, H=H, Mu=Mu, Mp=Mp, precision=precision, basis=basis)
+        ws = None
+        if basis == "store":
+            ws = torch.empty(max(workspace_size(W, H, x.shape[0], Mu, Mp, precision, basis), 1), dtype=torch.uint8,
+                             device=x.device)
+        E, a = energy(x, y, w, h, W=W, H=H, Mu=Mu, Mp=Mp, precision=precision, basis=basis, workspace=ws)
         ctx.save_for_backward(x, y, w, h, a)
         ctx.cfg = (W, H, precision, basis)
+        ctx.ws = ws
         return E
 
     @staticmethod
@@ -264,7 +275,8 @@ class PPEnergy(torch.autograd.Function):
         x, y, w, h, a = ctx.saved_tensors
         W, H, precision, basis = ctx.cfg
         gx, gy = field(x.detach(), y.detach(), w.detach(), h.detach(), a, W=W, H=H, precision=precision,
-                       basis=basis, dE=gE.detach())
+                       basis=basis, dE=gE.detach(), workspace=ctx.ws)
+        ctx.ws = None
         return gx, gy, None, None, None, None, None, None, None, None
 
 

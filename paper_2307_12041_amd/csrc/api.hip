@@ -26,7 +26,8 @@ int validate_problem(const pp_problem *P) {
     if (P->Mu < 1 || P->Mp < 1 || P->Mu > kMaxFreq || P->Mp > kMaxFreq) return PP_ERR_ARG;
     if (P->precision < PP_FP64 || P->precision > PP_FP8X3) return PP_ERR_ARG;
     if (P->basis_mode != PP_BASIS_RECOMPUTE && P->basis_mode != PP_BASIS_STORE) return PP_ERR_ARG;
-    if (!supported_precision(P->precision) || P->basis_mode != PP_BASIS_RECOMPUTE) return PP_ERR_UNSUPPORTED;
+    if (!supported_precision(P->precision)) return PP_ERR_UNSUPPORTED;
+    if (P->basis_mode == PP_BASIS_STORE && !is_bf16(P->precision)) return PP_ERR_UNSUPPORTED;
     return PP_OK;
 }
 
@@ -88,6 +89,7 @@ int bf16_kh(int Ka) { return (Ka + 63) / 64 * 32; }
 // region (partials, energy partials) and the backward region (operands, gradient partials) overlap.
 struct Layout {
     size_t tx, ty;                       // bf16 path: per-block phase records
+    size_t sxh, sxl, syh, syl;           // store mode: basis tables (kept from the forward to the backward)
     size_t part, epart;                  // forward region
     size_t bx, by, gpx, gpy, gpz;        // backward region (gpz: FP64 / FP32 point field only)
     size_t fwd_bytes, bwd_bytes, total;
@@ -102,6 +104,15 @@ Layout layout(const pp_problem &P) {
     if (is_bf16(P.precision)) {
         L.tx = off; off = align_up(off + (size_t)P.n * sizeof(PhaseRec));
         L.ty = off; off = align_up(off + (size_t)P.n * sizeof(PhaseRec));
+    }
+    if (P.basis_mode == PP_BASIS_STORE) {
+        const bool x3 = P.precision == PP_BF16X3;
+        const size_t rows = (size_t)store_rows(P.n);
+        const size_t bx = rows * (size_t)store_ld(P.Mu) * 2, by = rows * (size_t)store_ld(P.Mp) * 2;
+        L.sxh = off; off = align_up(off + bx);
+        if (x3) { L.sxl = off; off = align_up(off + bx); }
+        L.syh = off; off = align_up(off + by);
+        if (x3) { L.syl = off; off = align_up(off + by); }
     }
     const size_t common = off;
     L.part = off;  off = align_up(off + (size_t)f.splits * MM * f.part_elem);
@@ -127,6 +138,18 @@ Layout layout(const pp_problem &P) {
     return L;
 }
 
+StoreTables store_tables(const pp_problem &P, const Layout &L, char *base) {
+    const bool x3 = P.precision == PP_BF16X3;
+    StoreTables t;
+    t.xh = (const unsigned short *)(base + L.sxh);
+    t.xl = x3 ? (const unsigned short *)(base + L.sxl) : nullptr;
+    t.yh = (const unsigned short *)(base + L.syh);
+    t.yl = x3 ? (const unsigned short *)(base + L.syl) : nullptr;
+    t.ldx = store_ld(P.Mu);
+    t.ldy = store_ld(P.Mp);
+    return t;
+}
+
 int check_ws(const Layout &L, void *ws, size_t ws_bytes) {
     if (ws_bytes < L.total) return PP_ERR_WORKSPACE;
     if (L.total > 0 && (!ws || ((uintptr_t)ws % kAlign) != 0)) return PP_ERR_ARG;
@@ -143,10 +166,24 @@ int run_forward(const pp_problem &P, const double *x, const double *y, const dou
     double *epart = (double *)(base + L.epart);
     hipError_t err;
     if (is_bf16(P.precision)) {
+        const bool x3 = P.precision == PP_BF16X3;
         PhaseRec *tx = (PhaseRec *)(base + L.tx), *ty = (PhaseRec *)(base + L.ty);
         { TimedLaunch t("tables", s); err = launch_phase_tables(P.n, x, y, w, h, P.W, P.H, tx, ty, s); }
         if (err != hipSuccess) return PP_ERR_DEVICE;
-        { TimedLaunch t("fwd", s); err = launch_fwd_bf16(f, P.precision == PP_BF16X3, P.n, P.Mu, P.Mp, tx, ty, (float *)part, s); }
+        if (P.basis_mode == PP_BASIS_STORE) {
+            const StoreTables st = store_tables(P, L, base);
+            {
+                TimedLaunch t("build", s);
+                err = launch_build_table(x3, P.n, P.Mu, tx, (unsigned short *)st.xh, (unsigned short *)st.xl, s);
+                if (err == hipSuccess)
+                    err = launch_build_table(x3, P.n, P.Mp, ty, (unsigned short *)st.yh, (unsigned short *)st.yl, s);
+            }
+            if (err != hipSuccess) return PP_ERR_DEVICE;
+            { TimedLaunch t("fwd", s); err = launch_fwd_bf16_st(f, x3, P.n, P.Mu, P.Mp, st, (float *)part, s); }
+        } else {
+            TimedLaunch t("fwd", s);
+            err = launch_fwd_bf16(f, x3, P.n, P.Mu, P.Mp, tx, ty, (float *)part, s);
+        }
     } else if (P.precision == PP_FP32) {
         TimedLaunch t("fwd", s);
         err = launch_fwd_f32(f, P.n, P.Mu, P.Mp, P.W, P.H, x, y, w, h, (float *)part, s);
@@ -244,8 +281,17 @@ int pp_field(const pp_problem *P, const double *x, const double *y, const double
                 return PP_ERR_DEVICE;
         }
         // gx: K = p (basis of y), epilogue over u (x);  gy: K = u (basis of x), epilogue over p (y).
-        BwdAxisBf16 axx{ty, tx, P->Mp, P->Mu, khx, bxt, gpx};
-        BwdAxisBf16 axy{tx, ty, P->Mu, P->Mp, khy, byt, gpy};
+        BwdAxisBf16 axx{ty, tx, P->Mp, P->Mu, khx, bxt, gpx, nullptr, nullptr, 0, 0, 0};
+        BwdAxisBf16 axy{tx, ty, P->Mu, P->Mp, khy, byt, gpy, nullptr, nullptr, 0, 0, 0};
+        if (P->basis_mode == PP_BASIS_STORE) {
+            // the tables that pp_coeffs / pp_energy left in the workspace
+            const StoreTables st = store_tables(*P, L, base);
+            const int tb = (int)((P->n + 255) / 256);
+            axx.tab_h = st.yh; axx.tab_l = st.yl; axx.tab_ld = st.ldy;
+            axx.tiles_b = tb; axx.tiles_n = (P->Mu + 255) / 256;
+            axy.tab_h = st.xh; axy.tab_l = st.xl; axy.tab_ld = st.ldx;
+            axy.tiles_b = tb; axy.tiles_n = (P->Mp + 255) / 256;
+        }
         { TimedLaunch t("bwd", s); if (launch_bwd_bf16(x3, P->n, axx, s) != hipSuccess) return PP_ERR_DEVICE; }
         { TimedLaunch t("bwd", s); if (launch_bwd_bf16(x3, P->n, axy, s) != hipSuccess) return PP_ERR_DEVICE; }
         { TimedLaunch t("final", s); if (launch_bwd_final(gpx, b.tiles_nx, gpy, b.tiles_ny, P->n, dE, gx, gy, s) != hipSuccess) return PP_ERR_DEVICE; }

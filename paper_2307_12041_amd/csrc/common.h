@@ -78,6 +78,16 @@ struct BwdAxisBf16 {
     int Ka, Nb, Kh;              // K frequencies, N frequencies, K half length (multiple of 32)
     const unsigned short *B;     // tiled operand (hi and lo bf16, see k_prep_bwd_bf16)
     double *gpart;               // out: [tiles_n][n]
+    // Store mode (tab_h non-NULL): the K-axis basis read from its stored tables instead of
+    // generated; tab_ld is their row length, tiles_b / tiles_n the grid of block / N tiles.
+    const unsigned short *tab_h, *tab_l;
+    int tab_ld, tiles_b, tiles_n;
+};
+
+// Store-mode basis tables of both axes (bf16 hi and lo, row-major [block][frequency]).
+struct StoreTables {
+    const unsigned short *xh, *xl, *yh, *yl;
+    int ldx, ldy;
 };
 
 // Brackets one kernel launch with HIP events when event timing is on (timing.hip).
@@ -111,6 +121,14 @@ hipError_t launch_prep_bwd_bf16(const double *a, int Mu, int Mp, double W, doubl
                                 unsigned short *B, hipStream_t s);
 size_t bwd_bf16_operand_elems(int Np, int Kh);   // bf16 elements of one tiled backward operand
 hipError_t launch_bwd_bf16(bool x3, int64_t n, const BwdAxisBf16 &ax, hipStream_t s);
+// Store mode: table rows (n rounded up to 256) and row length (M rounded up to 256); the table of
+// one axis from its phase records (lo table only for x3); the forward from both axes' tables.
+int64_t store_rows(int64_t n);
+int store_ld(int M);
+hipError_t launch_build_table(bool x3, int64_t n, int M, const PhaseRec *tab, unsigned short *th, unsigned short *tl,
+                              hipStream_t s);
+hipError_t launch_fwd_bf16_st(const FwdPlan &pl, bool x3, int64_t n, int Mu, int Mp, const StoreTables &t,
+                              float *part, hipStream_t s);
 
 // Sum split-K partials (FP64 or FP32), scale, write a, per-block energy partials.
 hipError_t launch_reduce_scale(const void *part, bool part_f32, int splits, int Mu, int Mp, double W,

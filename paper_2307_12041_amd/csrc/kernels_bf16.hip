@@ -144,8 +144,7 @@ struct GenRec {
     float ca, sa, c2ah, c2al, cb, sb, c2bh, c2bl, size;
 };
 
-__device__ __forceinline__ GenRec load_rec(const PhaseRec *__restrict__ tab, int64_t n, int64_t chunk, int k) {
-    const int64_t ib = chunk * FKB + k;
+__device__ __forceinline__ GenRec load_rec_at(const PhaseRec *__restrict__ tab, int64_t n, int64_t ib) {
     GenRec g;
     if (ib < n) {
         const PhaseRec *p = tab + ib;
@@ -159,6 +158,29 @@ __device__ __forceinline__ GenRec load_rec(const PhaseRec *__restrict__ tab, int
         g.ca = g.sa = g.c2ah = g.c2al = g.cb = g.sb = g.c2bh = g.c2bl = g.size = 0.0f;
     }
     return g;
+}
+
+__device__ __forceinline__ GenRec load_rec(const PhaseRec *__restrict__ tab, int64_t n, int64_t chunk, int k) {
+    return load_rec_at(tab, n, chunk * FKB + k);
+}
+
+// The basis values S_u (u0 <= u < u0 + 32) of one record (S_0 = size); the same arithmetic as the
+// generating forward (fwd_gen), so stored and regenerated tables agree bit for bit.
+__device__ __forceinline__ void gen32(const GenRec &R, int u0, float (&v)[32]) {
+    Cheb ca, sb;
+    float c0, s0, cb0, sb0;
+    seed_phasor(u0, R.ta, c0, s0);
+    seed_phasor(u0, R.tb, cb0, sb0);
+    ca.f = c0;
+    ca.fm = c0 * R.ca + s0 * R.sa;            // cos((u0 - 1) alpha)
+    ca.ch = R.c2ah; ca.cl = R.c2al;
+    sb.f = 2.0f * sb0;                         // 2 sin(u0 beta); an all-zero record gives 0 throughout
+    sb.fm = 2.0f * (sb0 * R.cb - cb0 * R.sb);  // 2 sin((u0 - 1) beta)
+    sb.ch = R.c2bh; sb.cl = R.c2bl;
+    v[0] = ca.f * sb.f;
+#pragma unroll
+    for (int j = 1; j < 32; ++j) v[j] = ca.next() * sb.next();
+    if (u0 == 0) v[0] = R.size;
 }
 
 // 32 consecutive frequencies f0 + 32 r .. + 31 of block k of the chunk, split hi/lo and stored.
@@ -377,13 +399,26 @@ __device__ __forceinline__ void bwd_copy_b(const unsigned short *__restrict__ gt
 
 __device__ __forceinline__ void wait_copies() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-template <bool X3>
+template <bool X3, bool ST>
 __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
     __shared__ __attribute__((aligned(16))) char smem[2 * BBUF];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, j = lane & 31;
-    const int64_t i0 = (int64_t)blockIdx.x * 256 + 32 * wave;
-    const int ntile = blockIdx.y, n0 = ntile * BTN;
+    int btile, ntile;
+    if constexpr (ST) {
+        // One-dimensional grid, workgroups dealt round-robin over the 8 XCDs: the N tiles of one
+        // block tile go to the same XCD at about the same time, so they share its L2 copy of the
+        // block tile's table rows.
+        const int w = blockIdx.x, xcd = w & 7, slot = w >> 3;
+        btile = xcd + 8 * (slot / ax.tiles_n);
+        ntile = slot % ax.tiles_n;
+        if (btile >= ax.tiles_b) return;
+    } else {
+        btile = blockIdx.x;
+        ntile = blockIdx.y;
+    }
+    const int64_t i0 = (int64_t)btile * 256 + 32 * wave;
+    const int n0 = ntile * BTN;
     const int64_t ib = i0 + j;        // this lane's block for the A operand
     const bool valid = ib < n;
     const int Q = ax.Kh / 32;         // chunks along K
@@ -398,7 +433,7 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
     float jac, jas, jbc, jbs;         // 32-frequency jumps
     float sac, sas, sbc, sbs;         // one-frequency steps (for the k - 1 terms)
     float size0 = 0.0f;
-    if (valid) {
+    if (!ST && valid) {
         const PhaseRec RA = ax.ta[ib];
         seed_phasor(kcur, RA.ta, pac, pas);
         seed_phasor(kcur, RA.tb, pbc, pbs);
@@ -467,7 +502,7 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
 #pragma unroll
             for (int b = 0; b < 8; ++b) bl[b] = *(const bf16x8 *)(cur + BARR + (32 * b + j) * BROW + bseg);
         }
-        gen_a(nah, nal);
+        if constexpr (!ST) gen_a(nah, nal);
 #pragma unroll
         for (int b = 0; b < 8; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[b], acc[b], 0, 0, 0);
         if (X3) {
@@ -476,15 +511,53 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
 #pragma unroll
             for (int b = 0; b < 8; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[b], acc[b], 0, 0, 0);
         }
-        // Schedule: the B reads first, then each MFMA followed by a few VALU ops of the generator.
-        __builtin_amdgcn_sched_group_barrier(0x100, X3 ? 16 : 8, 0);
+        if constexpr (!ST) {
+            // Schedule: the B reads first, then each MFMA followed by a few VALU ops of the generator.
+            __builtin_amdgcn_sched_group_barrier(0x100, X3 ? 16 : 8, 0);
 #pragma unroll
-        for (int i = 0; i < (X3 ? 24 : 8); ++i) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x002, X3 ? 3 : 8, 0);
+            for (int i = 0; i < (X3 ? 24 : 8); ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x002, X3 ? 3 : 8, 0);
+            }
         }
     };
 
+    if constexpr (ST) {
+        // A from the stored basis table: row ib, frequencies h Kh + 32 q + 8 s + 0..7 for step s of
+        // chunk q (rows past n are zero).  The next chunk's operands are requested before its B
+        // copies, a whole chunk ahead of their use.
+        const unsigned short *rh = ax.tab_h + (size_t)ib * (size_t)ax.tab_ld + h * ax.Kh;
+        const unsigned short *rl = ax.tab_l + (size_t)ib * (size_t)ax.tab_ld + h * ax.Kh;
+        bf16x8 cah[4], cal[4], nah[4], nal[4];
+        auto load_a = [&](int q, bf16x8 (&dh)[4], bf16x8 (&dl)[4]) {
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+                dh[st] = *(const bf16x8 *)(rh + 32 * q + 8 * st);
+                if (X3) dl[st] = *(const bf16x8 *)(rl + 32 * q + 8 * st);
+            }
+        };
+        load_a(0, cah, cal);
+        bwd_copy_b(gb, smem, tid);
+        wait_copies();
+        __syncthreads();
+        for (int q = 0; q < Q; ++q) {
+            char *cur = smem + (q & 1) * BBUF, *nxt = smem + ((q & 1) ^ 1) * BBUF;
+            if (q + 1 < Q) {
+                load_a(q + 1, nah, nal);
+                bwd_copy_b(gb + (size_t)(q + 1) * tile_elems, nxt, tid);
+            }
+            bf16x8 dummy_h, dummy_l;
+#pragma unroll
+            for (int st = 0; st < 4; ++st) step(cur, st, cah[st], cal[st], dummy_h, dummy_l);
+            wait_copies();
+            __syncthreads();
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+                cah[st] = nah[st];
+                if (X3) cal[st] = nal[st];
+            }
+        }
+    } else {
     bf16x8 ah0, al0, ah1, al1;
     gen_a(ah0, al0);                  // A of the first step
     bwd_copy_b(gb, smem, tid);
@@ -502,6 +575,7 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
         step(cur, 3, ah1, al1, ah0, al0);
         wait_copies();
         __syncthreads();
+    }
     }
 
     // Epilogue: lane holds G for rows 8 (r / 4) + 4 h + r % 4 and columns n0 + 32 b + j.
@@ -587,6 +661,125 @@ __global__ void k_prep_bwd_bf16(const double *__restrict__ a, int Mu, int Mp, do
     B[idx] = __builtin_bit_cast(unsigned short, (__bf16)out);
 }
 
+// ================================================================================================
+// Store mode: the basis S_iu of one axis held in HBM as two bf16 tables (hi, lo), row-major
+// [row = block][frequency], ld = frequencies rounded up to 256, rows = blocks rounded up to 256
+// (rows past n are zero).  Built once per call from the phase records; the forward stages
+// 32-block x 256-frequency tiles of both tables into LDS by direct global->LDS copies in exactly
+// the swizzled byte order that the generating forward writes, and the backward loads its
+// K-axis operand straight from the rows.
+// ================================================================================================
+template <bool X3>
+__global__ __launch_bounds__(256) void k_build_table(int64_t n, int64_t nrows, int ld,
+                                                     const PhaseRec *__restrict__ tab,
+                                                     unsigned short *__restrict__ th,
+                                                     unsigned short *__restrict__ tl) {
+    const int runs = ld >> 5;
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= nrows * runs) return;
+    const int64_t ib = idx / runs;
+    const int r = (int)(idx % runs);
+    const GenRec R = load_rec_at(tab, n, ib);
+    float v[32];
+    gen32(R, 32 * r, v);
+    unsigned short *dh = th + (size_t)ib * (size_t)ld + 32 * r;
+    unsigned short *dl = X3 ? tl + (size_t)ib * (size_t)ld + 32 * r : nullptr;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        unsigned hh[4], ll[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (X3) split2(v[8 * m + 2 * e], v[8 * m + 2 * e + 1], hh[e], ll[e]);
+            else hh[e] = pack_bf16(v[8 * m + 2 * e], v[8 * m + 2 * e + 1]);
+        }
+        *(u32x4 *)(dh + 8 * m) = u32x4{hh[0], hh[1], hh[2], hh[3]};
+        if (X3) *(u32x4 *)(dl + 8 * m) = u32x4{ll[0], ll[1], ll[2], ll[3]};
+    }
+}
+
+// Direct copies of one chunk's four LDS tiles (Xh, Xl, Yh, Yl of 32 blocks x 256 frequencies):
+// LDS byte o of a tile holds row k = o / 512, physical segment o / 16 % 32, i.e. logical segment
+// (o / 16 % 32) ^ g(k) of the same row (the swizzle of fswz is an involution).
+template <bool X3>
+__device__ __forceinline__ void fwd_copy(const StoreTables &t, int64_t c, int tu0, int tp0, char *buf, int tid) {
+    typedef __attribute__((address_space(3))) void lds_void;
+    const int wave = tid >> 6, lane = tid & 63;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const int o = m * 8192 + wave * 1024 + lane * 16;
+        const int k = o >> 9, ps = (o >> 4) & 31;
+        const int g = ((k & 3) << 1) | ((k >> 2) & 1);
+        const int col = (ps ^ g) * 8;
+        const size_t row = (size_t)(c * FKB + k);
+        char *dst = buf + m * 8192 + wave * 1024;
+        __builtin_amdgcn_global_load_lds((const void *)(t.xh + row * t.ldx + tu0 + col), (lds_void *)dst, 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((const void *)(t.yh + row * t.ldy + tp0 + col), (lds_void *)(dst + 2 * FARR),
+                                         16, 0, 0);
+        if (X3) {
+            __builtin_amdgcn_global_load_lds((const void *)(t.xl + row * t.ldx + tu0 + col), (lds_void *)(dst + FARR),
+                                             16, 0, 0);
+            __builtin_amdgcn_global_load_lds((const void *)(t.yl + row * t.ldy + tp0 + col),
+                                             (lds_void *)(dst + 3 * FARR), 16, 0, 0);
+        }
+    }
+}
+
+// Forward from stored tables: all 8 waves contract the current chunk while the next one streams
+// into the other LDS buffer.  One-dimensional grid: the tiles of one K split go to the same XCD,
+// where they run at about the same time and share its L2 copy of the split's table rows.
+template <bool X3>
+__global__ __launch_bounds__(512) void k_fwd_bf16_st(int Mu, int Mp, StoreTables t, float *__restrict__ part,
+                                                     int tiles_u, int tiles_p, int splits, int64_t chunks,
+                                                     int64_t chunks_per_split) {
+    __shared__ __attribute__((aligned(16))) char smem[2 * FBUF];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tiles = tiles_u * tiles_p;
+    const int w = blockIdx.x, xcd = w & 7, slot = w >> 3;
+    const int split = xcd + 8 * (slot / tiles), tile = slot % tiles;
+    if (split >= splits) return;
+    const int tu0 = (tile / tiles_p) * FT, tp0 = (tile % tiles_p) * FT;
+    const int wu = 128 * (wave >> 2), wp = 64 * (wave & 3);
+    const int64_t c_begin = (int64_t)split * chunks_per_split;
+    const int64_t c_end = min(chunks, c_begin + chunks_per_split);
+
+    f32x16 acc[4][2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+    OpBase ox, oy;
+    ox.init(wu, lane);
+    oy.init(wp, lane);
+
+    if (c_begin < c_end) {
+        fwd_copy<X3>(t, c_begin, tu0, tp0, smem, tid);
+        wait_copies();
+    }
+    __syncthreads();
+    for (int64_t c = c_begin; c < c_end; ++c) {
+        const int bsel = (int)((c - c_begin) & 1);
+        char *cur = smem + bsel * FBUF, *nxt = smem + (bsel ^ 1) * FBUF;
+        if (c + 1 < c_end) fwd_copy<X3>(t, c + 1, tu0, tp0, nxt, tid);
+        fwd_mma<X3>(cur, ox, oy, acc);
+        wait_copies();
+        __syncthreads();
+    }
+
+    float *out = part + (size_t)split * (size_t)Mu * (size_t)Mp;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int u = tu0 + wu + 32 * a + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int p = tp0 + wp + 32 * b + (lane & 31);
+                if (u < Mu && p < Mp) out[(size_t)u * Mp + p] = acc[a][b][r];
+            }
+}
+
 }  // namespace
 
 hipError_t launch_phase_tables(int64_t n, const double *x, const double *y, const double *w, const double *h,
@@ -622,9 +815,50 @@ hipError_t launch_prep_bwd_bf16(const double *a, int Mu, int Mp, double W, doubl
 size_t bwd_bf16_operand_elems(int Np, int Kh) { return (size_t)(Np / BTN) * (size_t)(Kh / 32) * (size_t)(BBUF / 2); }
 
 hipError_t launch_bwd_bf16(bool x3, int64_t n, const BwdAxisBf16 &ax, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    if (ax.tab_h) {
+        // store mode: one-dimensional XCD-aware grid over (block tile, N tile)
+        if (ax.tiles_b != (int)((n + 255) / 256) || ax.tiles_n != (ax.Nb + BTN - 1) / BTN || ax.tab_ld < 2 * ax.Kh ||
+            (x3 && !ax.tab_l))
+            return hipErrorInvalidValue;
+        const unsigned g = (unsigned)((ax.tiles_b + 7) / 8 * 8 * ax.tiles_n);
+        if (x3) hipLaunchKernelGGL((k_bwd_bf16<true, true>), dim3(g), dim3(512), 0, s, n, ax);
+        else hipLaunchKernelGGL((k_bwd_bf16<false, true>), dim3(g), dim3(512), 0, s, n, ax);
+        return hipGetLastError();
+    }
     dim3 grid((unsigned)((n + 255) / 256), (unsigned)((ax.Nb + BTN - 1) / BTN));
-    if (x3) hipLaunchKernelGGL(k_bwd_bf16<true>, grid, dim3(512), 0, s, n, ax);
-    else hipLaunchKernelGGL(k_bwd_bf16<false>, grid, dim3(512), 0, s, n, ax);
+    if (x3) hipLaunchKernelGGL((k_bwd_bf16<true, false>), grid, dim3(512), 0, s, n, ax);
+    else hipLaunchKernelGGL((k_bwd_bf16<false, false>), grid, dim3(512), 0, s, n, ax);
+    return hipGetLastError();
+}
+
+int64_t store_rows(int64_t n) { return (n + 255) / 256 * 256; }
+int store_ld(int M) { return (M + 255) / 256 * 256; }
+
+hipError_t launch_build_table(bool x3, int64_t n, int M, const PhaseRec *tab, unsigned short *th, unsigned short *tl,
+                              hipStream_t s) {
+    const int64_t rows = store_rows(n);
+    const int ld = store_ld(M);
+    const int64_t total = rows * (ld / 32);
+    if (total == 0) return hipSuccess;
+    const unsigned g = (unsigned)((total + 255) / 256);
+    if (x3) hipLaunchKernelGGL(k_build_table<true>, dim3(g), dim3(256), 0, s, n, rows, ld, tab, th, tl);
+    else hipLaunchKernelGGL(k_build_table<false>, dim3(g), dim3(256), 0, s, n, rows, ld, tab, th, tl);
+    return hipGetLastError();
+}
+
+hipError_t launch_fwd_bf16_st(const FwdPlan &pl, bool x3, int64_t n, int Mu, int Mp, const StoreTables &t,
+                              float *part, hipStream_t s) {
+    if (pl.tu != FT || pl.tp != FT || pl.kb != FKB) return hipErrorInvalidValue;
+    if (t.ldx != store_ld(Mu) || t.ldy != store_ld(Mp) || pl.chunks * FKB > store_rows(n)) return hipErrorInvalidValue;
+    const int tiles = pl.tiles_u * pl.tiles_p;
+    const unsigned g = (unsigned)(tiles * ((pl.splits + 7) / 8 * 8));
+    if (x3)
+        hipLaunchKernelGGL(k_fwd_bf16_st<true>, dim3(g), dim3(512), 0, s, Mu, Mp, t, part, pl.tiles_u, pl.tiles_p,
+                           pl.splits, pl.chunks, pl.chunks_per_split);
+    else
+        hipLaunchKernelGGL(k_fwd_bf16_st<false>, dim3(g), dim3(512), 0, s, Mu, Mp, t, part, pl.tiles_u, pl.tiles_p,
+                           pl.splits, pl.chunks, pl.chunks_per_split);
     return hipGetLastError();
 }
 

@@ -133,8 +133,14 @@ def test_evaluation_entry_points_validate_before_launch(lib):
 def test_unsupported_modes_reported(lib):
     st, _ = ws_size(lib, P(precision=4))
     assert st == -3
-    st, _ = ws_size(lib, P(basis_mode=1))
-    assert st == -3
+    for prec in (0, 1):                  # stored tables exist for the bf16 operand types only
+        st, _ = ws_size(lib, P(precision=prec, basis_mode=1))
+        assert st == -3
+    st, rec = ws_size(lib, P(precision=3, basis_mode=0, n=5000))
+    st2, sto = ws_size(lib, P(precision=3, basis_mode=1, n=5000))
+    # store adds the x3 tables: 4 bytes per (row, frequency) of each axis, rows and frequencies
+    # rounded up to 256
+    assert st == 0 and st2 == 0 and sto >= rec + 4 * 5120 * (256 + 256)
 
 
 def test_python_binding_fails_loudly_without_gpu_tensors(lib):
