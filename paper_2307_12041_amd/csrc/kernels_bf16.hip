@@ -63,13 +63,28 @@ __device__ __forceinline__ unsigned pack_bf16(float a, float b) {
     return __builtin_bit_cast(unsigned, v);
 }
 
+// The bf16 pairs (-1, 0) and (0, -1), held in VGPRs (opaque to the compiler, which would otherwise
+// encode them as inline constants of the dot product; that encoding gave wrong results when
+// checked on the device against the shift-and-subtract split).
+struct SplitK {
+    bf16x2 m0, m1;
+};
+__device__ __forceinline__ SplitK split_consts() {
+    unsigned c0 = 0x0000bf80u, c1 = 0xbf800000u;
+    asm volatile("" : "+v"(c0));
+    asm volatile("" : "+v"(c1));
+    return SplitK{__builtin_bit_cast(bf16x2, c0), __builtin_bit_cast(bf16x2, c1)};
+}
+
 // Split two fp32 values into packed bf16 hi (round to nearest even) and packed bf16 lo of the
-// remainders.
-__device__ __forceinline__ void split2(float a, float b, unsigned &hi, unsigned &lo) {
+// remainders.  a - hi_a is exactly representable in fp32, so the bf16 dot product
+// a + (-1) hi_a + 0 hi_b (v_dot2c_f32_bf16) returns it exactly, in one instruction per value.
+__device__ __forceinline__ void split2(float a, float b, unsigned &hi, unsigned &lo, const SplitK &k) {
     hi = pack_bf16(a, b);
-    const float ha = __builtin_bit_cast(float, hi << 16);
-    const float hb = __builtin_bit_cast(float, hi & 0xffff0000u);
-    lo = pack_bf16(a - ha, b - hb);
+    const bf16x2 h = __builtin_bit_cast(bf16x2, hi);
+    const float la = __builtin_amdgcn_fdot2_f32_bf16(h, k.m0, a, false);
+    const float lb = __builtin_amdgcn_fdot2_f32_bf16(h, k.m1, b, false);
+    lo = pack_bf16(la, lb);
 }
 
 // Three-term recurrence state for cos(k alpha) (or any sinusoid) with a hi/lo coefficient.
@@ -127,15 +142,16 @@ constexpr int FROW = FT * 2;         // bytes per LDS row
 constexpr int FARR = FKB * FROW;     // bytes per array
 constexpr int FBUF = 4 * FARR;       // Xh, Xl, Yh, Yl
 
-// Byte offset of 16-byte segment `seg` of row `k` in an LDS tile.  The segment index is XORed with
-// g(k) = 2 (k % 4) + (k / 4) % 2, a permutation of 0..7 over any 8 consecutive rows whose halves
-// 2 (k % 4) differ within every aligned group of 4 rows.  The 64 lanes of a b128 store (8 rows x 8
-// runs) then spread evenly over all banks, and a 16-lane transpose read (4 rows x 32 bytes) hits
-// 8 distinct 16-byte bank groups.
-__device__ __forceinline__ int fswz(int k, int seg) {
-    const int g = ((k & 3) << 1) | ((k >> 2) & 1);
-    return k * FROW + ((seg ^ g) << 4);
-}
+// Byte offset of 16-byte segment `seg` of row `k` in an LDS tile.  The LDS has 64 banks of 4 bytes
+// (a 256-byte period, half a row), so a segment's bank group is its index mod 16.  The index is
+// XORed with M(k) = 4 (k % 4) + (k / 4) % 4, which swaps the two 2-bit halves of k % 16:
+//   * a b128 store by 16 lanes writes one segment of 16 consecutive rows (see fwd_gen), and M is a
+//     bijection on k % 16, so the 16 stores hit 16 distinct bank groups;
+//   * a 32-lane half of a transpose read covers 4 consecutive rows k0 .. k0 + 3 (k0 % 4 = 0) and 4
+//     consecutive segments of an aligned group of 4; M(k) / 4 = k % 4 moves each row's 4 segments
+//     to a different aligned group, so the 16 segments hit 16 distinct bank groups.
+__device__ __forceinline__ int fswz_mask(int k) { return ((k & 3) << 2) | ((k >> 2) & 3); }
+__device__ __forceinline__ int fswz(int k, int seg) { return k * FROW + ((seg ^ fswz_mask(k)) << 4); }
 
 // The fields of a phase record that a generating thread needs, held in registers so that the
 // record can be fetched one phase ahead of its use.
@@ -184,9 +200,11 @@ __device__ __forceinline__ void gen32(const GenRec &R, int u0, float (&v)[32]) {
 }
 
 // 32 consecutive frequencies f0 + 32 r .. + 31 of block k of the chunk, split hi/lo and stored.
+// Thread gt of the generating group handles block k = gt % 32 and run r = gt / 32, so the 16 lanes
+// of each store share the segment and cover 16 consecutive rows.
 template <bool X3>
-__device__ __forceinline__ void fwd_gen(const GenRec &R, int f0, char *arr_h, char *arr_l, int gt) {
-    const int k = gt >> 3, r = gt & 7;
+__device__ __forceinline__ void fwd_gen(const GenRec &R, int f0, char *arr_h, char *arr_l, int gt, const SplitK &sk) {
+    const int k = gt & 31, r = gt >> 5;
     const int u0 = f0 + 32 * r;
     Cheb ca, sb;
     float c0, s0, cb0, sb0;
@@ -209,7 +227,7 @@ __device__ __forceinline__ void fwd_gen(const GenRec &R, int f0, char *arr_h, ch
         unsigned h[4], l[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            if (X3) split2(v[8 * m + 2 * e], v[8 * m + 2 * e + 1], h[e], l[e]);
+            if (X3) split2(v[8 * m + 2 * e], v[8 * m + 2 * e + 1], h[e], l[e], sk);
             else h[e] = pack_bf16(v[8 * m + 2 * e], v[8 * m + 2 * e + 1]);
         }
         *(u32x4 *)(arr_h + fswz(k, 4 * r + m)) = u32x4{h[0], h[1], h[2], h[3]};
@@ -219,32 +237,30 @@ __device__ __forceinline__ void fwd_gen(const GenRec &R, int f0, char *arr_h, ch
 
 // Lane-dependent byte offsets for the transpose reads of one wave's operands.  An operand covers
 // frequencies f_base + 32 a .. + 31 (a = subtile) and blocks 16 ks .. + 15; lane (q = lane / 16,
-// i = lane % 16) reads 8 bytes at row r = 8 (q / 2) + i / 4 (+4 for the second read, +16 ks) and
-// frequency f = f_base + 32 a + 16 (q % 2) + 4 (i % 4).  Because g(r + 4) = g(r) ^ 1 and rows + 16
-// keep g, the swizzled offset is one of four bases (subtile parity x read half) plus
-// 64 (a - a % 2) + 8192 ks.
+// i = lane % 16) reads 8 bytes at row r = 8 (q / 2) + i / 4 + 4 rd (rd = read half, + 16 ks) and
+// frequency f = f_base + 32 a + 16 (q % 2) + 4 (i % 4).  M(r + 16) = M(r), so one base per
+// (subtile, read half) serves both K steps (+ 8192 bytes).
 struct OpBase {
-    int b[2][2];   // [subtile parity][read half]
+    int b[4][2];   // [subtile][read half]
     __device__ __forceinline__ void init(int f_base, int lane) {
         const int q = lane >> 4, i = lane & 15;
-        const int r0 = 8 * (q >> 1) + (i >> 2);
-        const int col = f_base + 16 * (q & 1) + 4 * (i & 3);
-        const int s0 = col >> 3, within = (col & 7) * 2;
-        const int g0 = ((r0 & 3) << 1) | ((r0 >> 2) & 1);
 #pragma unroll
-        for (int par = 0; par < 2; ++par)
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int rd = 0; rd < 2; ++rd)
-                b[par][rd] = (r0 + 4 * rd) * FROW + (((s0 + 4 * par) ^ (g0 ^ rd)) << 4) + within;
+            for (int rd = 0; rd < 2; ++rd) {
+                const int row = 8 * (q >> 1) + (i >> 2) + 4 * rd;
+                const int col = f_base + 32 * a + 16 * (q & 1) + 4 * (i & 3);
+                b[a][rd] = fswz(row, col >> 3) + (col & 7) * 2;
+            }
     }
 };
 
 // One 32 x 16 MFMA operand from an LDS [block][frequency] array: two transpose reads.
 __device__ __forceinline__ bf16x8 load_opT(const char *arr, const OpBase &ob, int a, int ks) {
     typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
-    const int off = 64 * (a & ~1) + 8192 * ks;
-    const s16x4 x = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4 *)(arr + ob.b[a & 1][0] + off));
-    const s16x4 y = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4 *)(arr + ob.b[a & 1][1] + off));
+    const int off = 8192 * ks;
+    const s16x4 x = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4 *)(arr + ob.b[a][0] + off));
+    const s16x4 y = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4 *)(arr + ob.b[a][1] + off));
     typedef short s16x8 __attribute__((ext_vector_type(8)));
     const s16x8 c = {x[0], x[1], x[2], x[3], y[0], y[1], y[2], y[3]};
     return __builtin_bit_cast(bf16x8, c);
@@ -292,16 +308,48 @@ __device__ __forceinline__ void fwd_mfma(const FwdOps &o, f32x16 (&acc)[4][2]) {
     }
 }
 
-// Both K steps of a chunk; the second step's operand reads are issued before the first step's
-// MFMAs so their LDS latency hides behind the matrix work.
+// Both K steps of a chunk.  The operand reads are issued in the order of first use (hi of B, hi of
+// A, lo of B, lo of A; step 0, then step 1), the first four operands ahead of the first MFMA and one
+// more after each of the next 20 MFMAs, so that every MFMA waits only for its own operands and the
+// LDS latency of the later reads hides behind the matrix work.  (Issuing all reads first would make
+// the first MFMA wait for most of them: the LDS counter that guards them counts at most 15.)
 template <bool X3>
 __device__ __forceinline__ void fwd_mma(const char *buf, const OpBase &ox, const OpBase &oy, f32x16 (&acc)[4][2]) {
     static_assert(FKB == 32 && FROW * 16 == 8192, "two K steps per chunk, 16 rows per step");
-    FwdOps o0, o1;
-    fwd_load<X3>(buf, ox, oy, 0, o0);
-    fwd_load<X3>(buf, ox, oy, 1, o1);
-    fwd_mfma<X3>(o0, acc);
-    fwd_mfma<X3>(o1, acc);
+    const char *xh = buf, *xl = buf + FARR, *yh = buf + 2 * FARR, *yl = buf + 3 * FARR;
+    FwdOps o[2];
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b) o[ks].bh[b] = load_opT(yh, oy, b, ks);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) o[ks].ah[a] = load_opT(xh, ox, a, ks);
+        if (X3) {
+#pragma unroll
+            for (int b = 0; b < 2; ++b) o[ks].bl[b] = load_opT(yl, oy, b, ks);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) o[ks].al[a] = load_opT(xl, ox, a, ks);
+        }
+    }
+    fwd_mfma<X3>(o[0], acc);
+    fwd_mfma<X3>(o[1], acc);
+    if (X3) {
+        __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+#pragma unroll
+        for (int i = 0; i < 20; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, 28, 0);
+    } else {
+        __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+    }
 }
 
 template <bool X3>
@@ -327,15 +375,16 @@ __global__ __launch_bounds__(512) void k_fwd_bf16(int64_t n, int Mu, int Mp, con
     ox.init(wu, lane);
     oy.init(wp, lane);
 
+    const SplitK sk = split_consts();
     // Group 0 generates the X tile (u), group 1 the Y tile (p).
     const PhaseRec *tab = group == 0 ? tx : ty;
     const int f0 = group == 0 ? tu0 : tp0;
     const int aoff = group == 0 ? 0 : 2 * FARR;
-    const int kk = gt >> 3;
+    const int kk = gt & 31;
     GenRec rec;
     if (c_begin < c_end) {
         rec = load_rec(tab, n, c_begin, kk);
-        fwd_gen<X3>(rec, f0, smem + aoff, smem + aoff + FARR, gt);
+        fwd_gen<X3>(rec, f0, smem + aoff, smem + aoff + FARR, gt, sk);
         if (group == 1 && c_begin + 1 < c_end) rec = load_rec(tab, n, c_begin + 1, kk);
     }
     __syncthreads();
@@ -343,14 +392,23 @@ __global__ __launch_bounds__(512) void k_fwd_bf16(int64_t n, int Mu, int Mp, con
         const int bsel = (int)((c - c_begin) & 1);
         char *cur = smem + bsel * FBUF, *nxt = smem + (bsel ^ 1) * FBUF;
         const bool more = c + 1 < c_end;
+        // Two phases per chunk, separated by a barrier so that the waves of a SIMD stay in
+        // opposite roles: while one contracts, the other generates.  (Without the middle barrier
+        // the contracting wave, which only issues its MFMAs, runs ahead into its own generation
+        // phase while the other still generates; the two generators then share the VALU and the
+        // second contraction runs alone.)
         if (group == 0) {
-            // fetch the next chunk's records before the MFMAs; generate after them
+            // fetch the next chunk's records before the MFMAs; they are used in phase 2
             if (more) rec = load_rec(tab, n, c + 1, kk);
             fwd_mma<X3>(cur, ox, oy, acc);
-            if (more) fwd_gen<X3>(rec, f0, nxt + aoff, nxt + aoff + FARR, gt);
         } else {
-            // generate first; fetch the records of the chunk after next before the MFMAs
-            if (more) fwd_gen<X3>(rec, f0, nxt + aoff, nxt + aoff + FARR, gt);
+            if (more) fwd_gen<X3>(rec, f0, nxt + aoff, nxt + aoff + FARR, gt, sk);
+        }
+        __syncthreads();
+        if (group == 0) {
+            if (more) fwd_gen<X3>(rec, f0, nxt + aoff, nxt + aoff + FARR, gt, sk);
+        } else {
+            // fetch the records of the chunk after next before the MFMAs
             if (c + 2 < c_end) rec = load_rec(tab, n, c + 2, kk);
             fwd_mma<X3>(cur, ox, oy, acc);
         }
@@ -468,6 +526,7 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
         for (int r = 0; r < 16; ++r) acc[b][r] = 0.0f;
 
     const size_t tile_elems = (size_t)BBUF / 2;      // bf16 elements per chunk tile (hi + lo)
+    const SplitK sk = split_consts();
     const unsigned short *gb = ax.B + (size_t)ntile * Q * tile_elems;
 
     // A operand of one K step (8 consecutive frequencies of this lane's block), split hi/lo.  Branch
@@ -483,7 +542,7 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
         unsigned hh[4], ll[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-            if (X3) split2(v[2 * m], v[2 * m + 1], hh[m], ll[m]);
+            if (X3) split2(v[2 * m], v[2 * m + 1], hh[m], ll[m], sk);
             else hh[m] = pack_bf16(v[2 * m], v[2 * m + 1]);
         }
         ah = __builtin_bit_cast(bf16x8, u32x4{hh[0], hh[1], hh[2], hh[3]});
@@ -680,6 +739,7 @@ __global__ __launch_bounds__(256) void k_build_table(int64_t n, int64_t nrows, i
     const int64_t ib = idx / runs;
     const int r = (int)(idx % runs);
     const GenRec R = load_rec_at(tab, n, ib);
+    const SplitK sk = split_consts();
     float v[32];
     gen32(R, 32 * r, v);
     unsigned short *dh = th + (size_t)ib * (size_t)ld + 32 * r;
@@ -689,7 +749,7 @@ __global__ __launch_bounds__(256) void k_build_table(int64_t n, int64_t nrows, i
         unsigned hh[4], ll[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            if (X3) split2(v[8 * m + 2 * e], v[8 * m + 2 * e + 1], hh[e], ll[e]);
+            if (X3) split2(v[8 * m + 2 * e], v[8 * m + 2 * e + 1], hh[e], ll[e], sk);
             else hh[e] = pack_bf16(v[8 * m + 2 * e], v[8 * m + 2 * e + 1]);
         }
         *(u32x4 *)(dh + 8 * m) = u32x4{hh[0], hh[1], hh[2], hh[3]};
@@ -699,7 +759,7 @@ __global__ __launch_bounds__(256) void k_build_table(int64_t n, int64_t nrows, i
 
 // Direct copies of one chunk's four LDS tiles (Xh, Xl, Yh, Yl of 32 blocks x 256 frequencies):
 // LDS byte o of a tile holds row k = o / 512, physical segment o / 16 % 32, i.e. logical segment
-// (o / 16 % 32) ^ g(k) of the same row (the swizzle of fswz is an involution).
+// (o / 16 % 32) ^ M(k) of the same row (the swizzle of fswz is an involution).
 template <bool X3>
 __device__ __forceinline__ void fwd_copy(const StoreTables &t, int64_t c, int tu0, int tp0, char *buf, int tid) {
     typedef __attribute__((address_space(3))) void lds_void;
@@ -708,8 +768,7 @@ __device__ __forceinline__ void fwd_copy(const StoreTables &t, int64_t c, int tu
     for (int m = 0; m < 2; ++m) {
         const int o = m * 8192 + wave * 1024 + lane * 16;
         const int k = o >> 9, ps = (o >> 4) & 31;
-        const int g = ((k & 3) << 1) | ((k >> 2) & 1);
-        const int col = (ps ^ g) * 8;
+        const int col = (ps ^ fswz_mask(k)) * 8;
         const size_t row = (size_t)(c * FKB + k);
         char *dst = buf + m * 8192 + wave * 1024;
         __builtin_amdgcn_global_load_lds((const void *)(t.xh + row * t.ldx + tu0 + col), (lds_void *)dst, 16, 0, 0);
