@@ -63,28 +63,15 @@ __device__ __forceinline__ unsigned pack_bf16(float a, float b) {
     return __builtin_bit_cast(unsigned, v);
 }
 
-// The bf16 pairs (-1, 0) and (0, -1), held in VGPRs (opaque to the compiler, which would otherwise
-// encode them as inline constants of the dot product; that encoding gave wrong results when
-// checked on the device against the shift-and-subtract split).
-struct SplitK {
-    bf16x2 m0, m1;
-};
-__device__ __forceinline__ SplitK split_consts() {
-    unsigned c0 = 0x0000bf80u, c1 = 0xbf800000u;
-    asm volatile("" : "+v"(c0));
-    asm volatile("" : "+v"(c1));
-    return SplitK{__builtin_bit_cast(bf16x2, c0), __builtin_bit_cast(bf16x2, c1)};
-}
-
 // Split two fp32 values into packed bf16 hi (round to nearest even) and packed bf16 lo of the
-// remainders.  a - hi_a is exactly representable in fp32, so the bf16 dot product
-// a + (-1) hi_a + 0 hi_b (v_dot2c_f32_bf16) returns it exactly, in one instruction per value.
-__device__ __forceinline__ void split2(float a, float b, unsigned &hi, unsigned &lo, const SplitK &k) {
+// remainders (exact in fp32).  Plain VALU shifts and subtractions: a bf16 dot-product form of the
+// remainder issues fewer instructions but shares the matrix pipe and stalls behind the MFMAs that
+// the other wave of the SIMD runs meanwhile (measured 4.8x slower there, against 1.6x for this).
+__device__ __forceinline__ void split2(float a, float b, unsigned &hi, unsigned &lo) {
     hi = pack_bf16(a, b);
-    const bf16x2 h = __builtin_bit_cast(bf16x2, hi);
-    const float la = __builtin_amdgcn_fdot2_f32_bf16(h, k.m0, a, false);
-    const float lb = __builtin_amdgcn_fdot2_f32_bf16(h, k.m1, b, false);
-    lo = pack_bf16(la, lb);
+    const float ha = __builtin_bit_cast(float, hi << 16);
+    const float hb = __builtin_bit_cast(float, hi & 0xffff0000u);
+    lo = pack_bf16(a - ha, b - hb);
 }
 
 // Three-term recurrence state for cos(k alpha) (or any sinusoid) with a hi/lo coefficient.
@@ -203,7 +190,7 @@ __device__ __forceinline__ void gen32(const GenRec &R, int u0, float (&v)[32]) {
 // Thread gt of the generating group handles block k = gt % 32 and run r = gt / 32, so the 16 lanes
 // of each store share the segment and cover 16 consecutive rows.
 template <bool X3>
-__device__ __forceinline__ void fwd_gen(const GenRec &R, int f0, char *arr_h, char *arr_l, int gt, const SplitK &sk) {
+__device__ __forceinline__ void fwd_gen(const GenRec &R, int f0, char *arr_h, char *arr_l, int gt) {
     const int k = gt & 31, r = gt >> 5;
     const int u0 = f0 + 32 * r;
     Cheb ca, sb;
@@ -227,7 +214,7 @@ __device__ __forceinline__ void fwd_gen(const GenRec &R, int f0, char *arr_h, ch
         unsigned h[4], l[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            if (X3) split2(v[8 * m + 2 * e], v[8 * m + 2 * e + 1], h[e], l[e], sk);
+            if (X3) split2(v[8 * m + 2 * e], v[8 * m + 2 * e + 1], h[e], l[e]);
             else h[e] = pack_bf16(v[8 * m + 2 * e], v[8 * m + 2 * e + 1]);
         }
         *(u32x4 *)(arr_h + fswz(k, 4 * r + m)) = u32x4{h[0], h[1], h[2], h[3]};
@@ -375,7 +362,6 @@ __global__ __launch_bounds__(512) void k_fwd_bf16(int64_t n, int Mu, int Mp, con
     ox.init(wu, lane);
     oy.init(wp, lane);
 
-    const SplitK sk = split_consts();
     // Group 0 generates the X tile (u), group 1 the Y tile (p).
     const PhaseRec *tab = group == 0 ? tx : ty;
     const int f0 = group == 0 ? tu0 : tp0;
@@ -384,7 +370,7 @@ __global__ __launch_bounds__(512) void k_fwd_bf16(int64_t n, int Mu, int Mp, con
     GenRec rec;
     if (c_begin < c_end) {
         rec = load_rec(tab, n, c_begin, kk);
-        fwd_gen<X3>(rec, f0, smem + aoff, smem + aoff + FARR, gt, sk);
+        fwd_gen<X3>(rec, f0, smem + aoff, smem + aoff + FARR, gt);
         if (group == 1 && c_begin + 1 < c_end) rec = load_rec(tab, n, c_begin + 1, kk);
     }
     __syncthreads();
@@ -402,11 +388,11 @@ __global__ __launch_bounds__(512) void k_fwd_bf16(int64_t n, int Mu, int Mp, con
             if (more) rec = load_rec(tab, n, c + 1, kk);
             fwd_mma<X3>(cur, ox, oy, acc);
         } else {
-            if (more) fwd_gen<X3>(rec, f0, nxt + aoff, nxt + aoff + FARR, gt, sk);
+            if (more) fwd_gen<X3>(rec, f0, nxt + aoff, nxt + aoff + FARR, gt);
         }
         __syncthreads();
         if (group == 0) {
-            if (more) fwd_gen<X3>(rec, f0, nxt + aoff, nxt + aoff + FARR, gt, sk);
+            if (more) fwd_gen<X3>(rec, f0, nxt + aoff, nxt + aoff + FARR, gt);
         } else {
             // fetch the records of the chunk after next before the MFMAs
             if (c + 2 < c_end) rec = load_rec(tab, n, c + 2, kk);
@@ -526,11 +512,9 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
         for (int r = 0; r < 16; ++r) acc[b][r] = 0.0f;
 
     const size_t tile_elems = (size_t)BBUF / 2;      // bf16 elements per chunk tile (hi + lo)
-    const SplitK sk = split_consts();
     const unsigned short *gb = ax.B + (size_t)ntile * Q * tile_elems;
 
-    // A operand of one K step (8 consecutive frequencies of this lane's block), split hi/lo.  Branch
-    // free, so that it can be scheduled between the MFMAs of the previous step.
+    // A operand of one K step (8 consecutive frequencies of this lane's block), split hi/lo.
     auto gen_a = [&](bf16x8 &ah, bf16x8 &al) {
         float v[8];
         v[0] = ca.f * sb.f;
@@ -542,7 +526,7 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
         unsigned hh[4], ll[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-            if (X3) split2(v[2 * m], v[2 * m + 1], hh[m], ll[m], sk);
+            if (X3) split2(v[2 * m], v[2 * m + 1], hh[m], ll[m]);
             else hh[m] = pack_bf16(v[2 * m], v[2 * m + 1]);
         }
         ah = __builtin_bit_cast(bf16x8, u32x4{hh[0], hh[1], hh[2], hh[3]});
@@ -550,9 +534,8 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
     };
 
     // One K step: B operands (row 32 b + j, logical segment 4 h + s, physical segment XORed with
-    // (j / 2) % 8) and the three MFMA passes over the 8 accumulators, with the next step's A operand
-    // generated in between (software pipelining inside the wave).
-    auto step = [&](const char *cur, int s, const bf16x8 &ah, const bf16x8 &al, bf16x8 &nah, bf16x8 &nal) {
+    // (j / 2) % 8) and the three MFMA passes over the 8 accumulators.
+    auto mma_step = [&](const char *cur, int s, const bf16x8 &ah, const bf16x8 &al) {
         const int bseg = ((4 * h + s) ^ ((j >> 1) & 7)) * 16;
         bf16x8 bh[8], bl[8];
 #pragma unroll
@@ -561,7 +544,6 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
 #pragma unroll
             for (int b = 0; b < 8; ++b) bl[b] = *(const bf16x8 *)(cur + BARR + (32 * b + j) * BROW + bseg);
         }
-        if constexpr (!ST) gen_a(nah, nal);
 #pragma unroll
         for (int b = 0; b < 8; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[b], acc[b], 0, 0, 0);
         if (X3) {
@@ -569,15 +551,6 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
             for (int b = 0; b < 8; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[b], acc[b], 0, 0, 0);
 #pragma unroll
             for (int b = 0; b < 8; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[b], acc[b], 0, 0, 0);
-        }
-        if constexpr (!ST) {
-            // Schedule: the B reads first, then each MFMA followed by a few VALU ops of the generator.
-            __builtin_amdgcn_sched_group_barrier(0x100, X3 ? 16 : 8, 0);
-#pragma unroll
-            for (int i = 0; i < (X3 ? 24 : 8); ++i) {
-                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                __builtin_amdgcn_sched_group_barrier(0x002, X3 ? 3 : 8, 0);
-            }
         }
     };
 
@@ -605,9 +578,8 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
                 load_a(q + 1, nah, nal);
                 bwd_copy_b(gb + (size_t)(q + 1) * tile_elems, nxt, tid);
             }
-            bf16x8 dummy_h, dummy_l;
 #pragma unroll
-            for (int st = 0; st < 4; ++st) step(cur, st, cah[st], cal[st], dummy_h, dummy_l);
+            for (int st = 0; st < 4; ++st) mma_step(cur, st, cah[st], cal[st]);
             wait_copies();
             __syncthreads();
 #pragma unroll
@@ -617,24 +589,44 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
             }
         }
     } else {
-    bf16x8 ah0, al0, ah1, al1;
-    gen_a(ah0, al0);                  // A of the first step
-    bwd_copy_b(gb, smem, tid);
-    wait_copies();
-    __syncthreads();
-    for (int q = 0; q < Q; ++q) {
-        char *cur = smem + (q & 1) * BBUF, *nxt = smem + ((q & 1) ^ 1) * BBUF;
-        if (q + 1 < Q) bwd_copy_b(gb + (size_t)(q + 1) * tile_elems, nxt, tid);
-        step(cur, 0, ah0, al0, ah1, al1);
-        step(cur, 1, ah1, al1, ah0, al0);
-        step(cur, 2, ah0, al0, ah1, al1);
-        // The next step is the first of the next chunk: 32 frequencies later, reseed first.
-        jump();
-        reseed();
-        step(cur, 3, ah1, al1, ah0, al0);
+        // Two wave groups in opposite roles, two phases per chunk separated by barriers: while the
+        // waves of one group contract (A in registers, B from LDS), the waves of the other generate
+        // their A operands for the chunk they contract next, so on every SIMD one wave issues
+        // MFMAs while the other issues the generator's VALU work.  Group 0 (waves 0-3) contracts
+        // chunk q in phase 1 and generates chunk q + 1 in phase 2; group 1 generates chunk q in
+        // phase 1 and contracts it in phase 2.
+        const int group = wave >> 2;
+        bf16x8 Ah[4], Al[4];
+        auto gen_chunk = [&]() {
+#pragma unroll
+            for (int st = 0; st < 4; ++st) gen_a(Ah[st], Al[st]);
+            // the next chunk starts 32 frequencies later: advance the phasors, reseed
+            jump();
+            reseed();
+        };
+        if (group == 0) gen_chunk();
+        bwd_copy_b(gb, smem, tid);
         wait_copies();
         __syncthreads();
-    }
+        for (int q = 0; q < Q; ++q) {
+            char *cur = smem + (q & 1) * BBUF, *nxt = smem + ((q & 1) ^ 1) * BBUF;
+            if (q + 1 < Q) bwd_copy_b(gb + (size_t)(q + 1) * tile_elems, nxt, tid);
+            if (group == 0) {
+#pragma unroll
+                for (int st = 0; st < 4; ++st) mma_step(cur, st, Ah[st], Al[st]);
+            } else {
+                gen_chunk();
+            }
+            __syncthreads();
+            if (group == 0) {
+                if (q + 1 < Q) gen_chunk();
+            } else {
+#pragma unroll
+                for (int st = 0; st < 4; ++st) mma_step(cur, st, Ah[st], Al[st]);
+            }
+            wait_copies();
+            __syncthreads();
+        }
     }
 
     // Epilogue: lane holds G for rows 8 (r / 4) + 4 h + r % 4 and columns n0 + 32 b + j.
@@ -739,7 +731,6 @@ __global__ __launch_bounds__(256) void k_build_table(int64_t n, int64_t nrows, i
     const int64_t ib = idx / runs;
     const int r = (int)(idx % runs);
     const GenRec R = load_rec_at(tab, n, ib);
-    const SplitK sk = split_consts();
     float v[32];
     gen32(R, 32 * r, v);
     unsigned short *dh = th + (size_t)ib * (size_t)ld + 32 * r;
@@ -749,7 +740,7 @@ __global__ __launch_bounds__(256) void k_build_table(int64_t n, int64_t nrows, i
         unsigned hh[4], ll[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            if (X3) split2(v[8 * m + 2 * e], v[8 * m + 2 * e + 1], hh[e], ll[e], sk);
+            if (X3) split2(v[8 * m + 2 * e], v[8 * m + 2 * e + 1], hh[e], ll[e]);
             else hh[e] = pack_bf16(v[8 * m + 2 * e], v[8 * m + 2 * e + 1]);
         }
         *(u32x4 *)(dh + 8 * m) = u32x4{hh[0], hh[1], hh[2], hh[3]};
