@@ -86,7 +86,7 @@ def timed_steps(pp, torch, t, wl, prec, steps, warmup, ws, positions=None, basis
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stages = {}
-    for st in ("tables", "build", "fwd", "reduce", "energy", "prep", "bwd", "final"):
+    for st in ("tables", "build", "fwd", "reduce", "energy", "prep", "bwd", "final", "point", "potential"):
         ms, cnt = pp.timing_query(st)
         if cnt:
             stages[st] = (ms, cnt)
@@ -106,6 +106,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--fp32-steps", type=int, default=2, help="steps of the FP32 path on the same workload (0: skip)")
+    ap.add_argument("--eval-precision", default="fp32", choices=["fp32", "fp64", "none"],
+                    help="time the evaluation calls (point field at the block centres, block potentials)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=12000, help="blocks in the oracle's timed sample")
@@ -212,6 +214,35 @@ def main():
                 "E": abs(float(E32) - float(E64)) / abs(float(E64)), "a": rel(a32, a64),
                 "g": rel(np.concatenate([gx32, gy32]), np.concatenate([gx64, gy64]))}
         out["speedup_vs_fp32"] = value / v32
+
+    if args.eval_precision != "none":
+        # The evaluation rows: psi and xi at every block centre (two contractions: psi and xi_x share
+        # one, xi_y is the other) and the block potentials N_i (one contraction), from the
+        # coefficients of the timed run; 1/2 sum_i N_i must equal the energy of those coefficients.
+        ep = args.eval_precision
+        wse = torch.empty(pp.workspace_size(wl.W, wl.H, wl.n, wl.Mu, wl.Mp, precision=ep), dtype=torch.uint8, device=dev)
+        pp.point_field(t[0], t[1], a, W=wl.W, H=wl.H, precision=ep, workspace=wse)
+        pp.block_potential(*t, a, W=wl.W, H=wl.H, precision=ep, workspace=wse)
+        torch.cuda.synchronize()
+        pp.timing_enable(True)
+        psi, xix, xiy = pp.point_field(t[0], t[1], a, W=wl.W, H=wl.H, precision=ep, workspace=wse)
+        N = pp.block_potential(*t, a, W=wl.W, H=wl.H, precision=ep, workspace=wse)
+        torch.cuda.synchronize()
+        tp, cp = pp.timing_query("point")
+        tn, cn = pp.timing_query("potential")
+        pp.timing_enable(False)
+        Ev = float(E.cpu())
+        ident = abs(0.5 * float(N.sum().cpu()) - Ev) / abs(Ev)
+        out["evaluation"] = {
+            "precision": ep,
+            "point_field_ms": tp, "point_field_contractions": cp,
+            "point_field_pairs_per_s": pairs / (tp * 1e-3),
+            "block_potential_ms": tn,
+            "block_potential_pairs_per_s": pairs / (tn * 1e-3),
+            "achieved_tflops_per_contraction": round(2.0 * pairs / ((tp + tn) / (cp + cn) * 1e-3) / 1e12, 2),
+            "half_sum_N_vs_E": ident}
+        log(f"[bench] evaluation ({ep}): point field {tp:.1f} ms ({cp} contractions), block potentials {tn:.1f} ms; "
+            f"|1/2 sum N - E| / E = {ident:.2e}")
 
     if not args.no_accuracy:
         import oracle
