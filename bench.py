@@ -106,7 +106,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--fp32-steps", type=int, default=2, help="steps of the FP32 path on the same workload (0: skip)")
-    ap.add_argument("--eval-precision", default="fp32", choices=["fp32", "fp64", "none"],
+    ap.add_argument("--eval-precision", default="bf16x3", choices=["bf16x3", "bf16", "fp32", "fp64", "none"],
                     help="time the evaluation calls (point field at the block centres, block potentials)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")

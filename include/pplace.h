@@ -125,8 +125,9 @@ int pp_field(const pp_problem *P, const double *x, const double *y, const double
  * Evaluation points may be the block centres or any other points (a grid for a picture of psi).
  * px, py: in [npts] FP64 device arrays.  a: in [Mu * Mp] FP64 coefficients (pp_coeffs).
  * psi, xix, xiy: out [npts] FP64, each may be NULL (not computed).
- * P->precision: PP_FP64 or PP_FP32 (operand type of the contractions; FP64 sums per point), others
- * give PP_ERR_UNSUPPORTED.  ws: at least pp_workspace_size(P) bytes, P->n = npts.
+ * P->precision: the operand type of the contractions (FP64, FP32, BF16 or BF16X3; FP64 sums per
+ * point); P->basis_mode must be PP_BASIS_RECOMPUTE (store gives PP_ERR_UNSUPPORTED).
+ * ws: at least pp_workspace_size(P) bytes, P->n = npts.
  * Errors as for pp_field. */
 int pp_point_field(const pp_problem *P, const double *px, const double *py, const double *a, double *psi,
                    double *xix, double *xiy, void *ws, size_t ws_bytes, void *stream);
@@ -135,7 +136,8 @@ int pp_point_field(const pp_problem *P, const double *px, const double *py, cons
  * density, so that E = 1/2 sum_i N_i): N_i = integral of psi over block i
  *   = sum_up a_up Xbar_iu Ybar_ip,  Xbar_iu the sine-difference integral of block i (w_i at u = 0).
  * x, y, w, h: in [n] FP64 blocks.  a: in [Mu * Mp] FP64 coefficients of the same problem.
- * N: out [n] FP64.  P->precision: PP_FP64 or PP_FP32, others give PP_ERR_UNSUPPORTED.
+ * N: out [n] FP64.  P->precision: FP64, FP32, BF16 or BF16X3; P->basis_mode must be
+ * PP_BASIS_RECOMPUTE (store gives PP_ERR_UNSUPPORTED).
  * Errors as for pp_field. */
 int pp_block_potential(const pp_problem *P, const double *x, const double *y, const double *w, const double *h,
                        const double *a, double *N, void *ws, size_t ws_bytes, void *stream);

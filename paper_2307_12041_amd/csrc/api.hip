@@ -91,7 +91,7 @@ struct Layout {
     size_t tx, ty;                       // bf16 path: per-block phase records
     size_t sxh, sxl, syh, syl;           // store mode: basis tables (kept from the forward to the backward)
     size_t part, epart;                  // forward region
-    size_t bx, by, gpx, gpy, gpz;        // backward region (gpz: FP64 / FP32 point field only)
+    size_t bx, by, gpx, gpy, gpz;        // backward region (gpz: second epilogue of the point field)
     size_t fwd_bytes, bwd_bytes, total;
 };
 
@@ -130,9 +130,7 @@ Layout layout(const pp_problem &P) {
     }
     L.gpx = off; off = align_up(off + (size_t)b.tiles_nx * (size_t)P.n * sizeof(double));
     L.gpy = off; off = align_up(off + (size_t)b.tiles_ny * (size_t)P.n * sizeof(double));
-    if (!is_bf16(P.precision)) {
-        L.gpz = off; off = align_up(off + (size_t)b.tiles_nx * (size_t)P.n * sizeof(double));
-    }
+    L.gpz = off; off = align_up(off + (size_t)b.tiles_nx * (size_t)P.n * sizeof(double));
     L.bwd_bytes = off;
     L.total = L.fwd_bytes > L.bwd_bytes ? L.fwd_bytes : L.bwd_bytes;
     return L;
@@ -214,8 +212,6 @@ hipError_t rowform(const pp_problem &P, RowForm f, const BwdPlan &b, const BwdAx
     return P.precision == PP_FP32 ? launch_rowform_f32(f, b, P.n, ax, s) : launch_rowform_f64(f, b, P.n, ax, s);
 }
 
-bool rowform_precision(int prec) { return prec == PP_FP64 || prec == PP_FP32; }
-
 }  // namespace
 }  // namespace pp
 
@@ -275,14 +271,16 @@ int pp_field(const pp_problem *P, const double *x, const double *y, const double
         { TimedLaunch t("tables", s); if (launch_phase_tables(P->n, x, y, w, h, P->W, P->H, tx, ty, s) != hipSuccess) return PP_ERR_DEVICE; }
         {
             TimedLaunch t("prep", s);
-            if (launch_prep_bwd_bf16(a, P->Mu, P->Mp, P->W, P->H, 0, b.tiles_nx * 256, khx, bxt, s) != hipSuccess)
+            if (launch_prep_bwd_bf16(ROW_FIELD, a, P->Mu, P->Mp, P->W, P->H, 0, b.tiles_nx * 256, khx, bxt, s) !=
+                hipSuccess)
                 return PP_ERR_DEVICE;
-            if (launch_prep_bwd_bf16(a, P->Mu, P->Mp, P->W, P->H, 1, b.tiles_ny * 256, khy, byt, s) != hipSuccess)
+            if (launch_prep_bwd_bf16(ROW_FIELD, a, P->Mu, P->Mp, P->W, P->H, 1, b.tiles_ny * 256, khy, byt, s) !=
+                hipSuccess)
                 return PP_ERR_DEVICE;
         }
         // gx: K = p (basis of y), epilogue over u (x);  gy: K = u (basis of x), epilogue over p (y).
-        BwdAxisBf16 axx{ty, tx, P->Mp, P->Mu, khx, bxt, gpx, nullptr, nullptr, 0, 0, 0};
-        BwdAxisBf16 axy{tx, ty, P->Mu, P->Mp, khy, byt, gpy, nullptr, nullptr, 0, 0, 0};
+        BwdAxisBf16 axx{ty, tx, P->Mp, P->Mu, khx, bxt, gpx, nullptr, nullptr, 0, 0, 0, nullptr, 0.0f};
+        BwdAxisBf16 axy{tx, ty, P->Mu, P->Mp, khy, byt, gpy, nullptr, nullptr, 0, 0, 0, nullptr, 0.0f};
         if (P->basis_mode == PP_BASIS_STORE) {
             // the tables that pp_coeffs / pp_energy left in the workspace
             const StoreTables st = store_tables(*P, L, base);
@@ -292,8 +290,8 @@ int pp_field(const pp_problem *P, const double *x, const double *y, const double
             axy.tab_h = st.xh; axy.tab_l = st.xl; axy.tab_ld = st.ldx;
             axy.tiles_b = tb; axy.tiles_n = (P->Mp + 255) / 256;
         }
-        { TimedLaunch t("bwd", s); if (launch_bwd_bf16(x3, P->n, axx, s) != hipSuccess) return PP_ERR_DEVICE; }
-        { TimedLaunch t("bwd", s); if (launch_bwd_bf16(x3, P->n, axy, s) != hipSuccess) return PP_ERR_DEVICE; }
+        { TimedLaunch t("bwd", s); if (launch_bwd_bf16(ROW_FIELD, x3, P->n, axx, s) != hipSuccess) return PP_ERR_DEVICE; }
+        { TimedLaunch t("bwd", s); if (launch_bwd_bf16(ROW_FIELD, x3, P->n, axy, s) != hipSuccess) return PP_ERR_DEVICE; }
         { TimedLaunch t("final", s); if (launch_bwd_final(gpx, b.tiles_nx, gpy, b.tiles_ny, P->n, dE, gx, gy, s) != hipSuccess) return PP_ERR_DEVICE; }
         return PP_OK;
     }
@@ -313,7 +311,7 @@ int pp_point_field(const pp_problem *P, const double *px, const double *py, cons
                    double *xix, double *xiy, void *ws, size_t ws_bytes, void *stream) {
     int st = validate_problem(P);
     if (st != PP_OK) return st;
-    if (!rowform_precision(P->precision)) return PP_ERR_UNSUPPORTED;
+    if (P->basis_mode != PP_BASIS_RECOMPUTE) return PP_ERR_UNSUPPORTED;
     if (P->n > 0 && (!px || !py || !aligned8(px) || !aligned8(py))) return PP_ERR_ARG;
     if (!a || !aligned8(a)) return PP_ERR_ARG;
     if ((psi && !aligned8(psi)) || (xix && !aligned8(xix)) || (xiy && !aligned8(xiy))) return PP_ERR_ARG;
@@ -325,6 +323,43 @@ int pp_point_field(const pp_problem *P, const double *px, const double *py, cons
     char *base = (char *)ws;
     double *gp1 = (double *)(base + L.gpx), *gp2 = (double *)(base + L.gpz), *gpy = (double *)(base + L.gpy);
     void *bx = base + L.bx, *by = base + L.by;
+    if (is_bf16(P->precision)) {
+        // bf16 operands: point phase records (size 0), hi/lo tiled a, the bf16 row-form kernels.
+        const bool x3 = P->precision == PP_BF16X3;
+        PhaseRec *tx = (PhaseRec *)(base + L.tx), *ty = (PhaseRec *)(base + L.ty);
+        unsigned short *bxt = (unsigned short *)bx, *byt = (unsigned short *)by;
+        const int khx = bf16_kh(P->Mp), khy = bf16_kh(P->Mu);
+        { TimedLaunch t("tables", s); if (launch_phase_tables(P->n, px, py, nullptr, nullptr, P->W, P->H, tx, ty, s) != hipSuccess) return PP_ERR_DEVICE; }
+        {
+            TimedLaunch t("prep", s);
+            if ((psi || xix) &&
+                launch_prep_bwd_bf16(ROW_POINT_DUAL, a, P->Mu, P->Mp, P->W, P->H, 0, b.tiles_nx * 256, khx, bxt, s) !=
+                    hipSuccess)
+                return PP_ERR_DEVICE;
+            if (xiy &&
+                launch_prep_bwd_bf16(ROW_POINT_DUAL, a, P->Mu, P->Mp, P->W, P->H, 1, b.tiles_ny * 256, khy, byt, s) !=
+                    hipSuccess)
+                return PP_ERR_DEVICE;
+        }
+        if (psi || xix) {
+            TimedLaunch t("point", s);
+            const RowForm f = psi ? ROW_POINT_DUAL : ROW_POINT_WSIN;
+            BwdAxisBf16 ax{ty, tx, P->Mp, P->Mu, khx, bxt, psi ? gp1 : gp2, nullptr, nullptr, 0, 0, 0,
+                           psi ? gp2 : nullptr, (float)(kPi / P->W)};
+            if (launch_bwd_bf16(f, x3, P->n, ax, s) != hipSuccess) return PP_ERR_DEVICE;
+        }
+        if (xiy) {
+            TimedLaunch t("point", s);
+            BwdAxisBf16 ax{tx, ty, P->Mu, P->Mp, khy, byt, gpy, nullptr, nullptr, 0, 0, 0, nullptr, (float)(kPi / P->H)};
+            if (launch_bwd_bf16(ROW_POINT_WSIN, x3, P->n, ax, s) != hipSuccess) return PP_ERR_DEVICE;
+        }
+        TimedLaunch t("final", s);
+        if (launch_bwd_final(gp1, b.tiles_nx, gpy, b.tiles_ny, P->n, nullptr, psi, xiy, s) != hipSuccess)
+            return PP_ERR_DEVICE;
+        if (xix && launch_bwd_final(gp2, b.tiles_nx, gp2, 0, P->n, nullptr, xix, nullptr, s) != hipSuccess)
+            return PP_ERR_DEVICE;
+        return PP_OK;
+    }
     if (prep_rowform(*P, ROW_POINT_DUAL, a, bx, xiy ? by : nullptr, s) != hipSuccess) return PP_ERR_DEVICE;
     // psi and xi_x share Z_iu = sum_p a_up cos(v_p y_i) (K = p, operand a^T); epilogues over u with
     // cos(w_u x_i) and w_u sin(w_u x_i).
@@ -352,7 +387,7 @@ int pp_block_potential(const pp_problem *P, const double *x, const double *y, co
                        const double *a, double *N, void *ws, size_t ws_bytes, void *stream) {
     int st = validate_problem(P);
     if (st != PP_OK) return st;
-    if (!rowform_precision(P->precision)) return PP_ERR_UNSUPPORTED;
+    if (P->basis_mode != PP_BASIS_RECOMPUTE) return PP_ERR_UNSUPPORTED;
     if ((st = validate_blocks(P, x, y, w, h)) != PP_OK) return st;
     if (!a || !aligned8(a)) return PP_ERR_ARG;
     if (P->n > 0 && (!N || !aligned8(N))) return PP_ERR_ARG;
@@ -364,6 +399,27 @@ int pp_block_potential(const pp_problem *P, const double *x, const double *y, co
     char *base = (char *)ws;
     double *gp = (double *)(base + L.gpx);
     void *bx = base + L.bx;
+    if (is_bf16(P->precision)) {
+        const bool x3 = P->precision == PP_BF16X3;
+        PhaseRec *tx = (PhaseRec *)(base + L.tx), *ty = (PhaseRec *)(base + L.ty);
+        unsigned short *bxt = (unsigned short *)bx;
+        const int khx = bf16_kh(P->Mp);
+        { TimedLaunch t("tables", s); if (launch_phase_tables(P->n, x, y, w, h, P->W, P->H, tx, ty, s) != hipSuccess) return PP_ERR_DEVICE; }
+        {
+            TimedLaunch t("prep", s);
+            if (launch_prep_bwd_bf16(ROW_POTENTIAL, a, P->Mu, P->Mp, P->W, P->H, 0, b.tiles_nx * 256, khx, bxt, s) !=
+                hipSuccess)
+                return PP_ERR_DEVICE;
+        }
+        {
+            TimedLaunch t("potential", s);
+            BwdAxisBf16 ax{ty, tx, P->Mp, P->Mu, khx, bxt, gp, nullptr, nullptr, 0, 0, 0, nullptr, 0.0f};
+            if (launch_bwd_bf16(ROW_POTENTIAL, x3, P->n, ax, s) != hipSuccess) return PP_ERR_DEVICE;
+        }
+        TimedLaunch t("final", s);
+        if (launch_bwd_final(gp, b.tiles_nx, gp, 0, P->n, nullptr, N, nullptr, s) != hipSuccess) return PP_ERR_DEVICE;
+        return PP_OK;
+    }
     if (prep_rowform(*P, ROW_POTENTIAL, a, bx, nullptr, s) != hipSuccess) return PP_ERR_DEVICE;
     // N_i = sum_u S_iu sum_p T_ip a_up / (vt_p wt_u): K = p, epilogue over u, both sine differences.
     {

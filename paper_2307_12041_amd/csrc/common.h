@@ -50,7 +50,17 @@ struct BwdAxis {
     double *gpart2;          // out: [tiles_n][n] partial row sums of the second epilogue, if any
 };
 
-// Which row-form contraction (kernels_f64.hip): K-side basis / epilogue basis.
+// Kinds of per-block basis values along one axis (frequency k, w_k = k pi / L, block centre c,
+// size sz):
+//   RUN_SINDIFF  sin(w_k (c + sz/2)) - sin(w_k (c - sz/2)), and sz at k = 0 (the sine-difference
+//                integral times w_k, Sec. III-A coefficient closed forms);
+//   RUN_COSDIFF  cos(w_k (c + sz/2)) - cos(w_k (c - sz/2)), 0 at k = 0 (its derivative, the field of
+//                eq. ksi integrated over the block);
+//   RUN_COS      cos(w_k c)  (point value of the eq. psi basis);
+//   RUN_WSIN     w_k sin(w_k c)  (point value of the eq. ksi basis).
+enum RunKind { RUN_SINDIFF = 0, RUN_COSDIFF = 1, RUN_COS = 2, RUN_WSIN = 3 };
+
+// Which row-form contraction (FP64 / FP32 and bf16 kernels): K-side basis / epilogue basis.
 enum RowForm {
     ROW_FIELD = 0,       // sine differences / cosine differences: the energy gradient (eq. ksi over a block)
     ROW_POTENTIAL = 1,   // sine differences / sine differences: block potentials (integral of eq. psi)
@@ -82,6 +92,10 @@ struct BwdAxisBf16 {
     // generated; tab_ld is their row length, tiles_b / tiles_n the grid of block / N tiles.
     const unsigned short *tab_h, *tab_l;
     int tab_ld, tiles_b, tiles_n;
+    // Row forms other than the gradient: a second epilogue's partial sums, and pi / L of the
+    // epilogue axis (for the w sin kind).
+    double *gpart2;
+    float pil;
 };
 
 // Store-mode basis tables of both axes (bf16 hi and lo, row-major [block][frequency]).
@@ -113,14 +127,15 @@ hipError_t launch_fwd_f32(const FwdPlan &pl, int64_t n, int Mu, int Mp, double W
                           const double *x, const double *y, const double *w, const double *h,
                           float *part, hipStream_t s);
 hipError_t launch_rowform_f32(RowForm f, const BwdPlan &pl, int64_t n, const BwdAxis &ax, hipStream_t s);
+// Phase records of both axes (w, h may be NULL for points: size 0).
 hipError_t launch_phase_tables(int64_t n, const double *x, const double *y, const double *w, const double *h,
                                double W, double H, PhaseRec *tx, PhaseRec *ty, hipStream_t s);
 hipError_t launch_fwd_bf16(const FwdPlan &pl, bool x3, int64_t n, int Mu, int Mp, const PhaseRec *tx,
                            const PhaseRec *ty, float *part, hipStream_t s);
-hipError_t launch_prep_bwd_bf16(const double *a, int Mu, int Mp, double W, double H, int trans, int Np, int Kh,
-                                unsigned short *B, hipStream_t s);
+hipError_t launch_prep_bwd_bf16(RowForm f, const double *a, int Mu, int Mp, double W, double H, int trans, int Np,
+                                int Kh, unsigned short *B, hipStream_t s);
 size_t bwd_bf16_operand_elems(int Np, int Kh);   // bf16 elements of one tiled backward operand
-hipError_t launch_bwd_bf16(bool x3, int64_t n, const BwdAxisBf16 &ax, hipStream_t s);
+hipError_t launch_bwd_bf16(RowForm f, bool x3, int64_t n, const BwdAxisBf16 &ax, hipStream_t s);
 // Store mode: table rows (n rounded up to 256) and row length (M rounded up to 256); the table of
 // one axis from its phase records (lo table only for x3); the forward from both axes' tables.
 int64_t store_rows(int64_t n);

@@ -92,7 +92,8 @@ __global__ void k_phase_table(int64_t n, const double *__restrict__ c, const dou
                               PhaseRec *__restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double ta = c[i] / L, tb = sz[i] / (2.0 * L);
+    const double szi = sz ? sz[i] : 0.0;
+    const double ta = c[i] / L, tb = szi / (2.0 * L);
     PhaseRec r;
     r.ta = ta;
     r.tb = tb;
@@ -107,7 +108,7 @@ __global__ void k_phase_table(int64_t n, const double *__restrict__ c, const dou
     r.ca32 = (float)co; r.sa32 = (float)s;
     sincospi(reduce_half_turns(32.0 * tb), &s, &co);
     r.cb32 = (float)co; r.sb32 = (float)s;
-    r.size = (float)sz[i];
+    r.size = (float)szi;
     r.pad0 = r.pad1 = r.pad2 = 0.0f;
     out[i] = r;
 }
@@ -443,7 +444,20 @@ __device__ __forceinline__ void bwd_copy_b(const unsigned short *__restrict__ gt
 
 __device__ __forceinline__ void wait_copies() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-template <bool X3, bool ST>
+// The epilogue basis value of kind EK at frequency nn from the phasors (ca, sa) of nn alpha and
+// (cb, sb) of nn beta (alpha = pi c / L, beta = pi sz / (2L)); pil = pi / L.
+template <int EK>
+__device__ __forceinline__ float ep_value(float ca, float sa, float cb, float sb, int nn, float size, float pil) {
+    (void)cb;
+    if constexpr (EK == RUN_COSDIFF) return -2.0f * sa * sb;
+    else if constexpr (EK == RUN_SINDIFF) return nn == 0 ? size : 2.0f * ca * sb;
+    else if constexpr (EK == RUN_COS) return ca;
+    else return (float)nn * pil * sa;
+}
+
+// KA: kind of the K-axis basis (RUN_SINDIFF or RUN_COS); E1, E2: kinds of the first and (if E2 >= 0)
+// second epilogue (see RunKind).  The gradient is <SINDIFF, COSDIFF, -1>.
+template <bool X3, bool ST, int KA, int E1, int E2>
 __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
     __shared__ __attribute__((aligned(16))) char smem[2 * BBUF];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -517,11 +531,18 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
     // A operand of one K step (8 consecutive frequencies of this lane's block), split hi/lo.
     auto gen_a = [&](bf16x8 &ah, bf16x8 &al) {
         float v[8];
-        v[0] = ca.f * sb.f;
+        if constexpr (KA == RUN_COS) {
+            v[0] = ca.f;
 #pragma unroll
-        for (int e = 1; e < 8; ++e) v[e] = ca.next() * sb.next();
-        ca.next(); sb.next();
-        v[0] = kcur == 0 ? size0 : v[0];
+            for (int e = 1; e < 8; ++e) v[e] = ca.next();
+            ca.next();
+        } else {
+            v[0] = ca.f * sb.f;
+#pragma unroll
+            for (int e = 1; e < 8; ++e) v[e] = ca.next() * sb.next();
+            ca.next(); sb.next();
+            v[0] = kcur == 0 ? size0 : v[0];
+        }
         kcur += 8;
         unsigned hh[4], ll[4];
 #pragma unroll
@@ -631,12 +652,14 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
 
     // Epilogue: lane holds G for rows 8 (r / 4) + 4 h + r % 4 and columns n0 + 32 b + j.
     // E = -2 sin(nn alpha) sin(nn beta) of the epilogue axis, stepped by 32 columns.
-    float rs[16];
+    // The E2 epilogue (if any) shares the phasors with E1.
+    constexpr bool DUAL = E2 >= 0;
+    float rs[16], rs2[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int row = 8 * (r >> 2) + 4 * h + (r & 3);
         const int64_t ibe = i0 + row;
-        float sum = 0.0f;
+        float sum = 0.0f, sum2 = 0.0f;
         if (ibe < n) {
             const PhaseRec RE = ax.te[ibe];
             const int nn = n0 + j;
@@ -645,7 +668,10 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
             seed_phasor(nn, RE.tb, cb0, sb0);
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
-                sum = fmaf(-2.0f * sa0 * sb0, acc[b][r], sum);
+                sum = fmaf(ep_value<E1>(ca0, sa0, cb0, sb0, nn + 32 * b, RE.size, ax.pil), acc[b][r], sum);
+                if constexpr (DUAL)
+                    sum2 = fmaf(ep_value<(DUAL ? E2 : 0)>(ca0, sa0, cb0, sb0, nn + 32 * b, RE.size, ax.pil), acc[b][r],
+                                sum2);
                 const float ta = ca0 * RE.ca32 - sa0 * RE.sa32;
                 sa0 = sa0 * RE.ca32 + ca0 * RE.sa32;
                 ca0 = ta;
@@ -655,34 +681,40 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
             }
         }
         rs[r] = sum;
+        rs2[r] = sum2;
     }
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        float v = rs[r];
-        v += __shfl_xor(v, 1);
-        v += __shfl_xor(v, 2);
-        v += __shfl_xor(v, 4);
-        v += __shfl_xor(v, 8);
-        v += __shfl_xor(v, 16);
-        rs[r] = v;
-    }
-    if (j == 0) {
+    auto reduce_store = [&](float (&x)[16], double *__restrict__ gp) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const int64_t ibe = i0 + 8 * (r >> 2) + 4 * h + (r & 3);
-            if (ibe < n) ax.gpart[(size_t)ntile * (size_t)n + (size_t)ibe] = (double)rs[r];
+            float v = x[r];
+            v += __shfl_xor(v, 1);
+            v += __shfl_xor(v, 2);
+            v += __shfl_xor(v, 4);
+            v += __shfl_xor(v, 8);
+            v += __shfl_xor(v, 16);
+            x[r] = v;
         }
-    }
+        if (j == 0) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t ibe = i0 + 8 * (r >> 2) + 4 * h + (r & 3);
+                if (ibe < n) gp[(size_t)ntile * (size_t)n + (size_t)ibe] = (double)x[r];
+            }
+        }
+    };
+    reduce_store(rs, ax.gpart);
+    if constexpr (DUAL) reduce_store(rs2, ax.gpart2);
 }
 
-// Backward operand preparation for the bf16 path: BT[nn][k] = a_up / (scale of the K axis),
+// Row-form operand preparation for the bf16 path: BT[nn][k] = a_up times the factor of the form
+// (gradient: 1 / scale of the K axis; potentials: 1 / (wt_u vt_p); point field: 1),
 // split into bf16 hi and lo, zero padded, and tiled exactly in the LDS byte order of k_bwd_bf16:
 // tile (n_tile, q) = [hi | lo][256 rows][8 segments of 8 values], the 16-byte segment of logical
 // index seg stored at seg ^ ((row / 2) % 8); logical segment seg = 4 half + s holds
 // k = half * Kh + 32 q + 8 s + e (e = 0..7).
 // trans = 0: nn = u, k = p (gx operand, a_up / vt_p);  trans = 1: nn = p, k = u (gy, a_up / wt_u).
-__global__ void k_prep_bwd_bf16(const double *__restrict__ a, int Mu, int Mp, double W, double H, int trans,
-                                int Np, int Kh, unsigned short *__restrict__ B) {
+__global__ void k_prep_bwd_bf16(int form, const double *__restrict__ a, int Mu, int Mp, double W, double H,
+                                int trans, int Np, int Kh, unsigned short *__restrict__ B) {
     const int Q = Kh / 32;
     const size_t per_tile = (size_t)BBUF / 2;
     const size_t total = (size_t)(Np / BTN) * (size_t)Q * per_tile;
@@ -702,9 +734,10 @@ __global__ void k_prep_bwd_bf16(const double *__restrict__ a, int Mu, int Mp, do
     float out = 0.0f;
     if (nn < Nb && k < Ka) {
         const int u = trans ? k : nn, p = trans ? nn : k;
-        double sc;
-        if (trans) sc = u ? (double)u * kPi / W : 1.0;
-        else sc = p ? (double)p * kPi / H : 1.0;
+        const double wt = u ? (double)u * kPi / W : 1.0, vt = p ? (double)p * kPi / H : 1.0;
+        double sc = 1.0;                                  // ROW_POINT_*: a itself
+        if (form == ROW_FIELD) sc = trans ? wt : vt;      // a / (scale of the K axis)
+        else if (form == ROW_POTENTIAL) sc = wt * vt;     // a / (wt_u vt_p)
         const double v = a[(size_t)u * Mp + p] / sc;
         const float hv = (float)(__bf16)(float)v;
         out = hl == 0 ? hv : (float)(__bf16)(float)(v - (double)hv);
@@ -854,32 +887,47 @@ hipError_t launch_fwd_bf16(const FwdPlan &pl, bool x3, int64_t n, int Mu, int Mp
     return hipGetLastError();
 }
 
-hipError_t launch_prep_bwd_bf16(const double *a, int Mu, int Mp, double W, double H, int trans, int Np, int Kh,
-                                unsigned short *B, hipStream_t s) {
+hipError_t launch_prep_bwd_bf16(RowForm f, const double *a, int Mu, int Mp, double W, double H, int trans, int Np,
+                                int Kh, unsigned short *B, hipStream_t s) {
     const size_t total = bwd_bf16_operand_elems(Np, Kh);
-    hipLaunchKernelGGL(k_prep_bwd_bf16, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a, Mu, Mp, W, H,
-                       trans, Np, Kh, B);
+    hipLaunchKernelGGL(k_prep_bwd_bf16, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, (int)f, a, Mu, Mp, W,
+                       H, trans, Np, Kh, B);
     return hipGetLastError();
 }
 
 size_t bwd_bf16_operand_elems(int Np, int Kh) { return (size_t)(Np / BTN) * (size_t)(Kh / 32) * (size_t)(BBUF / 2); }
 
-hipError_t launch_bwd_bf16(bool x3, int64_t n, const BwdAxisBf16 &ax, hipStream_t s) {
+namespace {
+template <int KA, int E1, int E2>
+hipError_t launch_rowform_bf16(bool x3, int64_t n, const BwdAxisBf16 &ax, hipStream_t s) {
+    dim3 grid((unsigned)((n + 255) / 256), (unsigned)((ax.Nb + BTN - 1) / BTN));
+    if (x3) hipLaunchKernelGGL((k_bwd_bf16<true, false, KA, E1, E2>), grid, dim3(512), 0, s, n, ax);
+    else hipLaunchKernelGGL((k_bwd_bf16<false, false, KA, E1, E2>), grid, dim3(512), 0, s, n, ax);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_bwd_bf16(RowForm f, bool x3, int64_t n, const BwdAxisBf16 &ax, hipStream_t s) {
     if (n == 0) return hipSuccess;
     if (ax.tab_h) {
-        // store mode: one-dimensional XCD-aware grid over (block tile, N tile)
-        if (ax.tiles_b != (int)((n + 255) / 256) || ax.tiles_n != (ax.Nb + BTN - 1) / BTN || ax.tab_ld < 2 * ax.Kh ||
-            (x3 && !ax.tab_l))
+        // store mode (gradient only): one-dimensional XCD-aware grid over (block tile, N tile)
+        if (f != ROW_FIELD || ax.tiles_b != (int)((n + 255) / 256) || ax.tiles_n != (ax.Nb + BTN - 1) / BTN ||
+            ax.tab_ld < 2 * ax.Kh || (x3 && !ax.tab_l))
             return hipErrorInvalidValue;
         const unsigned g = (unsigned)((ax.tiles_b + 7) / 8 * 8 * ax.tiles_n);
-        if (x3) hipLaunchKernelGGL((k_bwd_bf16<true, true>), dim3(g), dim3(512), 0, s, n, ax);
-        else hipLaunchKernelGGL((k_bwd_bf16<false, true>), dim3(g), dim3(512), 0, s, n, ax);
+        if (x3) hipLaunchKernelGGL((k_bwd_bf16<true, true, RUN_SINDIFF, RUN_COSDIFF, -1>), dim3(g), dim3(512), 0, s, n, ax);
+        else hipLaunchKernelGGL((k_bwd_bf16<false, true, RUN_SINDIFF, RUN_COSDIFF, -1>), dim3(g), dim3(512), 0, s, n, ax);
         return hipGetLastError();
     }
-    dim3 grid((unsigned)((n + 255) / 256), (unsigned)((ax.Nb + BTN - 1) / BTN));
-    if (x3) hipLaunchKernelGGL((k_bwd_bf16<true, false>), grid, dim3(512), 0, s, n, ax);
-    else hipLaunchKernelGGL((k_bwd_bf16<false, false>), grid, dim3(512), 0, s, n, ax);
-    return hipGetLastError();
+    switch (f) {
+        case ROW_FIELD: return launch_rowform_bf16<RUN_SINDIFF, RUN_COSDIFF, -1>(x3, n, ax, s);
+        case ROW_POTENTIAL: return launch_rowform_bf16<RUN_SINDIFF, RUN_SINDIFF, -1>(x3, n, ax, s);
+        case ROW_POINT_DUAL:
+            if (!ax.gpart2) return hipErrorInvalidValue;
+            return launch_rowform_bf16<RUN_COS, RUN_COS, RUN_WSIN>(x3, n, ax, s);
+        case ROW_POINT_WSIN: return launch_rowform_bf16<RUN_COS, RUN_WSIN, -1>(x3, n, ax, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 int64_t store_rows(int64_t n) { return (n + 255) / 256 * 256; }

@@ -77,16 +77,7 @@ struct PointRot {
     }
 };
 
-// Kinds of per-block basis runs along one axis (frequency k, w_k = k pi / L, block centre c, size sz):
-//   RUN_SINDIFF  sin(w_k (c + sz/2)) - sin(w_k (c - sz/2)), and sz at k = 0 (the sine-difference
-//                integral times w_k, Sec. III-A coefficient closed forms);
-//   RUN_COSDIFF  cos(w_k (c + sz/2)) - cos(w_k (c - sz/2)), 0 at k = 0 (its derivative, the field of
-//                eq. ksi integrated over the block);
-//   RUN_COS      cos(w_k c)  (point value of the eq. psi basis);
-//   RUN_WSIN     w_k sin(w_k c)  (point value of the eq. ksi basis).
-enum RunKind { RUN_SINDIFF = 0, RUN_COSDIFF = 1, RUN_COS = 2, RUN_WSIN = 3 };
-
-// R consecutive values of one kind for one block, written at dst[k*stride] (generated in FP64,
+// R consecutive values of one kind (RunKind) for one block, written at dst[k*stride] (generated in FP64,
 // rounded to T when stored).
 template <int KIND, int R, typename T>
 __device__ __forceinline__ void gen_run(double c, double sz, double L, int k0, bool valid, T *dst, int stride) {
