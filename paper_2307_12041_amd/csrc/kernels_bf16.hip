@@ -115,6 +115,14 @@ __global__ void k_phase_table(int64_t n, const double *__restrict__ c, const dou
 
 namespace {
 
+__device__ __forceinline__ void wait_copies() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Workgroup barrier that orders LDS only: this wave's LDS operations complete, then all waves meet.
+// (__syncthreads() also waits for every outstanding global load, which would expose the latency of
+// the record fetches and tile copies that are meant to stay in flight across a phase boundary; the
+// tile copies are waited for explicitly before the barrier that hands their buffer over.)
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // ================================================================================================
 // Forward: At[u][p] = sum_i S_iu T_ip over a range of blocks.
 // 512 threads = 8 waves in two ping-pong groups.  Wave w owns the 128 x 64 output sub-tile
@@ -391,7 +399,7 @@ __global__ __launch_bounds__(512) void k_fwd_bf16(int64_t n, int Mu, int Mp, con
         } else {
             if (more) fwd_gen<X3>(rec, f0, nxt + aoff, nxt + aoff + FARR, gt);
         }
-        __syncthreads();
+        lds_barrier();
         if (group == 0) {
             if (more) fwd_gen<X3>(rec, f0, nxt + aoff, nxt + aoff + FARR, gt);
         } else {
@@ -399,7 +407,7 @@ __global__ __launch_bounds__(512) void k_fwd_bf16(int64_t n, int Mu, int Mp, con
             if (c + 2 < c_end) rec = load_rec(tab, n, c + 2, kk);
             fwd_mma<X3>(cur, ox, oy, acc);
         }
-        __syncthreads();
+        lds_barrier();
     }
 
     float *out = part + (size_t)blockIdx.y * (size_t)Mu * (size_t)Mp;
@@ -441,8 +449,6 @@ __device__ __forceinline__ void bwd_copy_b(const unsigned short *__restrict__ gt
         __builtin_amdgcn_global_load_lds((const void *)((const char *)gtile + i * 8192 + tid * 16),
                                          (lds_void *)(buf + i * 8192 + wave * 1024), 16, 0, 0);
 }
-
-__device__ __forceinline__ void wait_copies() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // The epilogue basis value of kind EK at frequency nn from the phasors (ca, sa) of nn alpha and
 // (cb, sb) of nn beta (alpha = pi c / L, beta = pi sz / (2L)); pil = pi / L.
@@ -629,6 +635,8 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
         bwd_copy_b(gb, smem, tid);
         wait_copies();
         __syncthreads();
+        // The next chunk's B tile is copied from the start of the chunk; the middle barrier orders
+        // LDS only, so the copies stay in flight until the wait before the chunk's last barrier.
         for (int q = 0; q < Q; ++q) {
             char *cur = smem + (q & 1) * BBUF, *nxt = smem + ((q & 1) ^ 1) * BBUF;
             if (q + 1 < Q) bwd_copy_b(gb + (size_t)(q + 1) * tile_elems, nxt, tid);
@@ -638,7 +646,7 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
             } else {
                 gen_chunk();
             }
-            __syncthreads();
+            lds_barrier();
             if (group == 0) {
                 if (q + 1 < Q) gen_chunk();
             } else {
@@ -646,7 +654,7 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
                 for (int st = 0; st < 4; ++st) mma_step(cur, st, Ah[st], Al[st]);
             }
             wait_copies();
-            __syncthreads();
+            lds_barrier();
         }
     }
 
