@@ -139,14 +139,19 @@ constexpr int FARR = FKB * FROW;     // bytes per array
 constexpr int FBUF = 4 * FARR;       // Xh, Xl, Yh, Yl
 
 // Byte offset of 16-byte segment `seg` of row `k` in an LDS tile.  The LDS has 64 banks of 4 bytes
-// (a 256-byte period, half a row), so a segment's bank group is its index mod 16.  The index is
-// XORed with M(k) = 4 (k % 4) + (k / 4) % 4, which swaps the two 2-bit halves of k % 16:
-//   * a b128 store by 16 lanes writes one segment of 16 consecutive rows (see fwd_gen), and M is a
-//     bijection on k % 16, so the 16 stores hit 16 distinct bank groups;
+// (a 256-byte period, half a row), so a segment's bank group is its index mod 16 for reads; the b128
+// stores are served 8 lanes (128 bytes) at a time, where the index mod 8 counts.  The index is
+// XORed with M(k) = 4 (k % 4) + (k / 4) % 4, with bit 1 also flipped by bit 1 of k:
+//   * a b128 store by 8 (or 16) lanes writes one segment of 8 (or 16) consecutive rows (see fwd_gen);
+//     M mod 8 differs across any 8 consecutive aligned rows and M is a bijection on k % 16, so the
+//     stores hit distinct bank groups;
 //   * a 32-lane half of a transpose read covers 4 consecutive rows k0 .. k0 + 3 (k0 % 4 = 0) and 4
 //     consecutive segments of an aligned group of 4; M(k) / 4 = k % 4 moves each row's 4 segments
 //     to a different aligned group, so the 16 segments hit 16 distinct bank groups.
-__device__ __forceinline__ int fswz_mask(int k) { return ((k & 3) << 2) | ((k >> 2) & 3); }
+// (Measured with the LDS bank-conflict counter: no conflicts for either pattern.)
+__device__ __forceinline__ int fswz_mask(int k) {
+    return (((k & 3) << 2) | ((k >> 2) & 3)) ^ (((k >> 1) & 1) << 1);
+}
 __device__ __forceinline__ int fswz(int k, int seg) { return k * FROW + ((seg ^ fswz_mask(k)) << 4); }
 
 // The fields of a phase record that a generating thread needs, held in registers so that the
