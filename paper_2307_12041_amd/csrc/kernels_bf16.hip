@@ -21,6 +21,8 @@
 // element i % 4 of the 64 bits addressed by source lane 4 j + i / 4.
 #include "common.h"
 
+#include <utility>
+
 namespace pp {
 namespace {
 
@@ -63,15 +65,22 @@ __device__ __forceinline__ unsigned pack_bf16(float a, float b) {
     return __builtin_bit_cast(unsigned, v);
 }
 
+// The lo half of a split: packed bf16 of a - ha and b - hb, where ha, hb are the hi parts as fp32
+// bit patterns.  Contraction is off so that the remainders are taken from the rounded fp32 values
+// wherever a generator splits (a product fused into the subtraction would give other bits than a
+// generator whose product is kept for the hi half, and stored and regenerated tables must agree).
+__device__ __forceinline__ unsigned split_lo(float a, float b, unsigned ha, unsigned hb) {
+#pragma clang fp contract(off)
+    return pack_bf16(a - __builtin_bit_cast(float, ha), b - __builtin_bit_cast(float, hb));
+}
+
 // Split two fp32 values into packed bf16 hi (round to nearest even) and packed bf16 lo of the
 // remainders (exact in fp32).  Plain VALU shifts and subtractions: a bf16 dot-product form of the
 // remainder issues fewer instructions but shares the matrix pipe and stalls behind the MFMAs that
 // the other wave of the SIMD runs meanwhile (measured 4.8x slower there, against 1.6x for this).
 __device__ __forceinline__ void split2(float a, float b, unsigned &hi, unsigned &lo) {
     hi = pack_bf16(a, b);
-    const float ha = __builtin_bit_cast(float, hi << 16);
-    const float hb = __builtin_bit_cast(float, hi & 0xffff0000u);
-    lo = pack_bf16(a - ha, b - hb);
+    lo = split_lo(a, b, hi << 16, hi & 0xffff0000u);
 }
 
 // Three-term recurrence state for cos(k alpha) (or any sinusoid) with a hi/lo coefficient.
@@ -428,6 +437,229 @@ __global__ __launch_bounds__(512) void k_fwd_bf16(int64_t n, int Mu, int Mp, con
             }
 }
 
+// ------------------------------------------------------------------------------------------------
+// Forward, one wave per SIMD: 256 threads = 4 waves; wave w owns the 128 x 128 output sub-tile
+// (u-half w / 2, p-half w % 2) with 16 accumulator tiles (256 accumulator registers).  Every wave
+// both generates and contracts: while it contracts chunk c from one LDS buffer, its threads
+// generate one X run and one Y run of chunk c + 1 into the other, the generator's VALU work issued
+// in the shadow of the MFMAs of the same instruction stream.  One barrier per chunk.
+// ------------------------------------------------------------------------------------------------
+
+// The 16 operands of one K step of a 128 x 128 sub-tile.
+struct FwdOps1 {
+    bf16x8 ah[4], al[4], bh[4], bl[4];
+};
+
+// One run of 32 basis values generated in stages, one stage per MFMA slot of the chunk, so that its
+// VALU work spreads evenly over the matrix work.  Stage map: 0-7 seeds (FP64 reduction, the
+// sincospi polynomials, quadrant fix-up, recurrence set-up and the first two values); 8-37 one
+// value each; the hi/lo split of value pair q in two halves at stages 2q + 8 and 2q + 9; the four
+// 16-byte segments (hi and lo) stored at stages 16, 24, 32, 40.
+struct RunStages {
+    GenRec R;
+    float ra, rb, qa, qb, fa, fb, xa, xb, spa, spb, cpa, cpb;
+    Cheb C, S;
+    float v[32];
+    unsigned h[16], l[16], hah[16], hbh[16];
+
+    // Stage ST of the run starting at frequency u0, block row k, run r, stored into arr_h / arr_l.
+    template <int ST>
+    __device__ __forceinline__ void stage(int u0, char *arr_h, char *arr_l, int k, int r) {
+        constexpr int st = ST;
+        if constexpr (st == 0) {
+            ra = (float)reduce_half_turns((double)u0 * R.ta);
+            rb = (float)reduce_half_turns((double)u0 * R.tb);
+        } else if constexpr (st == 1) {
+            qa = rintf(2.0f * ra); fa = fmaf(-0.5f, qa, ra); xa = fa * fa;
+            qb = rintf(2.0f * rb); fb = fmaf(-0.5f, qb, rb); xb = fb * fb;
+        } else if constexpr (st == 2) {
+            spa = sin_poly(fa, xa);
+        } else if constexpr (st == 3) {
+            spb = sin_poly(fb, xb);
+        } else if constexpr (st == 4) {
+            cpa = cos_poly(xa);
+        } else if constexpr (st == 5) {
+            cpb = cos_poly(xb);
+        } else if constexpr (st == 6) {
+            quadrant(qa, spa, cpa);   // spa, cpa <- sin, cos of pi ra
+            quadrant(qb, spb, cpb);
+        } else if constexpr (st == 7) {
+            C.f = cpa;
+            C.fm = cpa * R.ca + spa * R.sa;              // cos((u0 - 1) alpha)
+            C.ch = R.c2ah; C.cl = R.c2al;
+            S.f = 2.0f * spb;                            // 2 sin(u0 beta)
+            S.fm = 2.0f * (spb * R.cb - cpb * R.sb);     // 2 sin((u0 - 1) beta)
+            S.ch = R.c2bh; S.cl = R.c2bl;
+            v[0] = C.f * S.f;
+            if (u0 == 0) v[0] = R.size;
+            v[1] = C.next() * S.next();
+        } else if constexpr (st < 38) {
+            constexpr int jv = st - 6;
+            v[jv] = C.next() * S.next();
+        }
+        // split of pair q: hi at stage 2q + 8, lo at 2q + 9
+        if constexpr (st >= 8 && st < 40) {
+            constexpr int q = (st - 8) >> 1;
+            if constexpr (((st - 8) & 1) == 0) {
+                h[q] = pack_bf16(v[2 * q], v[2 * q + 1]);
+                asm("" : "+v"(h[q]));   // keeps the shift below on h (else it re-converts v[2q] alone)
+                hah[q] = h[q] << 16;
+                hbh[q] = h[q] & 0xffff0000u;
+            } else {
+                l[q] = split_lo(v[2 * q], v[2 * q + 1], hah[q], hbh[q]);
+            }
+        }
+        if constexpr (st >= 16 && st <= 40 && (st & 7) == 0) {
+            constexpr int m = (st - 16) >> 3;
+            *(u32x4 *)(arr_h + fswz(k, 4 * r + m)) = u32x4{h[4 * m], h[4 * m + 1], h[4 * m + 2], h[4 * m + 3]};
+            *(u32x4 *)(arr_l + fswz(k, 4 * r + m)) = u32x4{l[4 * m], l[4 * m + 1], l[4 * m + 2], l[4 * m + 3]};
+        }
+    }
+    static constexpr int kStages = 41;
+
+    // The pieces of sincospi_seed, separated so that they can be spread over slots.
+    static __device__ __forceinline__ float sin_poly(float f, float x) {
+        return f * fmaf(x, fmaf(x, fmaf(x, -5.893013400e-01f, 2.549791082e+00f), -5.167708535e+00f),
+                        3.141592649e+00f);
+    }
+    static __device__ __forceinline__ float cos_poly(float x) {
+        return fmaf(x, fmaf(x, fmaf(x, fmaf(x, 2.314641957e-01f, -1.335062776e+00f), 4.058708069e+00f),
+                            -4.934802175e+00f), 1.0f);
+    }
+    static __device__ __forceinline__ void quadrant(float q, float &sp, float &cp) {
+        const int iq = (int)q;
+        const bool sw = iq & 1;
+        const float s0 = sw ? cp : sp, c0 = sw ? sp : cp;
+        const unsigned ns = ((unsigned)iq & 2u) << 30, nc = ((unsigned)(iq + 1) & 2u) << 30;
+        sp = __builtin_bit_cast(float, __builtin_bit_cast(unsigned, s0) ^ ns);
+        cp = __builtin_bit_cast(float, __builtin_bit_cast(unsigned, c0) ^ nc);
+    }
+};
+
+// Operand OP (0..15) of K step KS in first-use order: Ah0, Bh0..3, Ah1..3, Bl0..3, Al0..3.
+template <int KS, int OP>
+__device__ __forceinline__ void fwd1_read(const char *buf, const OpBase &ox, const OpBase &oy, FwdOps1 &o) {
+    const char *xh = buf, *xl = buf + FARR, *yh = buf + 2 * FARR, *yl = buf + 3 * FARR;
+    if constexpr (OP == 0) o.ah[0] = load_opT(xh, ox, 0, KS);
+    else if constexpr (OP < 5) o.bh[OP - 1] = load_opT(yh, oy, OP - 1, KS);
+    else if constexpr (OP < 8) o.ah[OP - 4] = load_opT(xh, ox, OP - 4, KS);
+    else if constexpr (OP < 12) o.bl[OP - 8] = load_opT(yl, oy, OP - 8, KS);
+    else o.al[OP - 12] = load_opT(xl, ox, OP - 12, KS);
+}
+
+// MFMA `i` (0..47) of one K step: pass hi*hi, then hi*lo, then lo*hi, each over the 16 accumulator
+// tiles a-major, so consecutive MFMAs never share an accumulator.
+template <int I>
+__device__ __forceinline__ void fwd1_mfma(const FwdOps1 &o, f32x16 (&acc)[4][4]) {
+    constexpr int pass = I >> 4, a = (I >> 2) & 3, b = I & 3;
+    const bf16x8 A = pass == 2 ? o.al[a] : o.ah[a];
+    const bf16x8 B = pass == 1 ? o.bl[b] : o.bh[b];
+    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, acc[a][b], 0, 0, 0);
+}
+
+// Slot I of a chunk: MFMA I, the operand read and the generator stages assigned to it, then a
+// scheduling fence so that the compiler keeps this interleaving.
+struct Fwd1Ctx {
+    const char *cur;
+    char *nxt;
+    const OpBase &ox, &oy;
+    f32x16 (&acc)[4][4];
+    RunStages &gx, &gy;
+    FwdOps1 &o0, &o1;
+    int ux, uy, k, r;
+};
+
+template <int I>
+__device__ __forceinline__ void fwd1_slot(Fwd1Ctx &c) {
+    if constexpr (I < 48) fwd1_mfma<I>(c.o0, c.acc);
+    else fwd1_mfma<I - 48>(c.o1, c.acc);
+    if constexpr (I >= 12 && I < 44 && (I & 1) == 0) fwd1_read<1, (I - 12) / 2>(c.cur, c.ox, c.oy, c.o1);
+    if constexpr (I < RunStages::kStages) c.gx.template stage<I>(c.ux, c.nxt, c.nxt + FARR, c.k, c.r);
+    if constexpr (I >= 48 && I < 48 + RunStages::kStages)
+        c.gy.template stage<I - 48>(c.uy, c.nxt + 2 * FARR, c.nxt + 3 * FARR, c.k, c.r);
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int... I>
+__device__ __forceinline__ void fwd1_reads0(Fwd1Ctx &c, std::integer_sequence<int, I...>) {
+    (fwd1_read<0, I>(c.cur, c.ox, c.oy, c.o0), ...);
+}
+
+template <int... I>
+__device__ __forceinline__ void fwd1_slots(Fwd1Ctx &c, std::integer_sequence<int, I...>) {
+    (fwd1_slot<I>(c), ...);
+}
+
+// One chunk: contract `cur` into acc while generating the next chunk's X and Y runs into `nxt`.
+// 96 slots of one MFMA each; step-0 operands are read up front, step-1 operands one every two slots
+// from slot 12; the X run's stages occupy slots 0-40, the Y run's slots 48-88.
+__device__ __forceinline__ void fwd1_chunk(const char *cur, char *nxt, const OpBase &ox, const OpBase &oy,
+                                           f32x16 (&acc)[4][4], RunStages &gx, RunStages &gy, int ux, int uy,
+                                           int k, int r) {
+    FwdOps1 o0, o1;
+    Fwd1Ctx c{cur, nxt, ox, oy, acc, gx, gy, o0, o1, ux, uy, k, r};
+    fwd1_reads0(c, std::make_integer_sequence<int, 16>{});
+    __builtin_amdgcn_sched_barrier(0);
+    fwd1_slots(c, std::make_integer_sequence<int, 96>{});
+}
+
+__global__ __launch_bounds__(256) void k_fwd1_bf16(int64_t n, int Mu, int Mp, const PhaseRec *__restrict__ tx,
+                                                   const PhaseRec *__restrict__ ty, float *__restrict__ part,
+                                                   int tiles_p, int64_t chunks, int64_t chunks_per_split) {
+    __shared__ __attribute__((aligned(16))) char smem[2 * FBUF];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tu0 = (int)(blockIdx.x / tiles_p) * FT, tp0 = (int)(blockIdx.x % tiles_p) * FT;
+    const int wu = 128 * (wave >> 1), wp = 128 * (wave & 1);
+    const int64_t c_begin = (int64_t)blockIdx.y * chunks_per_split;
+    const int64_t c_end = min(chunks, c_begin + chunks_per_split);
+
+    f32x16 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+    OpBase ox, oy;
+    ox.init(wu, lane);
+    oy.init(wp, lane);
+
+    // Thread tid generates block k = tid % 32 of each chunk, frequencies 32 r .. + 31 of the tile.
+    const int kk = tid & 31, rr = tid >> 5;
+    const int ux = tu0 + 32 * rr, uy = tp0 + 32 * rr;
+    if (c_begin < c_end) {
+        fwd_gen<true>(load_rec(tx, n, c_begin, kk), tu0, smem, smem + FARR, tid);
+        fwd_gen<true>(load_rec(ty, n, c_begin, kk), tp0, smem + 2 * FARR, smem + 3 * FARR, tid);
+    }
+    // The records of the chunk generated during an iteration are fetched one iteration earlier.
+    // (Past the range: zero records or records of the next split, generated into the idle buffer
+    // and never read.)
+    RunStages gx, gy;
+    gx.R = load_rec(tx, n, c_begin + 1, kk);
+    gy.R = load_rec(ty, n, c_begin + 1, kk);
+    lds_barrier();
+    for (int64_t c = c_begin; c < c_end; ++c) {
+        const int bsel = (int)((c - c_begin) & 1);
+        const GenRec nx = load_rec(tx, n, c + 2, kk), ny = load_rec(ty, n, c + 2, kk);
+        fwd1_chunk(smem + bsel * FBUF, smem + (bsel ^ 1) * FBUF, ox, oy, acc, gx, gy, ux, uy, kk, rr);
+        gx.R = nx;
+        gy.R = ny;
+        lds_barrier();
+    }
+
+    float *out = part + (size_t)blockIdx.y * (size_t)Mu * (size_t)Mp;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int u = tu0 + wu + 32 * a + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int p = tp0 + wp + 32 * b + (lane & 31);
+                if (u < Mu && p < Mp) out[(size_t)u * Mp + p] = acc[a][b][r];
+            }
+}
+
 // ================================================================================================
 // Backward: G[i][nn] = sum_k A_ik B[k][nn], g_i = sum_nn E_i,nn G[i][nn].
 // 512 threads = 8 waves; wave w owns blocks i0 + 32 w .. + 31 and all 256 columns of the N tile.
@@ -719,6 +951,368 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
     if constexpr (DUAL) reduce_store(rs2, ax.gpart2);
 }
 
+// ------------------------------------------------------------------------------------------------
+// Backward, one wave per SIMD (x3): 256 threads = 4 waves; wave w owns blocks i0 + 64 w .. + 63
+// (two 32-block subtiles) and all 256 columns of the N tile, 16 accumulator tiles.  Each wave
+// generates its A operands in registers one K step ahead, in the shadow of the current step's
+// MFMAs; B is read from LDS in the order of first use.  One barrier per chunk, in its last step:
+// after it the next chunk's tile (copied a chunk ahead) is read, and the chunk after next is copied
+// into the buffer just released.
+// ------------------------------------------------------------------------------------------------
+
+// A-operand generator of one 32-block subtile: recurrence state and the 32-frequency phasors (see
+// k_bwd_bf16), with the values and split halves of the step being generated.  The generator's
+// work is cut into pieces of at most three VALU instructions (a value and the first FMA of each
+// recurrence; the second FMAs; one half of a hi/lo split; half of a phasor jump), so that the
+// pieces can be dealt over the MFMA slots evenly.
+template <int KA>
+struct AGen {
+    Cheb ca, sb;
+    float tc, ts;                 // first FMAs of the two recurrences in flight
+    float pac, pas, pbc, pbs, jac, jas, jbc, jbs, sac, sas, sbc, sbs, size0;
+    float tj0, tj1;               // phasor jump in flight
+    float v[8];
+    unsigned hh[4], ll[4], hah[4], hbh[4];
+
+    __device__ __forceinline__ void init(const PhaseRec *__restrict__ tab, int64_t ib, bool valid, int k0) {
+        if (valid) {
+            const PhaseRec RA = tab[ib];
+            seed_phasor(k0, RA.ta, pac, pas);
+            seed_phasor(k0, RA.tb, pbc, pbs);
+            jac = RA.ca32; jas = RA.sa32; jbc = RA.cb32; jbs = RA.sb32;
+            sac = RA.ca; sas = RA.sa; sbc = RA.cb; sbs = RA.sb;
+            ca.ch = RA.c2ah; ca.cl = RA.c2al; sb.ch = RA.c2bh; sb.cl = RA.c2bl;
+            size0 = RA.size;
+        } else {
+            pac = pas = pbc = pbs = jac = jas = jbc = jbs = sac = sas = sbc = sbs = size0 = 0.0f;
+            ca.ch = ca.cl = sb.ch = sb.cl = 0.0f;
+        }
+        reseed();
+    }
+    __device__ __forceinline__ void reseed() {
+        ca.f = pac;
+        ca.fm = pac * sac + pas * sas;                // cos((k - 1) alpha)
+        sb.f = 2.0f * pbs;                            // 2 sin(k beta)
+        sb.fm = 2.0f * (pbs * sbc - pbc * sbs);       // 2 sin((k - 1) beta)
+    }
+    // The phasors advance by 32 frequencies in four pieces: the new cosine of alpha, then its sine
+    // (from the old cosine), then the same for beta.
+    template <int P>
+    __device__ __forceinline__ void jump() {
+        if constexpr (P == 0) tj0 = pac * jac - pas * jas;
+        else if constexpr (P == 1) { pas = pas * jac + pac * jas; pac = tj0; }
+        else if constexpr (P == 2) tj1 = pbc * jbc - pbs * jbs;
+        else { pbs = pbs * jbc + pbc * jbs; pbc = tj1; }
+    }
+    // Value E of the step (frequency k + E) and the first FMA of each recurrence; at k = 0 the
+    // sine-difference kind takes the block size (FIRST0: this step starts at frequency 0).
+    template <int E, bool FIRST0>
+    __device__ __forceinline__ void value1() {
+        if constexpr (KA == RUN_COS) {
+            v[E] = ca.f;
+            tc = fmaf(ca.cl, ca.f, -ca.fm);
+        } else {
+            v[E] = ca.f * sb.f;
+            if constexpr (E == 0 && FIRST0) v[0] = size0;
+            tc = fmaf(ca.cl, ca.f, -ca.fm);
+            ts = fmaf(sb.cl, sb.f, -sb.fm);
+        }
+    }
+    // The second FMAs: the recurrences advance by one frequency.
+    __device__ __forceinline__ void value2() {
+        const float nc = fmaf(ca.ch, ca.f, tc);
+        ca.fm = ca.f;
+        ca.f = nc;
+        if constexpr (KA != RUN_COS) {
+            const float ns = fmaf(sb.ch, sb.f, ts);
+            sb.fm = sb.f;
+            sb.f = ns;
+        }
+    }
+    template <int M>
+    __device__ __forceinline__ void half_hi() {
+        hh[M] = pack_bf16(v[2 * M], v[2 * M + 1]);
+        asm("" : "+v"(hh[M]));   // keeps the shift below on hh (else v[2M] is converted again)
+        hah[M] = hh[M] << 16;
+        hbh[M] = hh[M] & 0xffff0000u;
+    }
+    template <int M>
+    __device__ __forceinline__ void half_lo() {
+        ll[M] = split_lo(v[2 * M], v[2 * M + 1], hah[M], hbh[M]);
+    }
+    __device__ __forceinline__ bf16x8 hi() const { return __builtin_bit_cast(bf16x8, u32x4{hh[0], hh[1], hh[2], hh[3]}); }
+    __device__ __forceinline__ bf16x8 lo() const { return __builtin_bit_cast(bf16x8, u32x4{ll[0], ll[1], ll[2], ll[3]}); }
+};
+
+template <int KA>
+struct Bwd1Ctx {
+    const char *cur, *nxt;
+    char *cpy_dst;                 // buffer receiving the chunk after next
+    const char *cpy_src;           // its global tile (past the last chunk: the last chunk again)
+    AGen<KA> (&g)[2];
+    bf16x8 (&ah)[2], (&al)[2];     // A operands of the current step
+    bf16x8 (&bh)[8], (&bl)[8];     // B operands
+    f32x16 (&acc)[2][8];
+    int h, j;
+    unsigned lane_off;             // this lane's byte offset within a copy slice
+    int wave_off;                  // this wave's byte offset within a copy slice (uniform)
+};
+
+// B operand of column tile b, K step s of a chunk buffer: row 32 b + j, logical segment 4 h + s,
+// physical segment XORed with (j / 2) % 8.
+__device__ __forceinline__ bf16x8 bwd1_readb(const char *buf, int hl, int b, int s, int h, int j) {
+    const int bseg = ((4 * h + s) ^ ((j >> 1) & 7)) * 16;
+    return *(const bf16x8 *)(buf + hl * BARR + (32 * b + j) * BROW + bseg);
+}
+
+// Generator work of slot T (0..47) of a step, for the A operands of the following step (GS: the
+// step whose slots these are; FIRST0: the generated step starts at frequency 0).  Value u = 2 e + a
+// (e: frequency within the step, a: subtile) takes slots 3u (the value and first FMAs) and 3u + 1
+// (second FMAs).  Value pair m of subtile a is complete at slot 3 u2 with u2 = 4 m + 2 + a; its hi
+// half is split off at 3 u2 + 2 and, for m < 3, its lo half at 3 (u2 + 2) + 2.  The lo halves of
+// pair 3 fall into slots 2 and 5 of the next step, whose lo operands are assembled at slot 6 and
+// first used at slot 16; the hi operands are assembled at slot 47.  In step 0 the phasor jump
+// takes the second-FMA slots 1-22; in step 2 each subtile is reseeded from its phasors after its
+// last value of the chunk.
+template <int KA, int GS, bool FIRST0, int T>
+__device__ __forceinline__ void bwd1_gen(Bwd1Ctx<KA> &c) {
+    constexpr int u = T / 3, ph = T % 3;
+    constexpr int a = u & 1, e = u >> 1;
+    if constexpr (ph == 0) c.g[a].template value1<e, FIRST0>();
+    if constexpr (ph == 1) c.g[a].value2();
+    if constexpr (ph == 2) {
+        // hi halves at u = 4 m + 2 + a, lo halves (m < 3) at u = 4 m + 4 + a, lo of pair 3 at u = a
+        constexpr int r4 = u & 3;
+        if constexpr (r4 >= 2) c.g[r4 - 2].template half_hi<(u >> 2)>();
+        else if constexpr (u >= 4) c.g[r4].template half_lo<(u >> 2) - 1>();
+        else c.g[r4].template half_lo<3>();
+    }
+    if constexpr (GS == 0 && ph == 1 && u < 8) c.g[u >> 2].template jump<u & 3>();
+    if constexpr (GS == 2 && T == 45) c.g[0].reseed();
+    if constexpr (GS == 2 && T == 47) c.g[1].reseed();
+}
+
+// Slot I (0..191) of a chunk: one MFMA, the B reads, copies and generator work assigned to it, then
+// a scheduling fence.  MFMA order within a step: pass (hi*hi, lo*hi, hi*lo), column tile b,
+// subtile a.
+template <int KA, int I>
+__device__ __forceinline__ void bwd1_slot(Bwd1Ctx<KA> &c) {
+    constexpr int s = I / 48, t = I % 48;
+    constexpr int pass = t / 16, b = (t % 16) / 2, a = t % 2;
+    {
+        const bf16x8 A = pass == 1 ? c.al[a] : c.ah[a];
+        const bf16x8 B = pass == 2 ? c.bl[b] : c.bh[b];
+        c.acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, c.acc[a][b], 0, 0, 0);
+    }
+    // lo B of this step in the first half of the lo*hi pass, hi B of the next step in the first half
+    // of the hi*lo pass: each read lands at least 8 slots before its first use, so that even a full
+    // LDS wait (the compiler's while direct copies are in flight) finds them complete.
+    if constexpr (t >= 16 && t < 24) c.bl[t - 16] = bwd1_readb(c.cur, 1, t - 16, s, c.h, c.j);
+    if constexpr (s == 3 && t == 31) {
+        // all reads of this chunk's buffer are done and the next chunk's copies have landed
+        wait_copies();
+        lds_barrier();
+    }
+    if constexpr (t >= 32 && t < 40) {
+        constexpr int bb = t - 32;
+        if constexpr (s < 3) c.bh[bb] = bwd1_readb(c.cur, 0, bb, s + 1, c.h, c.j);
+        else c.bh[bb] = bwd1_readb(c.nxt, 0, bb, 0, c.h, c.j);
+    }
+    if constexpr (s == 3 && t >= 32) {
+        // copy slice (t - 32) of the chunk after next into the released buffer (unconditionally, so
+        // that the chunk stays one basic block: past the end the last chunk is copied again into
+        // a buffer that is not read any more)
+        typedef __attribute__((address_space(3))) void lds_void;
+        constexpr int sl = t - 32;
+        __builtin_amdgcn_global_load_lds((const void *)(c.cpy_src + sl * 4096 + c.lane_off),
+                                         (lds_void *)(c.cpy_dst + sl * 4096 + c.wave_off), 16, 0, 0);
+    }
+    bwd1_gen<KA, s, false, t>(c);
+    if constexpr (t == 6) {
+#pragma unroll
+        for (int aa = 0; aa < 2; ++aa) c.al[aa] = c.g[aa].lo();
+    }
+    if constexpr (t == 47) {
+#pragma unroll
+        for (int aa = 0; aa < 2; ++aa) c.ah[aa] = c.g[aa].hi();
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int KA, int... I>
+__device__ __forceinline__ void bwd1_slots(Bwd1Ctx<KA> &c, std::integer_sequence<int, I...>) {
+    (bwd1_slot<KA, I>(c), ...);
+}
+
+template <int KA, bool FIRST0, int... T>
+__device__ __forceinline__ void bwd1_gen_all(Bwd1Ctx<KA> &c, std::integer_sequence<int, T...>) {
+    (bwd1_gen<KA, 1, FIRST0, T>(c), ...);
+}
+
+// Epilogue generator of one row (block) along the N axis: the recurrences of the epilogue kinds
+// (sines or cosines of nn alpha, sine of nn beta), reseeded every 32 columns from phasors that
+// advance by the 32-frequency rotations of the phase record.
+template <int E1, int E2>
+struct EGen {
+    static constexpr bool DUAL = E2 >= 0;
+    // chain 0 (alpha): cosine for SINDIFF and COS, sine for COSDIFF and WSIN; chain 1: sine of
+    // alpha for the dual COS + WSIN epilogue, else sine of beta (SINDIFF, COSDIFF)
+    static constexpr bool C0_COS = E1 == RUN_SINDIFF || E1 == RUN_COS;
+    static constexpr bool HAS_C1 = DUAL || E1 == RUN_SINDIFF || E1 == RUN_COSDIFF;
+    static constexpr bool C1_BETA = !DUAL;
+    Cheb c0, c1;
+    float pac, pas, pbc, pbs;     // phasors of alpha and beta at the current 32-column start
+    float ca1, sa1, cb1, sb1;     // cos, sin of alpha and beta (one-column step)
+    float ja_c, ja_s, jb_c, jb_s; // 32-column rotations
+    float size, pil;
+
+    __device__ __forceinline__ void init(const PhaseRec &R, int nn0, float pil_) {
+        seed_phasor(nn0, R.ta, pac, pas);
+        seed_phasor(nn0, R.tb, pbc, pbs);
+        ca1 = R.ca; sa1 = R.sa; cb1 = R.cb; sb1 = R.sb;
+        ja_c = R.ca32; ja_s = R.sa32; jb_c = R.cb32; jb_s = R.sb32;
+        c0.ch = R.c2ah; c0.cl = R.c2al;
+        if constexpr (C1_BETA) { c1.ch = R.c2bh; c1.cl = R.c2bl; }
+        else { c1.ch = R.c2ah; c1.cl = R.c2al; }
+        size = R.size;
+        pil = pil_;
+    }
+    // chain values at the current start column nn and nn - 1
+    __device__ __forceinline__ void seed() {
+        if constexpr (C0_COS) { c0.f = pac; c0.fm = pac * ca1 + pas * sa1; }
+        else { c0.f = pas; c0.fm = pas * ca1 - pac * sa1; }
+        if constexpr (HAS_C1) {
+            if constexpr (C1_BETA) { c1.f = pbs; c1.fm = pbs * cb1 - pbc * sb1; }
+            else { c1.f = pas; c1.fm = pas * ca1 - pac * sa1; }
+        }
+    }
+    __device__ __forceinline__ void rotate() {
+        const float t = pac * ja_c - pas * ja_s;
+        pas = pas * ja_c + pac * ja_s;
+        pac = t;
+        if constexpr (C1_BETA && HAS_C1) {
+            const float tb = pbc * jb_c - pbs * jb_s;
+            pbs = pbs * jb_c + pbc * jb_s;
+            pbc = tb;
+        }
+    }
+};
+
+template <int KA, int E1, int E2>
+__global__ __launch_bounds__(256) void k_bwd1_bf16(int64_t n, BwdAxisBf16 ax) {
+    __shared__ __attribute__((aligned(16))) char smem[2 * BBUF];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int h = lane >> 5, j = lane & 31;
+    const int btile = blockIdx.x, ntile = blockIdx.y;
+    const int64_t i0 = (int64_t)btile * 256 + 64 * wave;
+    const int n0 = ntile * BTN;
+    const int Q = ax.Kh / 32;
+    const size_t tile_bytes = (size_t)BBUF;
+    const char *gb = (const char *)ax.B + (size_t)ntile * Q * tile_bytes;
+
+    AGen<KA> g[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const int64_t ib = i0 + 32 * a + j;
+        g[a].init(ax.ta, ib, ib < n, h * ax.Kh);
+    }
+    f32x16 acc[2][8];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+
+    // Prologue: copies of chunks 0 and 1, A of step 0 of chunk 0, hi B of step 0.
+    typedef __attribute__((address_space(3))) void lds_void;
+    for (int q = 0; q < 2 && q < Q; ++q)
+#pragma unroll
+        for (int sl = 0; sl < BBUF / 4096; ++sl)
+            __builtin_amdgcn_global_load_lds((const void *)(gb + (size_t)q * tile_bytes + sl * 4096 + tid * 16),
+                                             (lds_void *)(smem + q * BBUF + sl * 4096 + wave * 1024), 16, 0, 0);
+    bf16x8 ah[2], al[2], bh[8], bl[8];
+    Bwd1Ctx<KA> c{smem, smem + BBUF, smem, gb, g, ah, al, bh, bl, acc, h, j, (unsigned)tid * 16u, wave * 1024};
+    if (h == 0) bwd1_gen_all<KA, true>(c, std::make_integer_sequence<int, 48>{});
+    else bwd1_gen_all<KA, false>(c, std::make_integer_sequence<int, 48>{});
+    // the lo halves of pair 3 (in the loop: slots 2 and 5 of the next step)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        g[a].template half_lo<3>();
+        ah[a] = g[a].hi();
+        al[a] = g[a].lo();
+    }
+    wait_copies();
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < 8; ++b) bh[b] = bwd1_readb(smem, 0, b, 0, h, j);
+
+    for (int q = 0; q < Q; ++q) {
+        c.cur = smem + (q & 1) * BBUF;
+        c.nxt = smem + ((q & 1) ^ 1) * BBUF;
+        c.cpy_dst = smem + (q & 1) * BBUF;
+        c.cpy_src = gb + (size_t)min(q + 2, Q - 1) * tile_bytes;
+        bwd1_slots(c, std::make_integer_sequence<int, 192>{});
+    }
+    wait_copies();   // the copies issued in the last chunks must land before the buffers are reused
+    __syncthreads();
+
+    // Epilogue: g_i = sum_nn E_i,nn G[i][nn].  The accumulators hold G for rows
+    // 32 a + 8 (r / 4) + 4 h + r % 4 of the wave and column n0 + 32 b + j; one column tile at a
+    // time is transposed through LDS (rows of 36 floats: the b128 row reads of 16 lanes cover all
+    // banks), after which lane l holds row l and walks its 32 columns with the epilogue recurrences.
+    constexpr int EPS = 36;
+    float *tb = (float *)smem + wave * (64 * EPS);
+    const int64_t ibr = i0 + lane;
+    const bool rvalid = ibr < n;
+    EGen<E1, E2> eg;
+    if (rvalid) eg.init(ax.te[ibr], n0, ax.pil);
+    else eg.init(PhaseRec{}, n0, ax.pil);
+    float sum = 0.0f, sum2 = 0.0f, g00 = 0.0f;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) tb[(32 * a + 8 * (r >> 2) + 4 * h + (r & 3)) * EPS + j] = acc[a][b][r];
+        float gv[32];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const float4 x = *(const float4 *)(tb + lane * EPS + 4 * k);
+            gv[4 * k] = x.x; gv[4 * k + 1] = x.y; gv[4 * k + 2] = x.z; gv[4 * k + 3] = x.w;
+        }
+        if (b == 0) g00 = gv[0];
+        eg.seed();
+        float nnp = (float)(n0 + 32 * b) * eg.pil;   // nn pi / L for the w sin kind
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+            if constexpr (E1 == RUN_COSDIFF || E1 == RUN_SINDIFF) {
+                sum = fmaf(eg.c0.f * eg.c1.f, gv[k], sum);
+            } else if constexpr (E1 == RUN_COS) {
+                sum = fmaf(eg.c0.f, gv[k], sum);
+            } else {   // RUN_WSIN
+                sum = fmaf(nnp * eg.c0.f, gv[k], sum);
+            }
+            if constexpr (EGen<E1, E2>::DUAL) sum2 = fmaf(nnp * eg.c1.f, gv[k], sum2);   // w sin of alpha
+            if constexpr (E1 == RUN_WSIN || EGen<E1, E2>::DUAL) nnp += eg.pil;
+            eg.c0.next();
+            if constexpr (EGen<E1, E2>::HAS_C1) eg.c1.next();
+        }
+        eg.rotate();
+    }
+    // kind factors: -2 sin sin (cosine differences), 2 cos sin (sine differences, nn = 0: the size)
+    if constexpr (E1 == RUN_COSDIFF) sum *= -2.0f;
+    if constexpr (E1 == RUN_SINDIFF) {
+        sum *= 2.0f;
+        if (n0 == 0) sum = fmaf(eg.size, g00, sum);   // 2 cos sin vanishes at nn = 0
+    }
+    if (rvalid) {
+        ax.gpart[(size_t)ntile * (size_t)n + (size_t)ibr] = (double)sum;
+        if constexpr (EGen<E1, E2>::DUAL) ax.gpart2[(size_t)ntile * (size_t)n + (size_t)ibr] = (double)sum2;
+    }
+}
+
 // Row-form operand preparation for the bf16 path: BT[nn][k] = a_up times the factor of the form
 // (gradient: 1 / scale of the K axis; potentials: 1 / (wt_u vt_p); point field: 1),
 // split into bf16 hi and lo, zero padded, and tiled exactly in the LDS byte order of k_bwd_bf16:
@@ -892,7 +1486,7 @@ hipError_t launch_fwd_bf16(const FwdPlan &pl, bool x3, int64_t n, int Mu, int Mp
     if (pl.tu != FT || pl.tp != FT || pl.kb != FKB) return hipErrorInvalidValue;
     dim3 grid(pl.tiles_u * pl.tiles_p, pl.splits);
     if (x3)
-        hipLaunchKernelGGL(k_fwd_bf16<true>, grid, dim3(512), 0, s, n, Mu, Mp, tx, ty, part, pl.tiles_p, pl.chunks,
+        hipLaunchKernelGGL(k_fwd1_bf16, grid, dim3(256), 0, s, n, Mu, Mp, tx, ty, part, pl.tiles_p, pl.chunks,
                            pl.chunks_per_split);
     else
         hipLaunchKernelGGL(k_fwd_bf16<false>, grid, dim3(512), 0, s, n, Mu, Mp, tx, ty, part, pl.tiles_p,
@@ -914,7 +1508,7 @@ namespace {
 template <int KA, int E1, int E2>
 hipError_t launch_rowform_bf16(bool x3, int64_t n, const BwdAxisBf16 &ax, hipStream_t s) {
     dim3 grid((unsigned)((n + 255) / 256), (unsigned)((ax.Nb + BTN - 1) / BTN));
-    if (x3) hipLaunchKernelGGL((k_bwd_bf16<true, false, KA, E1, E2>), grid, dim3(512), 0, s, n, ax);
+    if (x3) hipLaunchKernelGGL((k_bwd1_bf16<KA, E1, E2>), grid, dim3(256), 0, s, n, ax);
     else hipLaunchKernelGGL((k_bwd_bf16<false, false, KA, E1, E2>), grid, dim3(512), 0, s, n, ax);
     return hipGetLastError();
 }
