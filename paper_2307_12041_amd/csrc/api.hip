@@ -102,8 +102,8 @@ Layout layout(const pp_problem &P) {
     Layout L{};
     size_t off = 0;
     if (is_bf16(P.precision)) {
-        L.tx = off; off = align_up(off + (size_t)P.n * sizeof(PhaseRec));
-        L.ty = off; off = align_up(off + (size_t)P.n * sizeof(PhaseRec));
+        L.tx = off; off = align_up(off + (size_t)phase_rows(P.n) * sizeof(PhaseRec));
+        L.ty = off; off = align_up(off + (size_t)phase_rows(P.n) * sizeof(PhaseRec));
     }
     if (P.basis_mode == PP_BASIS_STORE) {
         const bool x3 = P.precision == PP_BF16X3;

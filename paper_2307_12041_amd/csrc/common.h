@@ -81,6 +81,11 @@ struct __attribute__((aligned(16))) PhaseRec {
 };
 static_assert(sizeof(PhaseRec) == 80, "PhaseRec layout");
 
+// Rows of a phase-record table: n rounded up to whole chunks of 32 blocks, plus two more chunks, all
+// past n zero (an absent block: every basis value vanishes).  The bf16x3 forward fetches the
+// records of the chunk after next without a bounds test.
+inline int64_t phase_rows(int64_t n) { return (n + 31) / 32 * 32 + 64; }
+
 // One backward contraction of the bf16 path (gx or gy).
 struct BwdAxisBf16 {
     const PhaseRec *ta;          // K-axis records (basis generated along K)

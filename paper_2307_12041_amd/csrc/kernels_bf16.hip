@@ -96,11 +96,15 @@ struct Cheb {
 
 }  // namespace
 
-// Per-block phase record for one axis (see common.h).
-__global__ void k_phase_table(int64_t n, const double *__restrict__ c, const double *__restrict__ sz, double L,
-                              PhaseRec *__restrict__ out) {
+// Per-block phase record for one axis (see common.h); rows n .. rows - 1 get zero records.
+__global__ void k_phase_table(int64_t n, int64_t rows, const double *__restrict__ c, const double *__restrict__ sz,
+                              double L, PhaseRec *__restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= rows) return;
+    if (i >= n) {
+        out[i] = PhaseRec{};
+        return;
+    }
     const double szi = sz ? sz[i] : 0.0;
     const double ta = c[i] / L, tb = szi / (2.0 * L);
     PhaseRec r;
@@ -188,6 +192,19 @@ __device__ __forceinline__ GenRec load_rec_at(const PhaseRec *__restrict__ tab, 
 
 __device__ __forceinline__ GenRec load_rec(const PhaseRec *__restrict__ tab, int64_t n, int64_t chunk, int k) {
     return load_rec_at(tab, n, chunk * FKB + k);
+}
+
+// The same from a table padded with zero records (phase_rows): no bounds test, so that the fetch
+// issues the same loads on every path (a conditional fetch makes the compiler's later waits for
+// it, and for everything in flight with it, conservative).
+__device__ __forceinline__ GenRec load_rec_padded(const PhaseRec *__restrict__ tab, int64_t chunk, int k) {
+    const PhaseRec *p = tab + (chunk * FKB + k);
+    GenRec g;
+    g.ta = p->ta; g.tb = p->tb;
+    g.ca = p->ca; g.sa = p->sa; g.c2ah = p->c2ah; g.c2al = p->c2al;
+    g.cb = p->cb; g.sb = p->sb; g.c2bh = p->c2bh; g.c2bl = p->c2bl;
+    g.size = p->size;
+    return g;
 }
 
 // The basis values S_u (u0 <= u < u0 + 32) of one record (S_0 = size); the same arithmetic as the
@@ -569,20 +586,40 @@ struct Fwd1Ctx {
     int ux, uy, k, r;
 };
 
+// Step-0 operands: the first five (those of the first four MFMAs) are read in slots 84-88 of the
+// previous chunk, the others in slots 0-10 of their own chunk, each at least four slots before its
+// first use.
+template <int OP>
+constexpr int fwd1_read0_slot() { return OP < 5 ? 84 + OP : OP - 5; }
+
+template <int I, int... OP>
+__device__ __forceinline__ void fwd1_reads0_at(const char *buf, Fwd1Ctx &c, std::integer_sequence<int, OP...>) {
+    ((I == fwd1_read0_slot<OP>() ? fwd1_read<0, OP>(buf, c.ox, c.oy, c.o0) : void()), ...);
+}
+
 template <int I>
 __device__ __forceinline__ void fwd1_slot(Fwd1Ctx &c) {
     if constexpr (I < 48) fwd1_mfma<I>(c.o0, c.acc);
     else fwd1_mfma<I - 48>(c.o1, c.acc);
     if constexpr (I >= 12 && I < 44 && (I & 1) == 0) fwd1_read<1, (I - 12) / 2>(c.cur, c.ox, c.oy, c.o1);
-    if constexpr (I < RunStages::kStages) c.gx.template stage<I>(c.ux, c.nxt, c.nxt + FARR, c.k, c.r);
-    if constexpr (I >= 48 && I < 48 + RunStages::kStages)
-        c.gy.template stage<I - 48>(c.uy, c.nxt + 2 * FARR, c.nxt + 3 * FARR, c.k, c.r);
+    constexpr int Y0 = RunStages::kStages;   // the Y run's stages follow the X run's
+    if constexpr (I < Y0) c.gx.template stage<I>(c.ux, c.nxt, c.nxt + FARR, c.k, c.r);
+    if constexpr (I >= Y0 && I < 2 * Y0)
+        c.gy.template stage<I - Y0>(c.uy, c.nxt + 2 * FARR, c.nxt + 3 * FARR, c.k, c.r);
+    // The generator's last store is in slot 2 Y0 - 1 = 81: after the barrier the next chunk's tiles
+    // are complete (its first step-0 operands are read in the following slots, well before the
+    // next chunk's first MFMA) and this chunk's buffer is free for the next chunk's generator.
+    static_assert(2 * RunStages::kStages - 1 == 81, "slot plan");
+    if constexpr (I == 81) lds_barrier();
+    if constexpr (I >= 84 && I <= 88) fwd1_reads0_at<I>(c.nxt, c, std::make_integer_sequence<int, 5>{});
+    if constexpr (I <= 10) fwd1_reads0_at<I>(c.cur, c, std::make_integer_sequence<int, 16>{});
     __builtin_amdgcn_sched_barrier(0);
 }
 
 template <int... I>
-__device__ __forceinline__ void fwd1_reads0(Fwd1Ctx &c, std::integer_sequence<int, I...>) {
-    (fwd1_read<0, I>(c.cur, c.ox, c.oy, c.o0), ...);
+__device__ __forceinline__ void fwd1_reads0(const char *buf, const OpBase &ox, const OpBase &oy, FwdOps1 &o,
+                                            std::integer_sequence<int, I...>) {
+    (fwd1_read<0, I>(buf, ox, oy, o), ...);
 }
 
 template <int... I>
@@ -591,15 +628,14 @@ __device__ __forceinline__ void fwd1_slots(Fwd1Ctx &c, std::integer_sequence<int
 }
 
 // One chunk: contract `cur` into acc while generating the next chunk's X and Y runs into `nxt`.
-// 96 slots of one MFMA each; step-0 operands are read up front, step-1 operands one every two slots
-// from slot 12; the X run's stages occupy slots 0-40, the Y run's slots 48-88.
+// 96 slots of one MFMA each; the step-0 operands are read in slots 84-88 of the previous chunk and
+// 0-10 of this one, the step-1 operands one every two slots from slot 12; the X run's stages occupy
+// slots 0-40, the Y run's slots 41-81; the chunk's one barrier follows slot 81.
 __device__ __forceinline__ void fwd1_chunk(const char *cur, char *nxt, const OpBase &ox, const OpBase &oy,
-                                           f32x16 (&acc)[4][4], RunStages &gx, RunStages &gy, int ux, int uy,
-                                           int k, int r) {
-    FwdOps1 o0, o1;
+                                           f32x16 (&acc)[4][4], RunStages &gx, RunStages &gy, FwdOps1 &o0,
+                                           int ux, int uy, int k, int r) {
+    FwdOps1 o1;
     Fwd1Ctx c{cur, nxt, ox, oy, acc, gx, gy, o0, o1, ux, uy, k, r};
-    fwd1_reads0(c, std::make_integer_sequence<int, 16>{});
-    __builtin_amdgcn_sched_barrier(0);
     fwd1_slots(c, std::make_integer_sequence<int, 96>{});
 }
 
@@ -628,23 +664,27 @@ __global__ __launch_bounds__(256) void k_fwd1_bf16(int64_t n, int Mu, int Mp, co
     const int kk = tid & 31, rr = tid >> 5;
     const int ux = tu0 + 32 * rr, uy = tp0 + 32 * rr;
     if (c_begin < c_end) {
-        fwd_gen<true>(load_rec(tx, n, c_begin, kk), tu0, smem, smem + FARR, tid);
-        fwd_gen<true>(load_rec(ty, n, c_begin, kk), tp0, smem + 2 * FARR, smem + 3 * FARR, tid);
+        fwd_gen<true>(load_rec_padded(tx, c_begin, kk), tu0, smem, smem + FARR, tid);
+        fwd_gen<true>(load_rec_padded(ty, c_begin, kk), tp0, smem + 2 * FARR, smem + 3 * FARR, tid);
     }
     // The records of the chunk generated during an iteration are fetched one iteration earlier.
     // (Past the range: zero records or records of the next split, generated into the idle buffer
     // and never read.)
     RunStages gx, gy;
-    gx.R = load_rec(tx, n, c_begin + 1, kk);
-    gy.R = load_rec(ty, n, c_begin + 1, kk);
+    gx.R = load_rec_padded(tx, c_begin + 1, kk);
+    gy.R = load_rec_padded(ty, c_begin + 1, kk);
     lds_barrier();
+    FwdOps1 o0;
+    fwd1_reads0(smem, ox, oy, o0, std::make_integer_sequence<int, 5>{});
+    // Nothing the prologue loaded may still be in flight at the loop head (the compiler would then
+    // wait for every load and LDS read at the first use in each iteration).
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
     for (int64_t c = c_begin; c < c_end; ++c) {
         const int bsel = (int)((c - c_begin) & 1);
-        const GenRec nx = load_rec(tx, n, c + 2, kk), ny = load_rec(ty, n, c + 2, kk);
-        fwd1_chunk(smem + bsel * FBUF, smem + (bsel ^ 1) * FBUF, ox, oy, acc, gx, gy, ux, uy, kk, rr);
+        const GenRec nx = load_rec_padded(tx, c + 2, kk), ny = load_rec_padded(ty, c + 2, kk);
+        fwd1_chunk(smem + bsel * FBUF, smem + (bsel ^ 1) * FBUF, ox, oy, acc, gx, gy, o0, ux, uy, kk, rr);
         gx.R = nx;
         gy.R = ny;
-        lds_barrier();
     }
 
     float *out = part + (size_t)blockIdx.y * (size_t)Mu * (size_t)Mp;
@@ -1475,9 +1515,10 @@ __global__ __launch_bounds__(512) void k_fwd_bf16_st(int Mu, int Mp, StoreTables
 hipError_t launch_phase_tables(int64_t n, const double *x, const double *y, const double *w, const double *h,
                                double W, double H, PhaseRec *tx, PhaseRec *ty, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    const unsigned g = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_phase_table, dim3(g), dim3(256), 0, s, n, x, w, W, tx);
-    hipLaunchKernelGGL(k_phase_table, dim3(g), dim3(256), 0, s, n, y, h, H, ty);
+    const int64_t rows = phase_rows(n);
+    const unsigned g = (unsigned)((rows + 255) / 256);
+    hipLaunchKernelGGL(k_phase_table, dim3(g), dim3(256), 0, s, n, rows, x, w, W, tx);
+    hipLaunchKernelGGL(k_phase_table, dim3(g), dim3(256), 0, s, n, rows, y, h, H, ty);
     return hipGetLastError();
 }
 
