@@ -553,10 +553,21 @@ struct RunStages {
     }
 };
 
-// Operand OP (0..15) of K step KS in first-use order: Ah0, Bh0..3, Ah1..3, Bl0..3, Al0..3.
-template <int KS, int OP>
-__device__ __forceinline__ void fwd1_read(const char *buf, const OpBase &ox, const OpBase &oy, FwdOps1 &o) {
-    const char *xh = buf, *xl = buf + FARR, *yh = buf + 2 * FARR, *yl = buf + 3 * FARR;
+// LDS layout of the one-wave forward: the hi and lo arrays of both buffers interleaved,
+// [Xh0 Xh1 Xl0 Xl1 | Yh0 Yh1 Yl0 Yl1], 16 KB each, so that with one lane base for the X arrays
+// and one (64 KB further) for the Y arrays every operand read of either buffer is the base plus
+// an immediate offset below 64 KB.
+constexpr int F1_XH(int b) { return b * FARR; }
+constexpr int F1_XL(int b) { return (2 + b) * FARR; }
+constexpr int F1_YH(int b) { return (4 + b) * FARR; }
+constexpr int F1_YL(int b) { return (6 + b) * FARR; }
+
+// Operand OP (0..15) of K step KS of buffer B in first-use order: Ah0, Bh0..3, Ah1..3, Bl0..3,
+// Al0..3 (oy carries the 64 KB offset of the Y arrays).
+template <int KS, int OP, int B>
+__device__ __forceinline__ void fwd1_read(const char *smem, const OpBase &ox, const OpBase &oy, FwdOps1 &o) {
+    const char *xh = smem + F1_XH(B), *xl = smem + F1_XL(B);
+    const char *yh = smem + F1_YH(B) - F1_YH(0), *yl = smem + F1_YL(B) - F1_YH(0);
     if constexpr (OP == 0) o.ah[0] = load_opT(xh, ox, 0, KS);
     else if constexpr (OP < 5) o.bh[OP - 1] = load_opT(yh, oy, OP - 1, KS);
     else if constexpr (OP < 8) o.ah[OP - 4] = load_opT(xh, ox, OP - 4, KS);
@@ -564,7 +575,7 @@ __device__ __forceinline__ void fwd1_read(const char *buf, const OpBase &ox, con
     else o.al[OP - 12] = load_opT(xl, ox, OP - 12, KS);
 }
 
-// MFMA `i` (0..47) of one K step: pass hi*hi, then hi*lo, then lo*hi, each over the 16 accumulator
+// MFMA I (0..47) of one K step: pass hi*hi, then hi*lo, then lo*hi, each over the 16 accumulator
 // tiles a-major, so consecutive MFMAs never share an accumulator.
 template <int I>
 __device__ __forceinline__ void fwd1_mfma(const FwdOps1 &o, f32x16 (&acc)[4][4]) {
@@ -574,14 +585,11 @@ __device__ __forceinline__ void fwd1_mfma(const FwdOps1 &o, f32x16 (&acc)[4][4])
     acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, acc[a][b], 0, 0, 0);
 }
 
-// Slot I of a chunk: MFMA I, the operand read and the generator stages assigned to it, then a
-// scheduling fence so that the compiler keeps this interleaving.
 struct Fwd1Ctx {
-    const char *cur;
-    char *nxt;
+    char *smem;
     const OpBase &ox, &oy;
     f32x16 (&acc)[4][4];
-    RunStages &gx, &gy;
+    RunStages &gx, &gy;            // generator of the next chunk (records of the next chunk)
     FwdOps1 &o0, &o1;
     int ux, uy, k, r;
 };
@@ -592,51 +600,49 @@ struct Fwd1Ctx {
 template <int OP>
 constexpr int fwd1_read0_slot() { return OP < 5 ? 84 + OP : OP - 5; }
 
-template <int I, int... OP>
-__device__ __forceinline__ void fwd1_reads0_at(const char *buf, Fwd1Ctx &c, std::integer_sequence<int, OP...>) {
-    ((I == fwd1_read0_slot<OP>() ? fwd1_read<0, OP>(buf, c.ox, c.oy, c.o0) : void()), ...);
+template <int I, int B, int... OP>
+__device__ __forceinline__ void fwd1_reads0_at(Fwd1Ctx &c, std::integer_sequence<int, OP...>) {
+    ((I == fwd1_read0_slot<OP>() ? fwd1_read<0, OP, B>(c.smem, c.ox, c.oy, c.o0) : void()), ...);
 }
 
-template <int I>
+// Slot I of a chunk that contracts buffer B and generates into buffer 1 - B.
+template <int I, int B>
 __device__ __forceinline__ void fwd1_slot(Fwd1Ctx &c) {
+    constexpr int N = 1 - B;
     if constexpr (I < 48) fwd1_mfma<I>(c.o0, c.acc);
     else fwd1_mfma<I - 48>(c.o1, c.acc);
-    if constexpr (I >= 12 && I < 44 && (I & 1) == 0) fwd1_read<1, (I - 12) / 2>(c.cur, c.ox, c.oy, c.o1);
+    if constexpr (I >= 12 && I < 44 && (I & 1) == 0) fwd1_read<1, (I - 12) / 2, B>(c.smem, c.ox, c.oy, c.o1);
     constexpr int Y0 = RunStages::kStages;   // the Y run's stages follow the X run's
-    if constexpr (I < Y0) c.gx.template stage<I>(c.ux, c.nxt, c.nxt + FARR, c.k, c.r);
+    if constexpr (I < Y0) c.gx.template stage<I>(c.ux, c.smem + F1_XH(N), c.smem + F1_XL(N), c.k, c.r);
     if constexpr (I >= Y0 && I < 2 * Y0)
-        c.gy.template stage<I - Y0>(c.uy, c.nxt + 2 * FARR, c.nxt + 3 * FARR, c.k, c.r);
+        c.gy.template stage<I - Y0>(c.uy, c.smem + F1_YH(N), c.smem + F1_YL(N), c.k, c.r);
     // The generator's last store is in slot 2 Y0 - 1 = 81: after the barrier the next chunk's tiles
     // are complete (its first step-0 operands are read in the following slots, well before the
     // next chunk's first MFMA) and this chunk's buffer is free for the next chunk's generator.
     static_assert(2 * RunStages::kStages - 1 == 81, "slot plan");
     if constexpr (I == 81) lds_barrier();
-    if constexpr (I >= 84 && I <= 88) fwd1_reads0_at<I>(c.nxt, c, std::make_integer_sequence<int, 5>{});
-    if constexpr (I <= 10) fwd1_reads0_at<I>(c.cur, c, std::make_integer_sequence<int, 16>{});
+    if constexpr (I >= 84 && I <= 88) fwd1_reads0_at<I, N>(c, std::make_integer_sequence<int, 5>{});
+    if constexpr (I <= 10) fwd1_reads0_at<I, B>(c, std::make_integer_sequence<int, 16>{});
     __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int... I>
-__device__ __forceinline__ void fwd1_reads0(const char *buf, const OpBase &ox, const OpBase &oy, FwdOps1 &o,
-                                            std::integer_sequence<int, I...>) {
-    (fwd1_read<0, I>(buf, ox, oy, o), ...);
-}
-
-template <int... I>
+template <int B, int... I>
 __device__ __forceinline__ void fwd1_slots(Fwd1Ctx &c, std::integer_sequence<int, I...>) {
-    (fwd1_slot<I>(c), ...);
+    (fwd1_slot<I, B>(c), ...);
 }
 
-// One chunk: contract `cur` into acc while generating the next chunk's X and Y runs into `nxt`.
-// 96 slots of one MFMA each; the step-0 operands are read in slots 84-88 of the previous chunk and
-// 0-10 of this one, the step-1 operands one every two slots from slot 12; the X run's stages occupy
-// slots 0-40, the Y run's slots 41-81; the chunk's one barrier follows slot 81.
-__device__ __forceinline__ void fwd1_chunk(const char *cur, char *nxt, const OpBase &ox, const OpBase &oy,
-                                           f32x16 (&acc)[4][4], RunStages &gx, RunStages &gy, FwdOps1 &o0,
-                                           int ux, int uy, int k, int r) {
+// One chunk: contract buffer B into acc while generating the next chunk's X and Y runs into
+// buffer 1 - B.  96 slots of one MFMA each; the step-0 operands are read in slots 84-88 of the
+// previous chunk and 0-10 of this one, the step-1 operands one every two slots from slot 12; the
+// X run's stages occupy slots 0-40, the Y run's slots 41-81; the chunk's one barrier follows
+// slot 81.
+template <int B>
+__device__ __forceinline__ void fwd1_chunk(char *smem, const OpBase &ox, const OpBase &oy, f32x16 (&acc)[4][4],
+                                           RunStages &gx, RunStages &gy, FwdOps1 &o0, int ux, int uy, int k,
+                                           int r) {
     FwdOps1 o1;
-    Fwd1Ctx c{cur, nxt, ox, oy, acc, gx, gy, o0, o1, ux, uy, k, r};
-    fwd1_slots(c, std::make_integer_sequence<int, 96>{});
+    Fwd1Ctx c{smem, ox, oy, acc, gx, gy, o0, o1, ux, uy, k, r};
+    fwd1_slots<B>(c, std::make_integer_sequence<int, 96>{});
 }
 
 __global__ __launch_bounds__(256) void k_fwd1_bf16(int64_t n, int Mu, int Mp, const PhaseRec *__restrict__ tx,
@@ -659,33 +665,45 @@ __global__ __launch_bounds__(256) void k_fwd1_bf16(int64_t n, int Mu, int Mp, co
     OpBase ox, oy;
     ox.init(wu, lane);
     oy.init(wp, lane);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int rd = 0; rd < 2; ++rd) oy.b[a][rd] += F1_YH(0);
 
     // Thread tid generates block k = tid % 32 of each chunk, frequencies 32 r .. + 31 of the tile.
     const int kk = tid & 31, rr = tid >> 5;
     const int ux = tu0 + 32 * rr, uy = tp0 + 32 * rr;
     if (c_begin < c_end) {
-        fwd_gen<true>(load_rec_padded(tx, c_begin, kk), tu0, smem, smem + FARR, tid);
-        fwd_gen<true>(load_rec_padded(ty, c_begin, kk), tp0, smem + 2 * FARR, smem + 3 * FARR, tid);
+        fwd_gen<true>(load_rec_padded(tx, c_begin, kk), tu0, smem + F1_XH(0), smem + F1_XL(0), tid);
+        fwd_gen<true>(load_rec_padded(ty, c_begin, kk), tp0, smem + F1_YH(0), smem + F1_YL(0), tid);
     }
-    // The records of the chunk generated during an iteration are fetched one iteration earlier.
+    // Two record sets alternate: the chunk at even offset from c_begin generates from set B and
+    // fetches the records of the chunk after next into set A, the chunk at odd offset the reverse.
     // (Past the range: zero records or records of the next split, generated into the idle buffer
     // and never read.)
-    RunStages gx, gy;
-    gx.R = load_rec_padded(tx, c_begin + 1, kk);
-    gy.R = load_rec_padded(ty, c_begin + 1, kk);
+    RunStages gxA, gyA, gxB, gyB;
+    gxB.R = load_rec_padded(tx, c_begin + 1, kk);
+    gyB.R = load_rec_padded(ty, c_begin + 1, kk);
     lds_barrier();
     FwdOps1 o0;
-    fwd1_reads0(smem, ox, oy, o0, std::make_integer_sequence<int, 5>{});
+    fwd1_read<0, 0, 0>(smem, ox, oy, o0);
+    fwd1_read<0, 1, 0>(smem, ox, oy, o0);
+    fwd1_read<0, 2, 0>(smem, ox, oy, o0);
+    fwd1_read<0, 3, 0>(smem, ox, oy, o0);
+    fwd1_read<0, 4, 0>(smem, ox, oy, o0);
     // Nothing the prologue loaded may still be in flight at the loop head (the compiler would then
     // wait for every load and LDS read at the first use in each iteration).
     asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
-    for (int64_t c = c_begin; c < c_end; ++c) {
-        const int bsel = (int)((c - c_begin) & 1);
-        const GenRec nx = load_rec_padded(tx, c + 2, kk), ny = load_rec_padded(ty, c + 2, kk);
-        fwd1_chunk(smem + bsel * FBUF, smem + (bsel ^ 1) * FBUF, ox, oy, acc, gx, gy, o0, ux, uy, kk, rr);
-        gx.R = nx;
-        gy.R = ny;
+    int64_t c = c_begin;
+    for (; c + 1 < c_end; c += 2) {
+        gxA.R = load_rec_padded(tx, c + 2, kk);
+        gyA.R = load_rec_padded(ty, c + 2, kk);
+        fwd1_chunk<0>(smem, ox, oy, acc, gxB, gyB, o0, ux, uy, kk, rr);
+        gxB.R = load_rec_padded(tx, c + 3, kk);
+        gyB.R = load_rec_padded(ty, c + 3, kk);
+        fwd1_chunk<1>(smem, ox, oy, acc, gxA, gyA, o0, ux, uy, kk, rr);
     }
+    if (c < c_end) fwd1_chunk<0>(smem, ox, oy, acc, gxB, gyB, o0, ux, uy, kk, rr);
 
     float *out = part + (size_t)blockIdx.y * (size_t)Mu * (size_t)Mp;
 #pragma unroll
