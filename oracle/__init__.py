@@ -57,6 +57,9 @@ def _load():
     lib.oracle_coeffs_sampled.argtypes = [d, d, i64, _dp, _dp, _dp, _dp, i32, _ip, _ip, _dp, _dp]
     lib.oracle_point_field.argtypes = [d, d, i32, i32, _dp, i64, _dp, _dp, _dp, _dp, _dp]
     lib.oracle_block_potential.argtypes = [d, d, i64, _dp, _dp, _dp, _dp, i32, i32, _dp, _dp]
+    lib.oracle_bin_density.argtypes = [d, d, i64, _dp, _dp, _dp, _dp, i32, _dp]
+    lib.oracle_bin_coeffs.argtypes = [d, d, i32, _dp, i32, i32, _dp]
+    lib.oracle_bin_field.argtypes = [d, d, i32, i32, i32, _dp, _dp, _dp, _dp]
     lib.oracle_num_threads.argtypes = []
     for f in ("oracle_coeffs", "oracle_energy", "oracle_grad", "oracle_grad_sampled",
               "oracle_coeffs_sampled", "oracle_point_field", "oracle_block_potential",
@@ -175,3 +178,34 @@ def block_potential(W, H, x, y, w, h, a):
     _check(lib.oracle_block_potential(W, H, n, *[p for _, p in xs], a.shape[0], a.shape[1], pa,
                                       N.ctypes.data_as(_dp)), "block_potential")
     return N
+
+
+def bin_density(W, H, x, y, w, h, m):
+    """Bin densities P[l, j] of an m x m grid (Sec. III-D): exact overlap areas over the bin area."""
+    lib = _load()
+    xs = [_f64(v) for v in (x, y, w, h)]
+    n = xs[0][0].shape[0]
+    P = np.zeros((m, m))
+    _check(lib.oracle_bin_density(W, H, n, *[p for _, p in xs], m, P.ctypes.data_as(_dp)), "bin_density")
+    return P
+
+
+def bin_coeffs(W, H, P, Mu, Mp):
+    """Binned coefficients a[u, p] (Sec. III-D, eqs. disa-a..d) of the bin densities P (m x m)."""
+    lib = _load()
+    P, pP = _f64(P)
+    m = P.shape[0]
+    a = np.zeros((Mu, Mp))
+    _check(lib.oracle_bin_coeffs(W, H, m, pP, Mu, Mp, a.ctypes.data_as(_dp)), "bin_coeffs")
+    return a
+
+
+def bin_field(W, H, m, a):
+    """psi, xi_x, xi_y at the centres of the m x m bins (eqs. dis-psi1, dis-ksi), truncated at a."""
+    lib = _load()
+    a, pa = _f64(a)
+    Mu, Mp = a.shape
+    psi, xix, xiy = np.zeros((m, m)), np.zeros((m, m)), np.zeros((m, m))
+    _check(lib.oracle_bin_field(W, H, m, Mu, Mp, pa, psi.ctypes.data_as(_dp), xix.ctypes.data_as(_dp),
+                                xiy.ctypes.data_as(_dp)), "bin_field")
+    return psi, xix, xiy

@@ -43,6 +43,25 @@
  *  5. Point values of the potential psi (eq. psi) and field xi (eq. ksi), and the block
  *     potentials N_i = iint_{block i} psi = sum_up a_up Xbar_iu Ybar_ip.
  *
+ *  6. The bin scheme of Sec. III-D (a comparison path): an m x m grid of bins of size
+ *     wb = W/m, hb = H/m with centres x_l = (l + 1/2) wb, y_j = (j + 1/2) hb;
+ *       - bin densities P_lj = (area of the blocks inside bin lj) / (wb hb), read as the exact
+ *         overlap areas (the paper's "local smoothness" is not specified and is not applied);
+ *       - the binned coefficients of eqs. disa-a..d, i.e. the coefficients of the density
+ *         sum_lj P_lj [bin lj] minus its mean (eq. rho-dis), as plain double sums over the bins:
+ *           a_00 = 0,
+ *           a_0p = 4 H^2 / (p^3 pi^3 m) sin(p pi/(2m)) sum_lj P_lj cos(p (j+1/2) pi/m),
+ *           a_u0 = 4 W^2 / (u^3 pi^3 m) sin(u pi/(2m)) sum_lj P_lj cos(u (l+1/2) pi/m),
+ *           a_up = 16 W^2 H^2 / (u p (u^2 H^2 + p^2 W^2) pi^4) sin(u pi/(2m)) sin(p pi/(2m))
+ *                  * sum_lj P_lj cos(u (l+1/2) pi/m) cos(p (j+1/2) pi/m)
+ *         (the cosine argument of eq. disa-c, garbled in the text, is read as u (l + 1/2) pi/m);
+ *       - the potential and field at the bin centres truncated at the coefficient array
+ *         (eqs. dis-psi1 and dis-ksi):
+ *           psi(l,j) = sum_up a_up cos(u (l+1/2) pi/m) cos(p (j+1/2) pi/m),
+ *           xi_x(l,j) = sum_up (u pi/W) a_up sin(u (l+1/2) pi/m) cos(p (j+1/2) pi/m),
+ *           xi_y(l,j) = sum_up (p pi/H) a_up cos(u (l+1/2) pi/m) sin(p (j+1/2) pi/m).
+ *     Cosines and sines of k (2l+1) pi/(2m) take the integer k (2l+1) modulo 4m first.
+ *
  * Truncation: u in [0, Mu), p in [0, Mp).  Coefficient arrays are row-major, a[u*Mp + p].
  */
 #include <math.h>
@@ -387,4 +406,107 @@ int oracle_block_potential(double W, double H, int64_t n, const double *x, const
         free(Xb);
     }
     return fail ? -1 : 0;
+}
+
+
+/* ---------------------------------------------------------------------------------------------
+ * 6. Bin scheme (Sec. III-D).  Bin arrays are row-major over (l, j): P[l*m + j].
+ * ------------------------------------------------------------------------------------------- */
+
+/* cos and sin of k (2s+1) pi / (2m), the argument reduced exactly modulo 4m first. */
+static void bin_trig(long k, long s, long m, double *c, double *sn)
+{
+    long q = (k * (2 * s + 1)) % (4 * m);
+    double phi = ORACLE_PI * (double)q / (2.0 * (double)m);
+    *c = cos(phi);
+    *sn = sin(phi);
+}
+
+/* Bin densities: the overlap area of every block with every bin, over the bin area. */
+int oracle_bin_density(double W, double H, int64_t n, const double *x, const double *y,
+                       const double *w, const double *h, int m, double *P)
+{
+    if (m <= 0 || W <= 0.0 || H <= 0.0) return -1;
+    const double wb = W / m, hb = H / m;
+    long double *acc = (long double *)calloc((size_t)m * m, sizeof(long double));
+    if (!acc) return -2;
+    for (int64_t i = 0; i < n; ++i) {
+        const double x0 = x[i] - w[i] / 2.0, x1 = x[i] + w[i] / 2.0;
+        const double y0 = y[i] - h[i] / 2.0, y1 = y[i] + h[i] / 2.0;
+        for (int l = 0; l < m; ++l) {
+            const double ox = fmin(x1, (l + 1) * wb) - fmax(x0, l * wb);
+            if (ox <= 0.0) continue;
+            for (int j = 0; j < m; ++j) {
+                const double oy = fmin(y1, (j + 1) * hb) - fmax(y0, j * hb);
+                if (oy <= 0.0) continue;
+                acc[(size_t)l * m + j] += (long double)(ox * oy);
+            }
+        }
+    }
+    for (size_t k = 0; k < (size_t)m * m; ++k) P[k] = (double)(acc[k] / ((long double)wb * hb));
+    free(acc);
+    return 0;
+}
+
+/* Binned coefficients a[u*Mp + p] (eqs. disa-a..d), u < Mu, p < Mp. */
+int oracle_bin_coeffs(double W, double H, int m, const double *P, int Mu, int Mp, double *a)
+{
+    if (m <= 0 || Mu <= 0 || Mp <= 0) return -1;
+    const double pi = ORACLE_PI;
+    int st = 0;
+#pragma omp parallel for schedule(dynamic)
+    for (int u = 0; u < Mu; ++u) {
+        for (int p = 0; p < Mp; ++p) {
+            long double sum = 0.0L;
+            for (int l = 0; l < m; ++l) {
+                double cu, su;
+                bin_trig(u, l, m, &cu, &su);
+                for (int j = 0; j < m; ++j) {
+                    double cp, sp;
+                    bin_trig(p, j, m, &cp, &sp);
+                    sum += (long double)P[(size_t)l * m + j] * cu * cp;
+                }
+            }
+            double f;
+            if (u == 0 && p == 0) f = 0.0;
+            else if (u == 0) f = 4.0 * H * H / ((double)p * p * p * pi * pi * pi * m) * sin(p * pi / (2.0 * m));
+            else if (p == 0) f = 4.0 * W * W / ((double)u * u * u * pi * pi * pi * m) * sin(u * pi / (2.0 * m));
+            else
+                f = 16.0 * W * W * H * H / ((double)u * p * ((double)u * u * H * H + (double)p * p * W * W) *
+                                            pi * pi * pi * pi) *
+                    sin(u * pi / (2.0 * m)) * sin(p * pi / (2.0 * m));
+            a[(size_t)u * Mp + p] = (double)(f * sum);
+        }
+    }
+    return st;
+}
+
+/* Potential and field at the bin centres (eqs. dis-psi1, dis-ksi); NULL outputs are skipped. */
+int oracle_bin_field(double W, double H, int m, int Mu, int Mp, const double *a, double *psi,
+                     double *xix, double *xiy)
+{
+    if (m <= 0 || Mu <= 0 || Mp <= 0) return -1;
+    const double pi = ORACLE_PI;
+#pragma omp parallel for schedule(dynamic)
+    for (int l = 0; l < m; ++l) {
+        double *cu = (double *)malloc(sizeof(double) * (size_t)(2 * Mu + 2 * Mp));
+        double *su = cu + Mu, *cp = su + Mu, *sp = cp + Mp;
+        for (int u = 0; u < Mu; ++u) bin_trig(u, l, m, &cu[u], &su[u]);
+        for (int j = 0; j < m; ++j) {
+            for (int p = 0; p < Mp; ++p) bin_trig(p, j, m, &cp[p], &sp[p]);
+            long double e = 0.0L, ex = 0.0L, ey = 0.0L;
+            for (int u = 0; u < Mu; ++u)
+                for (int p = 0; p < Mp; ++p) {
+                    const double apu = a[(size_t)u * Mp + p];
+                    e += (long double)apu * cu[u] * cp[p];
+                    ex += (long double)((double)u * pi / W) * apu * su[u] * cp[p];
+                    ey += (long double)((double)p * pi / H) * apu * cu[u] * sp[p];
+                }
+            if (psi) psi[(size_t)l * m + j] = (double)e;
+            if (xix) xix[(size_t)l * m + j] = (double)ex;
+            if (xiy) xiy[(size_t)l * m + j] = (double)ey;
+        }
+        free(cu);
+    }
+    return 0;
 }

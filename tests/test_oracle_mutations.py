@@ -34,6 +34,14 @@ MUTANTS = {
                              "edge_diffs(u + 1, x[i], w[i], W, &S, &K); Sc[j * Mu + u] = S;"),
     "point field drops the frequency factor": ("ex += ((double)u * ORACLE_PI / W) * su[u] * zc;",
                                                "ex += su[u] * zc;"),
+    "bin centre without the half bin": ("long q = (k * (2 * s + 1)) % (4 * m);", "long q = (k * (2 * s)) % (4 * m);"),
+    "bin a_up constant 16 -> 8": ("f = 16.0 * W * W * H * H /", "f = 8.0 * W * W * H * H /"),
+    "bin sine factor uses pi/m": ("sin(u * pi / (2.0 * m)) * sin(p * pi / (2.0 * m));",
+                                  "sin(u * pi / (1.0 * m)) * sin(p * pi / (2.0 * m));"),
+    "bin density over the bin width only": ("P[k] = (double)(acc[k] / ((long double)wb * hb));",
+                                            "P[k] = (double)(acc[k] / ((long double)wb));"),
+    "bin field xi_y uses the x frequency": ("ey += (long double)((double)p * pi / H) * apu * cu[u] * sp[p];",
+                                            "ey += (long double)((double)u * pi / W) * apu * cu[u] * sp[p];"),
     "block potential y integral": ("for (int p = 0; p < Mp; ++p) Yb[p] = edge_integral(p, y[i], h[i], H);",
                                    "for (int p = 0; p < Mp; ++p) Yb[p] = edge_integral(p, y[i], w[i], H);"),
 }

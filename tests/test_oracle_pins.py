@@ -410,3 +410,105 @@ def test_rank1_central_difference_helper():
     xm = x.copy(); xm[i] -= 1e-3
     bf = (_E(W, H, xp, y, w, h, wl.Mu, wl.Mp) - _E(W, H, xm, y, w, h, wl.Mu, wl.Mp)) / 2e-3
     assert abs(bf - fx[1]) < 1e-7 * sc
+
+
+# ---------------------------------------------------------------------------------------------
+# Bin scheme (Sec. III-D), the comparison path.
+# ---------------------------------------------------------------------------------------------
+def test_bin_density_hand_case():
+    # W = H = 4, m = 4 (unit bins); one block over x in [0.5, 2], y in [1, 2]: half of bin (0, 1)
+    # and all of bin (1, 1).  A second block overhangs the region's corner: only its inside part
+    # [3.5, 4] x [3.5, 4] counts, a quarter of bin (3, 3).
+    P = oracle.bin_density(4.0, 4.0, [1.25, 4.0], [1.5, 4.0], [1.5, 1.0], [1.0, 1.0], 4)
+    ref = np.zeros((4, 4))
+    ref[0, 1], ref[1, 1], ref[3, 3] = 0.5, 1.0, 0.25
+    assert np.array_equal(P, ref)
+
+
+def test_bin_density_exact_by_lattice_sampling():
+    # Block edges on a lattice of 1/8 bin: sampling the lattice cell midpoints counts every cell
+    # exactly, so the sampled bin areas are exact (an independent brute force).
+    rng = np.random.default_rng(11)
+    W, H, m, q = 6.0, 3.0, 6, 8
+    wb, hb = W / m, H / m
+    n = 40
+    x0 = rng.integers(-4, m * q, n) * wb / q
+    y0 = rng.integers(-4, m * q, n) * hb / q
+    w = rng.integers(1, 3 * q, n) * wb / q
+    h = rng.integers(1, 3 * q, n) * hb / q
+    P = oracle.bin_density(W, H, x0 + w / 2, y0 + h / 2, w, h, m)
+    xs = (np.arange(m * q) + 0.5) * wb / q
+    ys = (np.arange(m * q) + 0.5) * hb / q
+    cover = np.zeros((m * q, m * q))
+    for i in range(n):
+        inx = (xs > x0[i]) & (xs < x0[i] + w[i])
+        iny = (ys > y0[i]) & (ys < y0[i] + h[i])
+        cover += np.outer(inx, iny)
+    ref = cover.reshape(m, q, m, q).sum(axis=(1, 3)) / (q * q)
+    assert np.abs(P - ref).max() <= 1e-12
+
+
+def test_bin_density_total_area():
+    rng = np.random.default_rng(3)
+    W, H, m, n = 10.0, 7.0, 9, 200
+    x, y = rng.uniform(-1, W + 1, n), rng.uniform(-1, H + 1, n)
+    w, h = rng.uniform(0.05, 3.0, n), rng.uniform(0.05, 2.0, n)
+    P = oracle.bin_density(W, H, x, y, w, h, m)
+    inside = (np.clip(np.minimum(x + w / 2, W) - np.maximum(x - w / 2, 0), 0, None)
+              * np.clip(np.minimum(y + h / 2, H) - np.maximum(y - h / 2, 0), 0, None))
+    assert P.sum() * (W / m) * (H / m) == pytest.approx(inside.sum(), rel=1e-13)
+
+
+def _disa_from_dct(W, H, P, Mu, Mp):
+    """Eqs. disa-a..d with the double sums taken by scipy's DCT-II."""
+    m = P.shape[0]
+    D = scipy.fft.dctn(P, type=2) / 4.0
+    ref = np.zeros((Mu, Mp))
+    uu, pp = np.meshgrid(np.arange(1, Mu), np.arange(1, Mp), indexing="ij")
+    ref[1:, 1:] = (16 * W**2 * H**2 / (uu * pp * (uu**2 * H**2 + pp**2 * W**2) * PI**4)
+                   * np.sin(uu * PI / (2 * m)) * np.sin(pp * PI / (2 * m)) * D[1:Mu, 1:Mp])
+    pr, ur = np.arange(1, Mp), np.arange(1, Mu)
+    ref[0, 1:] = 4 * H**2 / (pr**3 * PI**3 * m) * np.sin(pr * PI / (2 * m)) * D[0, 1:Mp]
+    ref[1:, 0] = 4 * W**2 / (ur**3 * PI**3 * m) * np.sin(ur * PI / (2 * m)) * D[1:Mu, 0]
+    return ref
+
+
+@pytest.mark.parametrize("W,H,m,Mu,Mp", [(12.0, 5.0, 6, 6, 6), (3.0, 8.0, 10, 7, 10), (9.0, 9.0, 16, 16, 5)])
+def test_bin_coeffs_match_dct2(W, H, m, Mu, Mp):
+    P = np.random.default_rng(m).uniform(0.0, 2.0, (m, m))
+    a = oracle.bin_coeffs(W, H, P, Mu, Mp)
+    ref = _disa_from_dct(W, H, P, Mu, Mp)
+    assert np.abs(a - ref).max() <= 1e-13 * np.abs(ref).max()
+    assert a[0, 0] == 0.0
+
+
+def test_bin_coeffs_equal_direct_sum_of_bin_blocks():
+    # Whole-bin occupancy: the binned coefficients are the exact coefficients of the blocks.
+    W, H, m = 8.0, 6.0, 8
+    occ = np.random.default_rng(5).integers(0, 2, (m, m))
+    l, j = np.nonzero(occ)
+    xs, ys = (l + 0.5) * W / m, (j + 0.5) * H / m
+    a_dir, _ = oracle.coeffs(W, H, xs, ys, np.full(len(xs), W / m), np.full(len(xs), H / m), m, m)
+    P = oracle.bin_density(W, H, xs, ys, np.full(len(xs), W / m), np.full(len(xs), H / m), m)
+    assert np.array_equal(P, occ.astype(float))
+    a_bin = oracle.bin_coeffs(W, H, P, m, m)
+    assert np.abs(a_bin - a_dir).max() <= 1e-13 * np.abs(a_dir).max()
+
+
+@pytest.mark.parametrize("W,H,m,Mu,Mp", [(12.0, 5.0, 6, 6, 6), (4.0, 9.0, 9, 5, 9)])
+def test_bin_field_matches_dct3_and_point_field(W, H, m, Mu, Mp):
+    a = np.random.default_rng(m + Mu).normal(size=(Mu, Mp))
+    psi, xix, xiy = oracle.bin_field(W, H, m, a)
+    # psi by scipy's DCT-III: y_k = x_0 + 2 sum_{n>=1} x_n cos(pi n (2k+1)/(2m)) on each axis
+    ap = np.zeros((m, m))
+    ap[:Mu, :Mp] = a
+    ap[1:, :] /= 2.0
+    ap[:, 1:] /= 2.0
+    ref = scipy.fft.dctn(ap, type=3)
+    assert np.abs(psi - ref).max() <= 1e-13 * np.abs(ref).max()
+    # psi and xi at the bin centres by the point evaluation of eqs. psi, ksi
+    xc, yc = (np.arange(m) + 0.5) * W / m, (np.arange(m) + 0.5) * H / m
+    X, Y = np.meshgrid(xc, yc, indexing="ij")
+    ps, ex, ey = oracle.point_field(W, H, a, X.ravel(), Y.ravel())
+    for got, want in ((psi, ps), (xix, ex), (xiy, ey)):
+        assert np.abs(got.ravel() - want).max() <= 1e-13 * np.abs(want).max()
