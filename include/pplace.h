@@ -142,6 +142,50 @@ int pp_point_field(const pp_problem *P, const double *px, const double *py, cons
 int pp_block_potential(const pp_problem *P, const double *x, const double *y, const double *w, const double *h,
                        const double *a, double *N, void *ws, size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------------------------------------
+ * Bin scheme (Sec. III-D), a comparison path for the direct sum above.  The region is cut into
+ * m x m bins of size wb = W/m, hb = H/m, centres x_l = (l + 1/2) wb, y_j = (j + 1/2) hb.  All
+ * arithmetic is FP64; bin arrays are row-major, P[l * m + j] (l: x bin, j: y bin).
+ * --------------------------------------------------------------------------------------------- */
+typedef struct pp_bin_problem {
+    double W, H;         /* region [0, W] x [0, H]; finite, > 0 */
+    int64_t n;           /* blocks (pp_bin_density), 0 <= n < 2^31 */
+    int32_t m;           /* bins per axis, 1 <= m <= 16384 */
+    int32_t Mu, Mp;      /* truncation u in [0, Mu), p in [0, Mp); 1 <= Mu, Mp <= m */
+} pp_bin_problem;
+
+/* Bytes of device workspace that the pp_bin_* calls need for B (one size serves all three).
+ * Host only. */
+int pp_bin_workspace_size(const pp_bin_problem *B, size_t *bytes);
+
+/* Bin densities (Sec. III-D, the density of bin b_lj): P_lj = area of the blocks inside bin lj
+ * divided by wb hb, taken as the exact overlap areas (the "local smoothness" of the text is not
+ * specified and is not applied); block parts outside the region lie in no bin.
+ * x, y, w, h: in [B->n] FP64 blocks.  P: out [m * m] FP64.  FP64 atomic sums: the last bits may
+ * differ between runs. */
+int pp_bin_density(const pp_bin_problem *B, const double *x, const double *y, const double *w, const double *h,
+                   double *P, void *ws, size_t ws_bytes, void *stream);
+
+/* Binned coefficients (Sec. III-D, eqs. disa-a..d): the coefficients of the density
+ * sum_lj P_lj [bin lj] minus its mean (eq. rho-dis), for u < Mu, p < Mp:
+ *   a_00 = 0,
+ *   a_0p = 4 H^2 / (p^3 pi^3 m) sin(p pi/(2m)) sum_lj P_lj cos(p (j + 1/2) pi/m),
+ *   a_u0 = 4 W^2 / (u^3 pi^3 m) sin(u pi/(2m)) sum_lj P_lj cos(u (l + 1/2) pi/m),
+ *   a_up = 16 W^2 H^2 sin(u pi/(2m)) sin(p pi/(2m)) / (u p (u^2 H^2 + p^2 W^2) pi^4)
+ *          * sum_lj P_lj cos(u (l + 1/2) pi/m) cos(p (j + 1/2) pi/m).
+ * P: in [m * m] FP64 (pp_bin_density, or any bin densities).  a: out [Mu * Mp] FP64. */
+int pp_bin_coeffs(const pp_bin_problem *B, const double *P, double *a, void *ws, size_t ws_bytes, void *stream);
+
+/* Potential and field at the bin centres, truncated at the coefficient array (Sec. III-D,
+ * eqs. dis-psi1 and dis-ksi):
+ *   psi[l, j] = sum_up a_up cos(u (l + 1/2) pi/m) cos(p (j + 1/2) pi/m),
+ *   xix[l, j] = sum_up (u pi/W) a_up sin(u (l + 1/2) pi/m) cos(p (j + 1/2) pi/m),
+ *   xiy[l, j] = sum_up (p pi/H) a_up cos(u (l + 1/2) pi/m) sin(p (j + 1/2) pi/m).
+ * a: in [Mu * Mp] FP64 (pp_bin_coeffs, or the direct-sum coefficients for comparison).
+ * psi, xix, xiy: out [m * m] FP64, each may be NULL (not computed). */
+int pp_bin_field(const pp_bin_problem *B, const double *a, double *psi, double *xix, double *xiy, void *ws,
+                 size_t ws_bytes, void *stream);
+
 /* Static description of a status code. */
 const char *pp_strerror(int status);
 
@@ -155,7 +199,8 @@ const char *pp_strerror(int status);
  * partials), "energy" (final energy sum), "prep" (row-form operands), "bwd" (the two gradient
  * contractions, one record each), "final" (per-block partial sums), "build" (store-mode basis
  * tables), "point" (pp_point_field
- * contractions), "potential" (pp_block_potential contraction).  Unknown names give count 0.
+ * contractions), "potential" (pp_block_potential contraction), "bin_density", "bin_coeffs",
+ * "bin_field" (the bin scheme, all launches of one call in one record).  Unknown names give count 0.
  * Returns PP_OK, PP_ERR_ARG for NULL arguments, PP_ERR_DEVICE if an event query fails.  Recording
  * is process wide and guarded by a lock; it is meant for benchmarks, not for production calls. */
 int pp_timing_enable(int on);

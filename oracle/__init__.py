@@ -60,6 +60,8 @@ def _load():
     lib.oracle_bin_density.argtypes = [d, d, i64, _dp, _dp, _dp, _dp, i32, _dp]
     lib.oracle_bin_coeffs.argtypes = [d, d, i32, _dp, i32, i32, _dp]
     lib.oracle_bin_field.argtypes = [d, d, i32, i32, i32, _dp, _dp, _dp, _dp]
+    lib.oracle_bin_density_at.argtypes = [d, d, i64, _dp, _dp, _dp, _dp, i32, i64, _ip, _ip, _dp]
+    lib.oracle_bin_coeffs_at.argtypes = [d, d, i32, _dp, i64, _ip, _ip, _dp]
     lib.oracle_num_threads.argtypes = []
     for f in ("oracle_coeffs", "oracle_energy", "oracle_grad", "oracle_grad_sampled",
               "oracle_coeffs_sampled", "oracle_point_field", "oracle_block_potential",
@@ -209,3 +211,28 @@ def bin_field(W, H, m, a):
     _check(lib.oracle_bin_field(W, H, m, Mu, Mp, pa, psi.ctypes.data_as(_dp), xix.ctypes.data_as(_dp),
                                 xiy.ctypes.data_as(_dp)), "bin_field")
     return psi, xix, xiy
+
+
+def bin_density_at(W, H, x, y, w, h, m, ls, js):
+    """Selected bin densities P[ls[k], js[k]] (for grids too large for bin_density)."""
+    lib = _load()
+    xs = [_f64(v) for v in (x, y, w, h)]
+    n = xs[0][0].shape[0]
+    ls = np.ascontiguousarray(ls, dtype=np.int32)
+    js = np.ascontiguousarray(js, dtype=np.int32)
+    out = np.zeros(len(ls))
+    _check(lib.oracle_bin_density_at(W, H, n, *[p for _, p in xs], m, len(ls), ls.ctypes.data_as(_ip),
+                                     js.ctypes.data_as(_ip), out.ctypes.data_as(_dp)), "bin_density_at")
+    return out
+
+
+def bin_coeffs_at(W, H, P, us, ps):
+    """Selected binned coefficients a[us[k], ps[k]] of the bin densities P (m x m)."""
+    lib = _load()
+    P, pP = _f64(P)
+    us = np.ascontiguousarray(us, dtype=np.int32)
+    ps = np.ascontiguousarray(ps, dtype=np.int32)
+    out = np.zeros(len(us))
+    _check(lib.oracle_bin_coeffs_at(W, H, P.shape[0], pP, len(us), us.ctypes.data_as(_ip), ps.ctypes.data_as(_ip),
+                                    out.ctypes.data_as(_dp)), "bin_coeffs_at")
+    return out

@@ -510,3 +510,56 @@ int oracle_bin_field(double W, double H, int m, int Mu, int Mp, const double *a,
     }
     return 0;
 }
+
+/* Selected bin densities P[ls[k], js[k]] (the same sums as oracle_bin_density, for large grids). */
+int oracle_bin_density_at(double W, double H, int64_t n, const double *x, const double *y,
+                          const double *w, const double *h, int m, int64_t count, const int *ls,
+                          const int *js, double *out)
+{
+    if (m <= 0 || W <= 0.0 || H <= 0.0) return -1;
+    const double wb = W / m, hb = H / m;
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t k = 0; k < count; ++k) {
+        const int l = ls[k], j = js[k];
+        long double acc = 0.0L;
+        for (int64_t i = 0; i < n; ++i) {
+            const double ox = fmin(x[i] + w[i] / 2.0, (l + 1) * wb) - fmax(x[i] - w[i] / 2.0, l * wb);
+            const double oy = fmin(y[i] + h[i] / 2.0, (j + 1) * hb) - fmax(y[i] - h[i] / 2.0, j * hb);
+            if (ox > 0.0 && oy > 0.0) acc += (long double)(ox * oy);
+        }
+        out[k] = (double)(acc / ((long double)wb * hb));
+    }
+    return 0;
+}
+
+/* Selected binned coefficients a[us[k], ps[k]] (the same sums as oracle_bin_coeffs). */
+int oracle_bin_coeffs_at(double W, double H, int m, const double *P, int64_t count, const int *us,
+                         const int *ps, double *out)
+{
+    if (m <= 0) return -1;
+    const double pi = ORACLE_PI;
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t k = 0; k < count; ++k) {
+        const int u = us[k], p = ps[k];
+        long double sum = 0.0L;
+        for (int l = 0; l < m; ++l) {
+            double cu, su;
+            bin_trig(u, l, m, &cu, &su);
+            for (int j = 0; j < m; ++j) {
+                double cp, sp;
+                bin_trig(p, j, m, &cp, &sp);
+                sum += (long double)P[(size_t)l * m + j] * cu * cp;
+            }
+        }
+        double f;
+        if (u == 0 && p == 0) f = 0.0;
+        else if (u == 0) f = 4.0 * H * H / ((double)p * p * p * pi * pi * pi * m) * sin(p * pi / (2.0 * m));
+        else if (p == 0) f = 4.0 * W * W / ((double)u * u * u * pi * pi * pi * m) * sin(u * pi / (2.0 * m));
+        else
+            f = 16.0 * W * W * H * H / ((double)u * p * ((double)u * u * H * H + (double)p * p * W * W) *
+                                        pi * pi * pi * pi) *
+                sin(u * pi / (2.0 * m)) * sin(p * pi / (2.0 * m));
+        out[k] = (double)(f * sum);
+    }
+    return 0;
+}

@@ -19,7 +19,7 @@ import torch
 
 __all__ = ["PRECISIONS", "BASIS_MODES", "PPError", "library_path", "load", "workspace_size", "coeffs",
            "energy", "field", "point_field", "block_potential", "PPEnergy", "energy_autograd", "timing_enable",
-           "timing_query"]
+           "timing_query", "bin_workspace_size", "bin_density", "bin_coeffs", "bin_field"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libpplace.so")
@@ -29,7 +29,8 @@ BASIS_MODES = {"recompute": 0, "store": 1}
 
 PP_OK = 0
 EXPORTS = ("pp_workspace_size", "pp_coeffs", "pp_energy", "pp_field", "pp_point_field", "pp_block_potential",
-           "pp_strerror", "pp_timing_enable", "pp_timing_query")
+           "pp_strerror", "pp_timing_enable", "pp_timing_query", "pp_bin_workspace_size", "pp_bin_density",
+           "pp_bin_coeffs", "pp_bin_field")
 
 
 class PPError(RuntimeError):
@@ -42,6 +43,11 @@ class PPProblem(ctypes.Structure):
     _fields_ = [("W", ctypes.c_double), ("H", ctypes.c_double), ("n", ctypes.c_int64),
                 ("Mu", ctypes.c_int32), ("Mp", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("basis_mode", ctypes.c_int32)]
+
+
+class PPBinProblem(ctypes.Structure):
+    _fields_ = [("W", ctypes.c_double), ("H", ctypes.c_double), ("n", ctypes.c_int64), ("m", ctypes.c_int32),
+                ("Mu", ctypes.c_int32), ("Mp", ctypes.c_int32)]
 
 
 _lib = None
@@ -73,7 +79,13 @@ def load():
     lib.pp_timing_enable.restype = ctypes.c_int
     lib.pp_timing_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
     lib.pp_timing_query.restype = ctypes.c_int
-    for f in ("pp_workspace_size", "pp_coeffs", "pp_energy", "pp_field", "pp_point_field", "pp_block_potential"):
+    B = ctypes.POINTER(PPBinProblem)
+    lib.pp_bin_workspace_size.argtypes = [B, ctypes.POINTER(sz)]
+    lib.pp_bin_density.argtypes = [B, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.pp_bin_coeffs.argtypes = [B, vp, vp, vp, sz, vp]
+    lib.pp_bin_field.argtypes = [B, vp, vp, vp, vp, vp, sz, vp]
+    for f in ("pp_workspace_size", "pp_coeffs", "pp_energy", "pp_field", "pp_point_field", "pp_block_potential",
+              "pp_bin_workspace_size", "pp_bin_density", "pp_bin_coeffs", "pp_bin_field"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -234,6 +246,90 @@ def block_potential(x, y, w, h, a, *, W, H, precision="fp64", workspace=None):
     if st != PP_OK:
         raise PPError(st, "pp_block_potential")
     return N
+
+
+# ------------------------------------------------------------------------------------------------
+# Bin scheme (Sec. III-D), the comparison path: m x m bins, FP64 throughout.
+# ------------------------------------------------------------------------------------------------
+def _bin_problem(W, H, n, m, Mu, Mp) -> PPBinProblem:
+    return PPBinProblem(float(W), float(H), int(n), int(m), int(Mu), int(Mp))
+
+
+def bin_workspace_size(W, H, n, m, Mu=None, Mp=None) -> int:
+    B = _bin_problem(W, H, n, m, m if Mu is None else Mu, m if Mp is None else Mp)
+    out = ctypes.c_size_t(0)
+    st = load().pp_bin_workspace_size(ctypes.byref(B), ctypes.byref(out))
+    if st != PP_OK:
+        raise PPError(st, "pp_bin_workspace_size")
+    return int(out.value)
+
+
+def _bin_ws(B, dev, workspace):
+    nbytes = ctypes.c_size_t(0)
+    st = load().pp_bin_workspace_size(ctypes.byref(B), ctypes.byref(nbytes))
+    if st != PP_OK:
+        raise PPError(st, "pp_bin_workspace_size")
+    if workspace is not None:
+        if workspace.device != dev or workspace.dtype != torch.uint8 or not workspace.is_contiguous():
+            raise ValueError("workspace must be a contiguous uint8 tensor on the data's device")
+        return workspace, int(workspace.numel())
+    return torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device=dev), int(nbytes.value)
+
+
+def _bin_matrix(t, rows, cols, dev, name):
+    if (not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or tuple(t.shape) != (rows, cols)
+            or not t.is_contiguous() or t.device != dev):
+        raise ValueError(f"{name} must be a contiguous float64 [{rows}, {cols}] tensor on the GPU")
+
+
+def bin_density(x, y, w, h, *, W, H, m, workspace=None):
+    """Bin densities P[l, j] of an m x m grid: exact overlap areas of the blocks over the bin area."""
+    dev, n = _blocks(x, y, w, h)
+    B = _bin_problem(W, H, n, m, 1, 1)
+    P = torch.empty((m, m), dtype=torch.float64, device=dev)
+    ws, nb = _bin_ws(B, dev, workspace)
+    with torch.cuda.device(dev):
+        st = load().pp_bin_density(ctypes.byref(B), _vp(x), _vp(y), _vp(w), _vp(h), _vp(P), _vp(ws), nb,
+                                   _stream(dev))
+    if st != PP_OK:
+        raise PPError(st, "pp_bin_density")
+    return P
+
+
+def bin_coeffs(P, *, W, H, Mu, Mp, workspace=None):
+    """Binned coefficients a[u, p], u < Mu, p < Mp (eqs. disa-a..d) of the m x m bin densities P."""
+    if not isinstance(P, torch.Tensor) or P.dim() != 2:
+        raise ValueError("P must be a 2-D tensor")
+    m, dev = P.shape[0], P.device
+    _bin_matrix(P, m, m, dev, "P")
+    B = _bin_problem(W, H, 0, m, Mu, Mp)
+    a = torch.empty((Mu, Mp), dtype=torch.float64, device=dev)
+    ws, nb = _bin_ws(B, dev, workspace)
+    with torch.cuda.device(dev):
+        st = load().pp_bin_coeffs(ctypes.byref(B), _vp(P), _vp(a), _vp(ws), nb, _stream(dev))
+    if st != PP_OK:
+        raise PPError(st, "pp_bin_coeffs")
+    return a
+
+
+def bin_field(a, *, W, H, m, want=("psi", "xix", "xiy"), workspace=None):
+    """psi, xi_x, xi_y at the centres of the m x m bins (eqs. dis-psi1, dis-ksi); outputs not named in
+    `want` are None."""
+    if not isinstance(a, torch.Tensor) or a.dim() != 2:
+        raise ValueError("a must be a 2-D tensor")
+    Mu, Mp = a.shape
+    dev = a.device
+    _bin_matrix(a, Mu, Mp, dev, "a")
+    B = _bin_problem(W, H, 0, m, Mu, Mp)
+    outs = {k: (torch.empty((m, m), dtype=torch.float64, device=dev) if k in want else None)
+            for k in ("psi", "xix", "xiy")}
+    ws, nb = _bin_ws(B, dev, workspace)
+    with torch.cuda.device(dev):
+        st = load().pp_bin_field(ctypes.byref(B), _vp(a), _vp(outs["psi"]), _vp(outs["xix"]), _vp(outs["xiy"]),
+                                 _vp(ws), nb, _stream(dev))
+    if st != PP_OK:
+        raise PPError(st, "pp_bin_field")
+    return outs["psi"], outs["xix"], outs["xiy"]
 
 
 def timing_enable(on: bool) -> None:

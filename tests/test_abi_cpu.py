@@ -151,3 +151,54 @@ def test_python_binding_fails_loudly_without_gpu_tensors(lib):
         pp.energy(x, x, x, x, W=1.0, H=1.0, Mu=4, Mp=4)
     with pytest.raises(ValueError):
         pp.energy(x, x, x, x, W=1.0, H=1.0, Mu=4, Mp=4, precision="fp7")
+
+
+def BP(**kw):
+    d = dict(W=100.0, H=50.0, n=1000, m=64, Mu=64, Mp=48)
+    d.update(kw)
+    return pp.PPBinProblem(d["W"], d["H"], d["n"], d["m"], d["Mu"], d["Mp"])
+
+
+def bin_ws(lib, prob):
+    out = ctypes.c_size_t(12345)
+    st = lib.pp_bin_workspace_size(ctypes.byref(prob), ctypes.byref(out))
+    return st, out.value
+
+
+def test_bin_workspace_size(lib):
+    st, a = bin_ws(lib, BP())
+    assert st == 0 and a > 0
+    st, b = bin_ws(lib, BP(m=128, Mu=128, Mp=128, n=5000))
+    assert st == 0 and b > a
+    assert bin_ws(lib, BP(n=0))[0] == 0
+    for bad in (BP(W=0.0), BP(H=float("nan")), BP(m=0), BP(m=20000), BP(Mu=65), BP(Mp=0), BP(n=-1),
+                BP(n=1 << 31)):
+        assert bin_ws(lib, bad)[0] == -1
+    assert lib.pp_bin_workspace_size(None, ctypes.byref(ctypes.c_size_t(0))) == -1
+    assert lib.pp_bin_workspace_size(ctypes.byref(BP()), None) == -1
+
+
+def test_bin_entry_points_validate_before_launch(lib):
+    prob = BP()
+    st, need = bin_ws(lib, prob)
+    assert st == 0
+    fake = ctypes.c_void_p(1 << 20)
+    odd = ctypes.c_void_p((1 << 20) + 4)
+    ws_odd = ctypes.c_void_p((1 << 20) + 8)
+    nul = None
+    bd, bc, bf = lib.pp_bin_density, lib.pp_bin_coeffs, lib.pp_bin_field
+    assert bd(None, fake, fake, fake, fake, fake, fake, need, nul) == -1
+    assert bd(ctypes.byref(prob), nul, fake, fake, fake, fake, fake, need, nul) == -1
+    assert bd(ctypes.byref(prob), fake, fake, fake, odd, fake, fake, need, nul) == -1
+    assert bd(ctypes.byref(prob), fake, fake, fake, fake, nul, fake, need, nul) == -1
+    assert bd(ctypes.byref(prob), fake, fake, fake, fake, fake, fake, need - 1, nul) == -2
+    assert bd(ctypes.byref(prob), fake, fake, fake, fake, fake, ws_odd, need, nul) == -1
+    assert bc(ctypes.byref(prob), nul, fake, fake, need, nul) == -1
+    assert bc(ctypes.byref(prob), fake, odd, fake, need, nul) == -1
+    assert bc(ctypes.byref(prob), fake, fake, fake, need - 1, nul) == -2
+    assert bc(ctypes.byref(BP(Mu=65)), fake, fake, fake, need, nul) == -1
+    assert bf(ctypes.byref(prob), nul, fake, fake, fake, fake, need, nul) == -1
+    assert bf(ctypes.byref(prob), fake, odd, fake, fake, fake, need, nul) == -1
+    assert bf(ctypes.byref(prob), fake, fake, fake, fake, fake, need - 1, nul) == -2
+    # nothing requested: nothing to do, after validation
+    assert bf(ctypes.byref(prob), fake, nul, nul, nul, fake, need, nul) == 0

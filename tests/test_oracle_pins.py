@@ -512,3 +512,16 @@ def test_bin_field_matches_dct3_and_point_field(W, H, m, Mu, Mp):
     ps, ex, ey = oracle.point_field(W, H, a, X.ravel(), Y.ravel())
     for got, want in ((psi, ps), (xix, ex), (xiy, ey)):
         assert np.abs(got.ravel() - want).max() <= 1e-13 * np.abs(want).max()
+
+
+def test_bin_sampled_routines_match_full():
+    rng = np.random.default_rng(21)
+    W, H, m, n = 9.0, 4.0, 12, 120
+    x, y = rng.uniform(-0.5, W + 0.5, n), rng.uniform(-0.5, H + 0.5, n)
+    w, h = rng.uniform(0.05, 4.0, n), rng.uniform(0.05, 2.0, n)
+    P = oracle.bin_density(W, H, x, y, w, h, m)
+    ls, js = rng.integers(0, m, 30), rng.integers(0, m, 30)
+    assert np.abs(oracle.bin_density_at(W, H, x, y, w, h, m, ls, js) - P[ls, js]).max() <= 1e-14
+    a = oracle.bin_coeffs(W, H, P, m, 9)
+    us, ps = rng.integers(0, m, 30), rng.integers(0, 9, 30)
+    assert np.abs(oracle.bin_coeffs_at(W, H, P, us, ps) - a[us, ps]).max() <= 1e-14 * np.abs(a).max()
