@@ -422,6 +422,18 @@ static void bin_trig(long k, long s, long m, double *c, double *sn)
     *sn = sin(phi);
 }
 
+/* The factor of the binned coefficient (u, p) in eqs. disa-a..d. */
+static double bin_factor(long u, long p, double W, double H, long m)
+{
+    const double pi = ORACLE_PI;
+    if (u == 0 && p == 0) return 0.0;
+    if (u == 0) return 4.0 * H * H / ((double)p * p * p * pi * pi * pi * m) * sin(p * pi / (2.0 * m));
+    if (p == 0) return 4.0 * W * W / ((double)u * u * u * pi * pi * pi * m) * sin(u * pi / (2.0 * m));
+    return 16.0 * W * W * H * H / ((double)u * p * ((double)u * u * H * H + (double)p * p * W * W) *
+                                   pi * pi * pi * pi) *
+           sin(u * pi / (2.0 * m)) * sin(p * pi / (2.0 * m));
+}
+
 /* Bin densities: the overlap area of every block with every bin, over the bin area. */
 int oracle_bin_density(double W, double H, int64_t n, const double *x, const double *y,
                        const double *w, const double *h, int m, double *P)
@@ -452,7 +464,6 @@ int oracle_bin_density(double W, double H, int64_t n, const double *x, const dou
 int oracle_bin_coeffs(double W, double H, int m, const double *P, int Mu, int Mp, double *a)
 {
     if (m <= 0 || Mu <= 0 || Mp <= 0) return -1;
-    const double pi = ORACLE_PI;
     int st = 0;
 #pragma omp parallel for schedule(dynamic)
     for (int u = 0; u < Mu; ++u) {
@@ -467,15 +478,7 @@ int oracle_bin_coeffs(double W, double H, int m, const double *P, int Mu, int Mp
                     sum += (long double)P[(size_t)l * m + j] * cu * cp;
                 }
             }
-            double f;
-            if (u == 0 && p == 0) f = 0.0;
-            else if (u == 0) f = 4.0 * H * H / ((double)p * p * p * pi * pi * pi * m) * sin(p * pi / (2.0 * m));
-            else if (p == 0) f = 4.0 * W * W / ((double)u * u * u * pi * pi * pi * m) * sin(u * pi / (2.0 * m));
-            else
-                f = 16.0 * W * W * H * H / ((double)u * p * ((double)u * u * H * H + (double)p * p * W * W) *
-                                            pi * pi * pi * pi) *
-                    sin(u * pi / (2.0 * m)) * sin(p * pi / (2.0 * m));
-            a[(size_t)u * Mp + p] = (double)(f * sum);
+            a[(size_t)u * Mp + p] = (double)(bin_factor(u, p, W, H, m) * sum);
         }
     }
     return st;
@@ -537,7 +540,6 @@ int oracle_bin_coeffs_at(double W, double H, int m, const double *P, int64_t cou
                          const int *ps, double *out)
 {
     if (m <= 0) return -1;
-    const double pi = ORACLE_PI;
 #pragma omp parallel for schedule(dynamic)
     for (int64_t k = 0; k < count; ++k) {
         const int u = us[k], p = ps[k];
@@ -551,15 +553,7 @@ int oracle_bin_coeffs_at(double W, double H, int m, const double *P, int64_t cou
                 sum += (long double)P[(size_t)l * m + j] * cu * cp;
             }
         }
-        double f;
-        if (u == 0 && p == 0) f = 0.0;
-        else if (u == 0) f = 4.0 * H * H / ((double)p * p * p * pi * pi * pi * m) * sin(p * pi / (2.0 * m));
-        else if (p == 0) f = 4.0 * W * W / ((double)u * u * u * pi * pi * pi * m) * sin(u * pi / (2.0 * m));
-        else
-            f = 16.0 * W * W * H * H / ((double)u * p * ((double)u * u * H * H + (double)p * p * W * W) *
-                                        pi * pi * pi * pi) *
-                sin(u * pi / (2.0 * m)) * sin(p * pi / (2.0 * m));
-        out[k] = (double)(f * sum);
+        out[k] = (double)(bin_factor(u, p, W, H, m) * sum);
     }
     return 0;
 }

@@ -18,8 +18,8 @@ MUTANTS = {
     "a_up constant 4 -> 2": ("return 4.0 * W * W * H * H /", "return 2.0 * W * W * H * H /"),
     "a_u0 constant 2 -> 4": ("if (p == 0) return 2.0 * W * W /", "if (p == 0) return 4.0 * W * W /"),
     "a_0p uses W^2 for H^2": ("if (u == 0) return 2.0 * H * H /", "if (u == 0) return 2.0 * W * W /"),
-    "a_up denominator swaps W and H": ("((double)u * u * H * H + (double)p * p * W * W)",
-                                       "((double)u * u * W * W + (double)p * p * H * H)"),
+    "a_up denominator swaps W and H": ("(((double)u * u * H * H + (double)p * p * W * W) * (double)u",
+                                       "(((double)u * u * W * W + (double)p * p * H * H) * (double)u"),
     "moment factor of the u-row": ("if (p == 0) return W / ((double)u * pi);",
                                    "if (p == 0) return H / ((double)u * pi);"),
     "energy drops the one half": ("return (double)(0.5L * e);", "return (double)(e);"),
@@ -35,7 +35,7 @@ MUTANTS = {
     "point field drops the frequency factor": ("ex += ((double)u * ORACLE_PI / W) * su[u] * zc;",
                                                "ex += su[u] * zc;"),
     "bin centre without the half bin": ("long q = (k * (2 * s + 1)) % (4 * m);", "long q = (k * (2 * s)) % (4 * m);"),
-    "bin a_up constant 16 -> 8": ("f = 16.0 * W * W * H * H /", "f = 8.0 * W * W * H * H /"),
+    "bin a_up constant 16 -> 8": ("return 16.0 * W * W * H * H /", "return 8.0 * W * W * H * H /"),
     "bin sine factor uses pi/m": ("sin(u * pi / (2.0 * m)) * sin(p * pi / (2.0 * m));",
                                   "sin(u * pi / (1.0 * m)) * sin(p * pi / (2.0 * m));"),
     "bin density over the bin width only": ("P[k] = (double)(acc[k] / ((long double)wb * hb));",
