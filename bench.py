@@ -106,6 +106,9 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--fp32-steps", type=int, default=2, help="steps of the FP32 path on the same workload (0: skip)")
+    ap.add_argument("--bins", type=int, default=-1,
+                    help="bins per axis of the Sec. III-D bin-scheme comparison leg (-1: the workload's truncation "
+                         "when Mu = Mp; 0: skip)")
     ap.add_argument("--eval-precision", default="bf16x3", choices=["bf16x3", "bf16", "fp32", "fp64", "none"],
                     help="time the evaluation calls (point field at the block centres, block potentials)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -250,6 +253,48 @@ def main():
             "half_sum_N_vs_E": ident}
         log(f"[bench] evaluation ({ep}): point field {tp:.1f} ms ({cp} contractions), block potentials {tn:.1f} ms; "
             f"|1/2 sum N - E| / E = {ident:.2e}")
+
+    m_bins = (wl.Mu if wl.Mu == wl.Mp else 0) if args.bins < 0 else args.bins
+    if m_bins > 0:
+        # The bin scheme of Sec. III-D at m x m bins and the same truncation M = m: its cost, and how
+        # far its coefficients and its bin-centre potential and field are from the direct sum's.
+        Mb = min(m_bins, wl.Mu, wl.Mp)
+        wsb = torch.empty(pp.bin_workspace_size(wl.W, wl.H, wl.n, m_bins, Mb, Mb), dtype=torch.uint8, device=dev)
+        Pb = pp.bin_density(*t, W=wl.W, H=wl.H, m=m_bins, workspace=wsb)
+        ab = pp.bin_coeffs(Pb, W=wl.W, H=wl.H, Mu=Mb, Mp=Mb, workspace=wsb)
+        pp.bin_field(ab, W=wl.W, H=wl.H, m=m_bins, workspace=wsb)
+        torch.cuda.synchronize()
+        pp.timing_enable(True)
+        Pb = pp.bin_density(*t, W=wl.W, H=wl.H, m=m_bins, workspace=wsb)
+        ab = pp.bin_coeffs(Pb, W=wl.W, H=wl.H, Mu=Mb, Mp=Mb, workspace=wsb)
+        fb = pp.bin_field(ab, W=wl.W, H=wl.H, m=m_bins, workspace=wsb)
+        torch.cuda.synchronize()
+        td, _ = pp.timing_query("bin_density")
+        tcf, _ = pp.timing_query("bin_coeffs")
+        tf, _ = pp.timing_query("bin_field")
+        pp.timing_enable(False)
+        gemm_flops = 2.0 * m_bins * Mb * m_bins + 2.0 * Mb * Mb * m_bins + 2 * 2.0 * Mb * m_bins * Mb \
+            + 3 * 2.0 * m_bins * m_bins * Mb
+        if ref is not None:
+            a_dir, dir_name = ref[1], "fp64 direct sum (GPU)"
+        else:
+            a_dir, dir_name = a, f"{args.precision} direct sum (GPU)"
+        a_dir = a_dir[:Mb, :Mb].contiguous()
+        fd = pp.bin_field(a_dir, W=wl.W, H=wl.H, m=m_bins, workspace=wsb)
+        abn, adn = ab.cpu().numpy(), a_dir.cpu().numpy()
+        lo = min(64, Mb)
+        bins = {"m": m_bins, "M": Mb, "density_ms": td, "coeffs_ms": tcf, "field_ms": tf,
+                "transform_gemm_tflops_fp64": round(gemm_flops / ((tcf + tf) * 1e-3) / 1e12, 2),
+                "compared_with": dir_name,
+                "coeffs_rel_diff": rel(abn, adn),
+                f"coeffs_rel_diff_u_p_below_{lo}": rel(abn[:lo, :lo], adn[:lo, :lo]),
+                "psi_rel_diff_at_bin_centres": rel(fb[0].cpu().numpy(), fd[0].cpu().numpy()),
+                "xi_rel_diff_at_bin_centres": rel(np.concatenate([fb[1].cpu().numpy(), fb[2].cpu().numpy()]),
+                                                  np.concatenate([fd[1].cpu().numpy(), fd[2].cpu().numpy()]))}
+        out["bin_scheme"] = bins
+        log(f"[bench] bin scheme m={m_bins}: density {td:.2f} ms, coefficients {tcf:.2f} ms, field {tf:.2f} ms; "
+            f"vs direct: a {bins['coeffs_rel_diff']:.3e}, psi {bins['psi_rel_diff_at_bin_centres']:.3e}, "
+            f"xi {bins['xi_rel_diff_at_bin_centres']:.3e}")
 
     if not args.no_accuracy:
         import oracle
