@@ -138,7 +138,8 @@ __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(
 
 // ================================================================================================
 // Forward: At[u][p] = sum_i S_iu T_ip over a range of blocks.
-// 512 threads = 8 waves in two ping-pong groups.  Wave w owns the 128 x 64 output sub-tile
+// Kernels: k_fwd1_bf16 (x3, one wave per SIMD, further below) and k_fwd_bf16 (plain bf16, here).
+// k_fwd_bf16: 512 threads = 8 waves in two ping-pong groups.  Wave w owns the 128 x 64 output sub-tile
 // (u-half w / 4, p-quarter w % 4); waves w and w + 4 share a SIMD.  Per chunk of 32 blocks the
 // group of waves 0-3 generates the X tile, the group of waves 4-7 the Y tile; while one group
 // contracts chunk c from one LDS buffer the other generates chunk c + 1 into the other buffer.
@@ -720,7 +721,9 @@ __global__ __launch_bounds__(256) void k_fwd1_bf16(int64_t n, int Mu, int Mp, co
 
 // ================================================================================================
 // Backward: G[i][nn] = sum_k A_ik B[k][nn], g_i = sum_nn E_i,nn G[i][nn].
-// 512 threads = 8 waves; wave w owns blocks i0 + 32 w .. + 31 and all 256 columns of the N tile.
+// Kernels: k_bwd1_bf16 (x3 with the basis regenerated, one wave per SIMD, further below) and
+// k_bwd_bf16 (plain bf16, and the store mode of both bf16 types, here).
+// k_bwd_bf16: 512 threads = 8 waves; wave w owns blocks i0 + 32 w .. + 31 and all 256 columns of the N tile.
 // A (sine differences along the K axis) is generated in registers directly in MFMA operand
 // layout: lane half h = lane / 32 walks frequencies h * Kh + 8 t (t = 0, 1, ...), so each lane's
 // recurrence runs over contiguous frequencies.  B is staged per chunk of 32 + 32 frequencies
