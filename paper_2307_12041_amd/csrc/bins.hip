@@ -117,7 +117,8 @@ struct BinOp {
 __device__ __forceinline__ double binop_at(const BinOp &o, const double *__restrict__ tab, int m4, int r, int c) {
     if (o.trig == 0) return o.ptr[(size_t)r * o.ld + c];
     const int f = o.freq_is_row ? r : c, s = o.freq_is_row ? c : r;
-    const int q = (int)(((int64_t)f * (2 * s + 1)) % m4);
+    // f < m and 2s + 1 < 2m, so the product is below 2 m^2 <= 2^29: exact in 32-bit unsigned
+    const int q = (int)(((unsigned)f * (unsigned)(2 * s + 1)) % (unsigned)m4);
     double v = tab[(o.trig - 1) * m4 + q];
     if (o.wscale != 0.0) v *= (double)f * o.wscale;
     return v;
@@ -138,8 +139,8 @@ constexpr int GT = 64, GK = 16, GPAD = GT + 1;
 template <bool DISA>
 __global__ __launch_bounds__(256) void k_bin_gemm(int M, int N, int K, BinOp A, BinOp B, const double *__restrict__ tab,
                                                   int m4, double *__restrict__ C, int ldc, double W, double H, int m) {
-    __shared__ double As[GK * GPAD];   // [k][i]
-    __shared__ double Bs[GK * GPAD];   // [k][j]
+    __shared__ double As[2][GK * GPAD];   // [buffer][k][i]
+    __shared__ double Bs[2][GK * GPAD];   // [buffer][k][j]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r0 = blockIdx.y * GT, c0 = blockIdx.x * GT;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
@@ -149,31 +150,50 @@ __global__ __launch_bounds__(256) void k_bin_gemm(int M, int N, int K, BinOp A, 
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-    for (int k0 = 0; k0 < K; k0 += GK) {
+    // K chunks are double-buffered: the operands of chunk c + 1 are fetched into registers while
+    // the MFMAs of chunk c run, then stored to the other LDS buffer; one barrier per chunk.
+    constexpr int PER = GT * GK / 256;
+    double na[PER], nb[PER];
+    auto fetch = [&](int k0) {
 #pragma unroll
-        for (int q = 0; q < GT * GK / 256; ++q) {
+        for (int q = 0; q < PER; ++q) {
             const int e = tid + 256 * q;
             const int ia = e / GK, ka = e % GK;      // A element (r0 + ia, k0 + ka)
             const int kb = e / GT, jb = e % GT;      // B element (k0 + kb, c0 + jb)
             const int ra = r0 + ia, ca = k0 + ka, rb = k0 + kb, cb = c0 + jb;
-            As[ka * GPAD + ia] = (ra < M && ca < K) ? binop_at(A, tab, m4, ra, ca) : 0.0;
-            Bs[kb * GPAD + jb] = (rb < K && cb < N) ? binop_at(B, tab, m4, rb, cb) : 0.0;
+            na[q] = (ra < M && ca < K) ? binop_at(A, tab, m4, ra, ca) : 0.0;
+            nb[q] = (rb < K && cb < N) ? binop_at(B, tab, m4, rb, cb) : 0.0;
         }
-        __syncthreads();
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + 256 * q;
+            As[buf][(e % GK) * GPAD + e / GK] = na[q];
+            Bs[buf][(e / GT) * GPAD + e % GT] = nb[q];
+        }
+    };
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int k0 = 0, buf = 0; k0 < K; k0 += GK, buf ^= 1) {
+        const bool more = k0 + GK < K;
+        if (more) fetch(k0 + GK);
 #pragma unroll
         for (int ks = 0; ks < GK / 4; ++ks) {
             const int kr = 4 * ks + (lane >> 4);
             double av[2], bv[2];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) av[a] = As[kr * GPAD + wr + 16 * a + (lane & 15)];
+            for (int a = 0; a < 2; ++a) av[a] = As[buf][kr * GPAD + wr + 16 * a + (lane & 15)];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) bv[b] = Bs[kr * GPAD + wc + 16 * b + (lane & 15)];
+            for (int b = 0; b < 2; ++b) bv[b] = Bs[buf][kr * GPAD + wc + 16 * b + (lane & 15)];
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
                 for (int b = 0; b < 2; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
         }
+        if (more) stash(buf ^ 1);
         __syncthreads();
     }
     // D layout of v_mfma_f64_16x16x4f64: row 4 r + lane / 16, column lane % 16.
