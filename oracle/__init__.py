@@ -62,6 +62,7 @@ def _load():
     lib.oracle_bin_field.argtypes = [d, d, i32, i32, i32, _dp, _dp, _dp, _dp]
     lib.oracle_bin_density_at.argtypes = [d, d, i64, _dp, _dp, _dp, _dp, i32, i64, _ip, _ip, _dp]
     lib.oracle_bin_coeffs_at.argtypes = [d, d, i32, _dp, i64, _ip, _ip, _dp]
+    lib.oracle_bin_interp.argtypes = [d, d, i64, _dp, _dp, _dp, _dp, i32, _dp, _dp, _dp, _dp, _dp, _dp]
     lib.oracle_num_threads.argtypes = []
     for f in ("oracle_coeffs", "oracle_energy", "oracle_grad", "oracle_grad_sampled",
               "oracle_coeffs_sampled", "oracle_point_field", "oracle_block_potential",
@@ -236,3 +237,26 @@ def bin_coeffs_at(W, H, P, us, ps):
     _check(lib.oracle_bin_coeffs_at(W, H, P.shape[0], pP, len(us), us.ctypes.data_as(_ip), ps.ctypes.data_as(_ip),
                                     out.ctypes.data_as(_dp)), "bin_coeffs_at")
     return out
+
+
+def bin_interp(W, H, x, y, w, h, m, psi=None, xix=None, xiy=None):
+    """Block values from bin values: (N, gx, gy), N_i = sum over the bins of |block i cap bin| psi,
+    gx_i = -sum |block i cap bin| xi_x, gy_i likewise; an output is None when its field is None."""
+    lib = _load()
+    xs = [_f64(v) for v in (x, y, w, h)]
+    n = xs[0][0].shape[0]
+    ins, outs = [], []
+    for f in (psi, xix, xiy):
+        if f is None:
+            ins.append(None)
+            outs.append(None)
+        else:
+            f, _ = _f64(f)
+            if f.shape != (m, m):
+                raise ValueError("bin fields must be m x m")
+            ins.append(f)
+            outs.append(np.zeros(n))
+    ptr = lambda a: None if a is None else a.ctypes.data_as(_dp)
+    _check(lib.oracle_bin_interp(W, H, n, *[p for _, p in xs], m, *[ptr(a) for a in ins], *[ptr(a) for a in outs]),
+           "bin_interp")
+    return tuple(outs)

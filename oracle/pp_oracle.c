@@ -60,7 +60,13 @@
  *           psi(l,j) = sum_up a_up cos(u (l+1/2) pi/m) cos(p (j+1/2) pi/m),
  *           xi_x(l,j) = sum_up (u pi/W) a_up sin(u (l+1/2) pi/m) cos(p (j+1/2) pi/m),
  *           xi_y(l,j) = sum_up (p pi/H) a_up cos(u (l+1/2) pi/m) sin(p (j+1/2) pi/m).
- *     Cosines and sines of k (2l+1) pi/(2m) take the integer k (2l+1) modulo 4m first.
+ *     Cosines and sines of k (2l+1) pi/(2m) take the integer k (2l+1) modulo 4m first;
+ *       - the values of each block from those of the bins around it (the last step of the
+ *         scheme, whose weights the paper leaves open), read as the integral over the block of
+ *         the bin values held constant on each bin, in the conventions of item 5 and of item 4:
+ *           N_i  = sum_lj |block i cap bin lj| psi(l,j),
+ *           gx_i = - sum_lj |block i cap bin lj| xi_x(l,j),  gy_i = - sum_lj ... xi_y(l,j),
+ *         the counterparts of the block potentials and of the gradient of the direct path.
  *
  * Truncation: u in [0, Mu), p in [0, Mp).  Coefficient arrays are row-major, a[u*Mp + p].
  */
@@ -554,6 +560,40 @@ int oracle_bin_coeffs_at(double W, double H, int m, const double *P, int64_t cou
             }
         }
         out[k] = (double)(bin_factor(u, p, W, H, m) * sum);
+    }
+    return 0;
+}
+
+/* Block values from bin values (the last step of the scheme): for each block, the sum over the
+ * bins it overlaps of the overlap area times the bin value; the field sums carry a minus sign so
+ * that they approximate the gradient dE/dx_i, dE/dy_i.  A NULL field skips its output. */
+int oracle_bin_interp(double W, double H, int64_t n, const double *x, const double *y,
+                      const double *w, const double *h, int m, const double *psi, const double *xix,
+                      const double *xiy, double *N, double *gx, double *gy)
+{
+    if (m <= 0 || W <= 0.0 || H <= 0.0) return -1;
+    const double wb = W / m, hb = H / m;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+        const double x0 = x[i] - w[i] / 2.0, x1 = x[i] + w[i] / 2.0;
+        const double y0 = y[i] - h[i] / 2.0, y1 = y[i] + h[i] / 2.0;
+        long double sp = 0.0L, sx = 0.0L, sy = 0.0L;
+        for (int l = 0; l < m; ++l) {
+            const double ox = fmin(x1, (l + 1) * wb) - fmax(x0, l * wb);
+            if (ox <= 0.0) continue;
+            for (int j = 0; j < m; ++j) {
+                const double oy = fmin(y1, (j + 1) * hb) - fmax(y0, j * hb);
+                if (oy <= 0.0) continue;
+                const long double area = (long double)ox * oy;
+                const size_t b = (size_t)l * m + j;
+                if (psi) sp += area * psi[b];
+                if (xix) sx += area * xix[b];
+                if (xiy) sy += area * xiy[b];
+            }
+        }
+        if (psi) N[i] = (double)sp;
+        if (xix) gx[i] = (double)-sx;
+        if (xiy) gy[i] = (double)-sy;
     }
     return 0;
 }

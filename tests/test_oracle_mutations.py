@@ -42,6 +42,10 @@ MUTANTS = {
                                             "P[k] = (double)(acc[k] / ((long double)wb));"),
     "bin field xi_y uses the x frequency": ("ey += (long double)((double)p * pi / H) * apu * cu[u] * sp[p];",
                                             "ey += (long double)((double)u * pi / W) * apu * cu[u] * sp[p];"),
+    "bin interpolation swaps the bin axes": ("const size_t b = (size_t)l * m + j;", "const size_t b = (size_t)j * m + l;"),
+    "bin interpolation drops the gradient sign": ("if (xix) gx[i] = (double)-sx;", "if (xix) gx[i] = (double)sx;"),
+    "bin interpolation area uses the width twice": ("const long double area = (long double)ox * oy;",
+                                                    "const long double area = (long double)ox * ox;"),
     "block potential y integral": ("for (int p = 0; p < Mp; ++p) Yb[p] = edge_integral(p, y[i], h[i], H);",
                                    "for (int p = 0; p < Mp; ++p) Yb[p] = edge_integral(p, y[i], w[i], H);"),
 }

@@ -11,6 +11,8 @@ or a transposed operand anywhere in the oracle fails at least one of them:
   truncation semantics ................ monotone energy, O(M^-3) convergence
   gradient ............................ central differences, mirror signs, field quadrature
   point potential / field ............. block quadrature of psi, finite differences of psi
+  bin scheme .......................... lattice brute force, DCT-II / DCT-III, whole-bin blocks,
+                                        adjoint of the densities, convergence to the direct path
 """
 import numpy as np
 import pytest
@@ -525,3 +527,72 @@ def test_bin_sampled_routines_match_full():
     a = oracle.bin_coeffs(W, H, P, m, 9)
     us, ps = rng.integers(0, m, 30), rng.integers(0, 9, 30)
     assert np.abs(oracle.bin_coeffs_at(W, H, P, us, ps) - a[us, ps]).max() <= 1e-14 * np.abs(a).max()
+
+
+def test_bin_interp_exact_by_lattice_sampling():
+    # Block values from bin values: with block edges on a lattice of 1/8 bin, summing the lattice
+    # cells inside each block, each weighted by the value of the bin that holds it, is exact (an
+    # independent brute force).  Distinct random fields for psi, xi_x and xi_y and a non-square
+    # region catch a transposed or swapped field; the field sums carry the gradient's minus sign.
+    rng = np.random.default_rng(17)
+    W, H, m, q = 6.0, 3.0, 6, 8
+    wb, hb = W / m, H / m
+    n = 40
+    x0 = rng.integers(-4, m * q, n) * wb / q
+    y0 = rng.integers(-4, m * q, n) * hb / q
+    w = rng.integers(1, 3 * q, n) * wb / q
+    h = rng.integers(1, 3 * q, n) * hb / q
+    fields = [rng.normal(size=(m, m)) for _ in range(3)]
+    N, gx, gy = oracle.bin_interp(W, H, x0 + w / 2, y0 + h / 2, w, h, m, *fields)
+    xs = (np.arange(m * q) + 0.5) * wb / q
+    ys = (np.arange(m * q) + 0.5) * hb / q
+    cell = (wb / q) * (hb / q)
+    fine = [np.repeat(np.repeat(f, q, axis=0), q, axis=1) for f in fields]
+    for i in range(n):
+        inx = (xs > x0[i]) & (xs < x0[i] + w[i])
+        iny = (ys > y0[i]) & (ys < y0[i] + h[i])
+        mask = np.outer(inx, iny)
+        ref = [cell * f[mask].sum() for f in fine]
+        assert N[i] == pytest.approx(ref[0], abs=1e-12)
+        assert gx[i] == pytest.approx(-ref[1], abs=1e-12)
+        assert gy[i] == pytest.approx(-ref[2], abs=1e-12)
+
+
+def test_bin_interp_is_the_adjoint_of_the_densities():
+    # sum_i N_i = wb hb sum_lj P_lj psi_lj for any bin field, and a unit field gives every block
+    # its area inside the region.
+    rng = np.random.default_rng(23)
+    W, H, m, n = 10.0, 7.0, 9, 150
+    x, y = rng.uniform(-1, W + 1, n), rng.uniform(-1, H + 1, n)
+    w, h = rng.uniform(0.05, 4.0, n), rng.uniform(0.05, 3.0, n)
+    psi = rng.normal(size=(m, m))
+    P = oracle.bin_density(W, H, x, y, w, h, m)
+    N, gx, gy = oracle.bin_interp(W, H, x, y, w, h, m, psi)
+    assert gx is None and gy is None
+    assert N.sum() == pytest.approx((W / m) * (H / m) * (P * psi).sum(), rel=1e-12)
+    N1, _, _ = oracle.bin_interp(W, H, x, y, w, h, m, np.ones((m, m)))
+    inside = (np.clip(np.minimum(x + w / 2, W) - np.maximum(x - w / 2, 0), 0, None)
+              * np.clip(np.minimum(y + h / 2, H) - np.maximum(y - h / 2, 0), 0, None))
+    assert np.abs(N1 - inside).max() <= 1e-13 * inside.max()
+
+
+def test_bin_scheme_block_values_converge_to_the_direct_ones():
+    # For a smooth potential (few frequencies) the bin scheme's block potentials and gradients
+    # approach the direct path's N_i and dE/dx_i, dE/dy_i as the bins shrink: the error of a partly
+    # covered bin (value taken at its centre, not at the covered part's) is O(bin size) over O(bin
+    # size) of the block's edge, so the relative error falls with the square of the bin size.  A
+    # flipped sign of the field sums would leave an error near 2.
+    rng = np.random.default_rng(29)
+    W, H, n, M = 5.0, 4.0, 60, 4
+    x, y = rng.uniform(0.5, W - 0.5, n), rng.uniform(0.5, H - 0.5, n)
+    w, h = rng.uniform(0.2, 1.0, n), rng.uniform(0.2, 1.0, n)
+    a = rng.normal(size=(M, M))
+    N_dir = oracle.block_potential(W, H, x, y, w, h, a)
+    gx_dir, gy_dir = oracle.grad(W, H, x, y, w, h, a)
+    errs = []
+    for m in (32, 128):
+        N, gx, gy = oracle.bin_interp(W, H, x, y, w, h, m, *oracle.bin_field(W, H, m, a))
+        errs.append(max(np.abs(N - N_dir).max() / np.abs(N_dir).max(),
+                        np.abs(gx - gx_dir).max() / np.abs(gx_dir).max(),
+                        np.abs(gy - gy_dir).max() / np.abs(gy_dir).max()))
+    assert errs[0] < 2e-2 and errs[1] < 2e-3 and errs[1] < errs[0] / 8, errs
