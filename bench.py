@@ -257,44 +257,53 @@ def main():
     m_bins = (wl.Mu if wl.Mu == wl.Mp else 0) if args.bins < 0 else args.bins
     if m_bins > 0:
         # The bin scheme of Sec. III-D at m x m bins and the same truncation M = m: its cost, and how
-        # far its coefficients and its bin-centre potential and field are from the direct sum's.
+        # far its coefficients, its bin-centre potential and field and its block gradients (weighted
+        # back from the bins) are from the direct sum's.
         Mb = min(m_bins, wl.Mu, wl.Mp)
         wsb = torch.empty(pp.bin_workspace_size(wl.W, wl.H, wl.n, m_bins, Mb, Mb), dtype=torch.uint8, device=dev)
         Pb = pp.bin_density(*t, W=wl.W, H=wl.H, m=m_bins, workspace=wsb)
         ab = pp.bin_coeffs(Pb, W=wl.W, H=wl.H, Mu=Mb, Mp=Mb, workspace=wsb)
-        pp.bin_field(ab, W=wl.W, H=wl.H, m=m_bins, workspace=wsb)
+        fb = pp.bin_field(ab, W=wl.W, H=wl.H, m=m_bins, workspace=wsb)
+        pp.bin_interp(*t, None, fb[1], fb[2], W=wl.W, H=wl.H, workspace=wsb)
         torch.cuda.synchronize()
         pp.timing_enable(True)
         Pb = pp.bin_density(*t, W=wl.W, H=wl.H, m=m_bins, workspace=wsb)
         ab = pp.bin_coeffs(Pb, W=wl.W, H=wl.H, Mu=Mb, Mp=Mb, workspace=wsb)
         fb = pp.bin_field(ab, W=wl.W, H=wl.H, m=m_bins, workspace=wsb)
+        _, gxb, gyb = pp.bin_interp(*t, None, fb[1], fb[2], W=wl.W, H=wl.H, workspace=wsb)
         torch.cuda.synchronize()
         td, _ = pp.timing_query("bin_density")
         tcf, _ = pp.timing_query("bin_coeffs")
         tf, _ = pp.timing_query("bin_field")
+        ti, _ = pp.timing_query("bin_interp")
         pp.timing_enable(False)
         gemm_flops = 2.0 * m_bins * Mb * m_bins + 2.0 * Mb * Mb * m_bins + 2 * 2.0 * Mb * m_bins * Mb \
             + 3 * 2.0 * m_bins * m_bins * Mb
         if ref is not None:
-            a_dir, dir_name = ref[1], "fp64 direct sum (GPU)"
+            a_dir, g_dir, dir_name = ref[1], (ref[2], ref[3]), "fp64 direct sum (GPU)"
         else:
-            a_dir, dir_name = a, f"{args.precision} direct sum (GPU)"
+            a_dir, g_dir, dir_name = a, (gx, gy), f"{args.precision} direct sum (GPU)"
         a_dir = a_dir[:Mb, :Mb].contiguous()
         fd = pp.bin_field(a_dir, W=wl.W, H=wl.H, m=m_bins, workspace=wsb)
         abn, adn = ab.cpu().numpy(), a_dir.cpu().numpy()
         lo = min(64, Mb)
-        bins = {"m": m_bins, "M": Mb, "density_ms": td, "coeffs_ms": tcf, "field_ms": tf,
+        gbin = np.concatenate([gxb.cpu().numpy(), gyb.cpu().numpy()])
+        gdir = np.concatenate([g_dir[0].cpu().numpy(), g_dir[1].cpu().numpy()])
+        bins = {"m": m_bins, "M": Mb, "density_ms": td, "coeffs_ms": tcf, "field_ms": tf, "interp_ms": ti,
+                "total_ms": td + tcf + tf + ti,
                 "transform_gemm_tflops_fp64": round(gemm_flops / ((tcf + tf) * 1e-3) / 1e12, 2),
                 "compared_with": dir_name,
                 "coeffs_rel_diff": rel(abn, adn),
                 f"coeffs_rel_diff_u_p_below_{lo}": rel(abn[:lo, :lo], adn[:lo, :lo]),
                 "psi_rel_diff_at_bin_centres": rel(fb[0].cpu().numpy(), fd[0].cpu().numpy()),
                 "xi_rel_diff_at_bin_centres": rel(np.concatenate([fb[1].cpu().numpy(), fb[2].cpu().numpy()]),
-                                                  np.concatenate([fd[1].cpu().numpy(), fd[2].cpu().numpy()]))}
+                                                  np.concatenate([fd[1].cpu().numpy(), fd[2].cpu().numpy()])),
+                "block_gradient_rel_diff": rel(gbin, gdir)}
         out["bin_scheme"] = bins
-        log(f"[bench] bin scheme m={m_bins}: density {td:.2f} ms, coefficients {tcf:.2f} ms, field {tf:.2f} ms; "
-            f"vs direct: a {bins['coeffs_rel_diff']:.3e}, psi {bins['psi_rel_diff_at_bin_centres']:.3e}, "
-            f"xi {bins['xi_rel_diff_at_bin_centres']:.3e}")
+        log(f"[bench] bin scheme m={m_bins}: density {td:.2f} ms, coefficients {tcf:.2f} ms, field {tf:.2f} ms, "
+            f"interpolation {ti:.2f} ms; vs direct: a {bins['coeffs_rel_diff']:.3e}, "
+            f"psi {bins['psi_rel_diff_at_bin_centres']:.3e}, xi {bins['xi_rel_diff_at_bin_centres']:.3e}, "
+            f"block gradient {bins['block_gradient_rel_diff']:.3e}")
 
     if not args.no_accuracy:
         import oracle

@@ -186,6 +186,23 @@ int pp_bin_coeffs(const pp_bin_problem *B, const double *P, double *a, void *ws,
 int pp_bin_field(const pp_bin_problem *B, const double *a, double *psi, double *xix, double *xiy, void *ws,
                  size_t ws_bytes, void *stream);
 
+/* Block values from the bin-centre values (Sec. III-D, the final step of the fast scheme, whose
+ * weights the text leaves open): each block takes the integral over its area of the bin values
+ * held constant on each bin, i.e. the overlap-area weighted sum over the bins it covers,
+ *   N[i]  =  sum_lj |block i cap bin lj| psi[l, j],
+ *   gx[i] = -sum_lj |block i cap bin lj| xix[l, j],   gy[i] = -sum_lj |block i cap bin lj| xiy[l, j],
+ * the bin-scheme counterparts of pp_block_potential and of the gradient of pp_field.  Block parts
+ * outside the region take no bin.
+ * x, y, w, h: in [B->n] FP64 blocks.  psi, xix, xiy: in [m * m] FP64 (pp_bin_field).  N, gx, gy:
+ * out [B->n] FP64, none aliasing an input.  Each (field, output) pair is both NULL (skipped) or
+ * both given; a NULL in only one of a pair is PP_ERR_ARG.  With B->n = 0 nothing is read or
+ * written and every pointer may be NULL.  Results do not depend on scheduling
+ * (per-block sums in a fixed order; blocks over more than 16 bins are summed by one workgroup
+ * with a fixed-order reduction). */
+int pp_bin_interp(const pp_bin_problem *B, const double *x, const double *y, const double *w, const double *h,
+                  const double *psi, const double *xix, const double *xiy, double *N, double *gx, double *gy,
+                  void *ws, size_t ws_bytes, void *stream);
+
 /* Static description of a status code. */
 const char *pp_strerror(int status);
 
@@ -200,7 +217,7 @@ const char *pp_strerror(int status);
  * contractions, one record each), "final" (per-block partial sums), "build" (store-mode basis
  * tables), "point" (pp_point_field
  * contractions), "potential" (pp_block_potential contraction), "bin_density", "bin_coeffs",
- * "bin_field" (the bin scheme, all launches of one call in one record).  Unknown names give count 0.
+ * "bin_field", "bin_interp" (the bin scheme, all launches of one call in one record).  Unknown names give count 0.
  * Returns PP_OK, PP_ERR_ARG for NULL arguments, PP_ERR_DEVICE if an event query fails.  Recording
  * is process wide and guarded by a lock; it is meant for benchmarks, not for production calls. */
 int pp_timing_enable(int on);

@@ -30,7 +30,7 @@ BASIS_MODES = {"recompute": 0, "store": 1}
 PP_OK = 0
 EXPORTS = ("pp_workspace_size", "pp_coeffs", "pp_energy", "pp_field", "pp_point_field", "pp_block_potential",
            "pp_strerror", "pp_timing_enable", "pp_timing_query", "pp_bin_workspace_size", "pp_bin_density",
-           "pp_bin_coeffs", "pp_bin_field")
+           "pp_bin_coeffs", "pp_bin_field", "pp_bin_interp")
 
 
 class PPError(RuntimeError):
@@ -84,8 +84,9 @@ def load():
     lib.pp_bin_density.argtypes = [B, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.pp_bin_coeffs.argtypes = [B, vp, vp, vp, sz, vp]
     lib.pp_bin_field.argtypes = [B, vp, vp, vp, vp, vp, sz, vp]
+    lib.pp_bin_interp.argtypes = [B, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     for f in ("pp_workspace_size", "pp_coeffs", "pp_energy", "pp_field", "pp_point_field", "pp_block_potential",
-              "pp_bin_workspace_size", "pp_bin_density", "pp_bin_coeffs", "pp_bin_field"):
+              "pp_bin_workspace_size", "pp_bin_density", "pp_bin_coeffs", "pp_bin_field", "pp_bin_interp"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -330,6 +331,29 @@ def bin_field(a, *, W, H, m, want=("psi", "xix", "xiy"), workspace=None):
     if st != PP_OK:
         raise PPError(st, "pp_bin_field")
     return outs["psi"], outs["xix"], outs["xiy"]
+
+
+def bin_interp(x, y, w, h, psi=None, xix=None, xiy=None, *, W, H, workspace=None):
+    """Block values from bin values (N, gx, gy): N_i = sum over the bins of |block i cap bin| psi,
+    gx_i = -sum |block i cap bin| xi_x, gy_i likewise; an output is None when its field is None."""
+    dev, n = _blocks(x, y, w, h)
+    fields = (psi, xix, xiy)
+    given = [f for f in fields if f is not None]
+    if not given:
+        raise ValueError("give at least one of psi, xix, xiy")
+    m = given[0].shape[0]
+    for f, name in zip(fields, ("psi", "xix", "xiy")):
+        if f is not None:
+            _bin_matrix(f, m, m, dev, name)
+    B = _bin_problem(W, H, n, m, 1, 1)
+    outs = [torch.empty(n, dtype=torch.float64, device=dev) if f is not None else None for f in fields]
+    ws, nb = _bin_ws(B, dev, workspace)
+    with torch.cuda.device(dev):
+        st = load().pp_bin_interp(ctypes.byref(B), _vp(x), _vp(y), _vp(w), _vp(h), *[_vp(f) for f in fields],
+                                  *[_vp(o) for o in outs], _vp(ws), nb, _stream(dev))
+    if st != PP_OK:
+        raise PPError(st, "pp_bin_interp")
+    return tuple(outs)
 
 
 def timing_enable(on: bool) -> None:

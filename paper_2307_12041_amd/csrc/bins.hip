@@ -1,6 +1,6 @@
 // bins.hip -- the bin scheme of Sec. III-D as a comparison path for the direct sum: exact bin
-// densities, the binned coefficients (eqs. disa-a..d) and the potential and field at the bin
-// centres (eqs. dis-psi1, dis-ksi), all in FP64.
+// densities, the binned coefficients (eqs. disa-a..d), the potential and field at the bin
+// centres (eqs. dis-psi1, dis-ksi) and the block values weighted from the bins, all in FP64.
 //
 // The two cosine transforms of the coefficients and the inverse transforms of the field are
 // separable: with C_f(s) = cos(f (2s+1) pi / (2m)) and S_f(s) = sin(...),
@@ -88,6 +88,97 @@ __global__ void k_bin_density_big(const double *__restrict__ x, const double *__
         const int64_t nb = (int64_t)(l1 - l0 + 1) * nj;
         for (int64_t b = threadIdx.x; b < nb; b += blockDim.x)
             bin_add(g, P, x0, x1, y0, y1, l0 + (int)(b / nj), j0 + (int)(b % nj));
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Block values from bin values (the last step of the scheme): each block takes the overlap-area
+// weighted sum of the bins it covers, out_k[i] = sign_k sum_lj |block i cap bin lj| v_k[l, j], for
+// the fields k that are present (psi -> N with sign +1, xi_x -> gx and xi_y -> gy with sign -1).
+// One thread per block sums a block of up to kSmallBins bins in a fixed order; larger blocks go to
+// a list, and one workgroup per listed block sums its bins and reduces in LDS in a fixed order, so
+// every result is independent of scheduling.
+// ------------------------------------------------------------------------------------------------
+struct InterpIO {
+    const double *v[3];
+    double *out[3];
+};
+
+__device__ __forceinline__ void interp_bin(const BinGeom &g, const InterpIO &io, double x0, double x1, double y0,
+                                           double y1, int l, int j, double acc[3]) {
+    const double ox = fmin(x1, (l + 1) * g.wb) - fmax(x0, l * g.wb);
+    const double oy = fmin(y1, (j + 1) * g.hb) - fmax(y0, j * g.hb);
+    if (ox > 0.0 && oy > 0.0) {
+        const double area = ox * oy;
+        const size_t b = (size_t)l * g.m + j;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (io.v[k]) acc[k] = fma(area, io.v[k][b], acc[k]);
+    }
+}
+
+__device__ __forceinline__ void interp_store(const InterpIO &io, int64_t i, const double acc[3]) {
+    if (io.v[0]) io.out[0][i] = acc[0];
+    if (io.v[1]) io.out[1][i] = -acc[1];
+    if (io.v[2]) io.out[2][i] = -acc[2];
+}
+
+__global__ void k_bin_interp(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+                             const double *__restrict__ w, const double *__restrict__ h, BinGeom g, InterpIO io,
+                             int *__restrict__ big, int *__restrict__ nbig) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double x0 = x[i] - 0.5 * w[i], x1 = x[i] + 0.5 * w[i];
+    const double y0 = y[i] - 0.5 * h[i], y1 = y[i] + 0.5 * h[i];
+    int l0, l1, j0, j1;
+    bin_range(g, x0, x1, y0, y1, l0, l1, j0, j1);
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (l1 >= l0 && j1 >= j0) {
+        if ((int64_t)(l1 - l0 + 1) * (j1 - j0 + 1) > kSmallBins) {
+            big[atomicAdd(nbig, 1)] = (int)i;
+            return;
+        }
+        for (int l = l0; l <= l1; ++l)
+            for (int j = j0; j <= j1; ++j) interp_bin(g, io, x0, x1, y0, y1, l, j, acc);
+    }
+    interp_store(io, i, acc);
+}
+
+constexpr int kInterpThreads = 256;
+
+__global__ __launch_bounds__(kInterpThreads) void k_bin_interp_big(const double *__restrict__ x,
+                                                                   const double *__restrict__ y,
+                                                                   const double *__restrict__ w,
+                                                                   const double *__restrict__ h, BinGeom g,
+                                                                   InterpIO io, const int *__restrict__ big,
+                                                                   const int *__restrict__ nbig) {
+    __shared__ double red[3][kInterpThreads];
+    const int count = *nbig;
+    for (int t = blockIdx.x; t < count; t += gridDim.x) {
+        const int i = big[t];
+        const double x0 = x[i] - 0.5 * w[i], x1 = x[i] + 0.5 * w[i];
+        const double y0 = y[i] - 0.5 * h[i], y1 = y[i] + 0.5 * h[i];
+        int l0, l1, j0, j1;
+        bin_range(g, x0, x1, y0, y1, l0, l1, j0, j1);
+        const int nj = j1 - j0 + 1;
+        const int64_t nb = (int64_t)(l1 - l0 + 1) * nj;
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int64_t b = threadIdx.x; b < nb; b += kInterpThreads)
+            interp_bin(g, io, x0, x1, y0, y1, l0 + (int)(b / nj), j0 + (int)(b % nj), acc);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = acc[k];
+        __syncthreads();
+        for (int half = kInterpThreads / 2; half > 0; half >>= 1) {
+            if ((int)threadIdx.x < half)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + half];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const double tot[3] = {red[0][0], red[1][0], red[2][0]};
+            interp_store(io, i, tot);
+        }
+        __syncthreads();
     }
 }
 
@@ -358,6 +449,33 @@ int pp_bin_field(const pp_bin_problem *B, const double *a, double *psi, double *
         return PP_ERR_DEVICE;
     if (xiy && gemm(m, m, Mu, trig(1, false, 0.0), dense(Rs, m), tab, m, xiy, m, false, B->W, B->H, s) != hipSuccess)
         return PP_ERR_DEVICE;
+    return PP_OK;
+}
+
+int pp_bin_interp(const pp_bin_problem *B, const double *x, const double *y, const double *w, const double *h,
+                  const double *psi, const double *xix, const double *xiy, double *N, double *gx, double *gy, void *ws,
+                  size_t ws_bytes, void *stream) {
+    int st = check_bin_problem(B);
+    if (st != PP_OK) return st;
+    if (B->n == 0) return PP_OK;   // nothing read or written
+    if (!psi != !N || !xix != !gx || !xiy != !gy) return PP_ERR_ARG;
+    const void *ptrs[6] = {psi, xix, xiy, N, gx, gy};
+    for (const void *p : ptrs)
+        if (p && !al8(p)) return PP_ERR_ARG;
+    if (!x || !y || !w || !h || !al8(x) || !al8(y) || !al8(w) || !al8(h)) return PP_ERR_ARG;
+    if ((st = check_ws(B, ws, ws_bytes)) != PP_OK) return st;
+    if (!psi && !xix && !xiy) return PP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const BinLayout L = bin_layout(*B);
+    int *list = (int *)((char *)ws + L.list);
+    BinGeom g{B->W, B->H, B->W / B->m, B->H / B->m, 1.0 / ((B->W / B->m) * (B->H / B->m)), B->m};
+    InterpIO io{{psi, xix, xiy}, {N, gx, gy}};
+    TimedLaunch t("bin_interp", s);
+    hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(64), 0, s, list);
+    hipLaunchKernelGGL(k_bin_interp, dim3((unsigned)((B->n + 255) / 256)), dim3(256), 0, s, B->n, x, y, w, h, g, io,
+                       list + 1, list);
+    hipLaunchKernelGGL(k_bin_interp_big, dim3(1024), dim3(kInterpThreads), 0, s, x, y, w, h, g, io, list + 1, list);
+    if (hipGetLastError() != hipSuccess) return PP_ERR_DEVICE;
     return PP_OK;
 }
 

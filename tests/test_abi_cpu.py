@@ -202,3 +202,17 @@ def test_bin_entry_points_validate_before_launch(lib):
     assert bf(ctypes.byref(prob), fake, fake, fake, fake, fake, need - 1, nul) == -2
     # nothing requested: nothing to do, after validation
     assert bf(ctypes.byref(prob), fake, nul, nul, nul, fake, need, nul) == 0
+    bi = lib.pp_bin_interp
+    blocks = (fake, fake, fake, fake)
+    assert bi(None, *blocks, fake, nul, nul, fake, nul, nul, fake, need, nul) == -1
+    # a field without its output, or an output without its field
+    assert bi(ctypes.byref(prob), *blocks, fake, nul, nul, nul, nul, nul, fake, need, nul) == -1
+    assert bi(ctypes.byref(prob), *blocks, nul, nul, nul, nul, fake, nul, fake, need, nul) == -1
+    assert bi(ctypes.byref(prob), *blocks, nul, nul, fake, nul, nul, odd, fake, need, nul) == -1
+    assert bi(ctypes.byref(prob), nul, fake, fake, fake, fake, nul, nul, fake, nul, nul, fake, need, nul) == -1
+    assert bi(ctypes.byref(prob), *blocks, fake, nul, nul, fake, nul, nul, fake, need - 1, nul) == -2
+    assert bi(ctypes.byref(prob), *blocks, fake, nul, nul, fake, nul, nul, ws_odd, need, nul) == -1
+    # no blocks (any pointer may be NULL), or no field: nothing to do, after validation
+    assert bi(ctypes.byref(BP(n=0)), nul, nul, nul, nul, fake, nul, nul, nul, nul, nul, nul, 0, nul) == 0
+    assert bi(ctypes.byref(BP(n=0, m=0)), nul, nul, nul, nul, fake, nul, nul, nul, nul, nul, nul, 0, nul) == -1
+    assert bi(ctypes.byref(prob), *blocks, nul, nul, nul, nul, nul, nul, fake, need, nul) == 0

@@ -1,4 +1,6 @@
-"""The bin scheme of Sec. III-D (the comparison path) on the GPU against the FP64 oracle.
+"""The bin scheme of Sec. III-D (the comparison path) on the GPU against the FP64 oracle:
+densities, coefficients, bin-centre potential and field, and the block values weighted back
+from the bins.
 
 Bars: FP64 throughout, 1e-12 relative to the largest magnitude of each output (the densities are
 FP64 atomic sums, so their last bits depend on the order of arrival; the transforms are FP64
@@ -104,6 +106,43 @@ def test_bin_pipeline_matches_oracle_pipeline():
     assert relmax(a.cpu().numpy(), ao) <= TOL
     assert relmax(psi.cpu().numpy(), po) <= TOL
     assert relmax(xix.cpu().numpy(), xo) <= TOL and relmax(xiy.cpu().numpy(), yo) <= TOL
+    N, gx, gy = pp.bin_interp(*dev(x, y, w, h), psi, xix, xiy, W=W, H=H, workspace=ws)
+    No, gxo, gyo = oracle.bin_interp(W, H, x, y, w, h, m, po, xo, yo)
+    assert relmax(N.cpu().numpy(), No) <= TOL
+    assert relmax(gx.cpu().numpy(), gxo) <= TOL and relmax(gy.cpu().numpy(), gyo) <= TOL
+
+
+@pytest.mark.parametrize("m", [1, 7, 64, 200])
+def test_bin_interp_parity(m):
+    W, H = 300.0, 170.0
+    x, y, w, h = mixed_blocks(3000, W, H, seed=40 + m)
+    rng = np.random.default_rng(m)
+    fields = [rng.normal(size=(m, m)) for _ in range(3)]
+    say(f"[bins] interp m={m} n={len(x)}")
+    got = pp.bin_interp(*dev(x, y, w, h), *dev(*fields), W=W, H=H)
+    ref = oracle.bin_interp(W, H, x, y, w, h, m, *fields)
+    for g, r in zip(got, ref):
+        assert relmax(g.cpu().numpy(), r) <= TOL
+
+
+def test_bin_interp_pairs_and_determinism():
+    W, H, m = 90.0, 60.0, 40
+    x, y, w, h = mixed_blocks(5000, W, H, seed=3, n_macros=30)
+    rng = np.random.default_rng(9)
+    psi, xix, xiy = dev(*[rng.normal(size=(m, m)) for _ in range(3)])
+    t = dev(x, y, w, h)
+    say("[bins] interp pairs")
+    full = [o.cpu().numpy() for o in pp.bin_interp(*t, psi, xix, xiy, W=W, H=H)]
+    again = [o.cpu().numpy() for o in pp.bin_interp(*t, psi, xix, xiy, W=W, H=H)]
+    # per-block sums in a fixed order (one workgroup with a fixed-order reduction for big blocks)
+    assert all(np.array_equal(a, b) for a, b in zip(full, again))
+    N, n1, n2 = pp.bin_interp(*t, psi, W=W, H=H)
+    assert n1 is None and n2 is None and np.array_equal(N.cpu().numpy(), full[0])
+    n0, n1, gy = pp.bin_interp(*t, xiy=xiy, W=W, H=H)
+    assert n0 is None and n1 is None and np.array_equal(gy.cpu().numpy(), full[2])
+    e = torch.empty(0, dtype=torch.float64, device=DEV)
+    N0, _, _ = pp.bin_interp(e, e, e, e, psi, W=W, H=H)
+    assert N0.numel() == 0
 
 
 def test_bin_full_grid_2m_blocks_sampled():
@@ -136,3 +175,11 @@ def test_bin_full_grid_2m_blocks_sampled():
     for got, want in ((psi, ps_), (xix, ex), (xiy, ey)):
         g = got.cpu().numpy()[sl, sj]
         assert np.abs(g - want).max() <= 1e-11 * np.abs(got.cpu().numpy()).max()
+    # block values from the bins: sampled blocks (all macros among them) against the oracle
+    N, gx, gy = pp.bin_interp(x, y, w, h, psi, xix, xiy, W=wl.W, H=wl.H)
+    idx = np.concatenate([rng.choice(wl.n, 200, replace=False), np.argsort(wl.w * wl.h)[-20:]])
+    arrs = [v[idx] for v in wl.arrays()]
+    No, gxo, gyo = oracle.bin_interp(wl.W, wl.H, *arrs, m, psi.cpu().numpy(), xix.cpu().numpy(), xiy.cpu().numpy())
+    for got, want in ((N, No), (gx, gxo), (gy, gyo)):
+        g = got.cpu().numpy()
+        assert np.abs(g[idx] - want).max() <= TOL * np.abs(g).max()
