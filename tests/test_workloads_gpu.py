@@ -1,5 +1,10 @@
 """The large workloads at full size, on the GPU.
 
+* 2,000,000 cells + 500 macros in 16384 x 16384, M = 2048 x 2048, in the benchmark's launch
+  configuration (BF16X3, basis regenerated on chip, one caller workspace for energy and gradient):
+  sampled coefficients against the oracle (each a direct sum over all blocks); the gradient of
+  seeded synthetic coefficients at sampled blocks (the largest macros among them) against the
+  oracle, in BF16X3 and FP64; and E = 1/2 sum_up a_up^2 / s_up over the GPU's own coefficients.
 * 1,000,000 cells in 16 Gaussian clusters (sigma 800) in 16384 x 16384, M = 1024 x 1024: forces from
   the differentiable energy (torch.autograd through the hand-written backward) against central
   differences with h = 1e-3 on 100 seeded random blocks, and sampled coefficients against the oracle.
@@ -7,9 +12,11 @@
   evaluations with N(0, 1) jittered positions; sampled coefficients against the oracle at the first
   and last iteration and the central-difference check of the forces at the last.
 
-The central differences use the exact rank-one energy change of one moved block
-(tests/fd_rank1.py, pinned against the oracle's gradient on the CPU) with the FP64 GPU coefficients
-of the same blocks, so they hold at any size.
+Expected values come from the oracle and seeded inputs only.  The central differences are a
+consistency property of the GPU's own outputs (its forces are the derivative of its energy): they
+use the exact rank-one energy change of one moved block (tests/fd_rank1.py, pinned against the
+oracle's gradient on the CPU) with the FP64 GPU coefficients of the same blocks, so they hold at any
+size; the oracle comparisons of the gradient use seeded coefficients instead.
 """
 import sys
 
@@ -17,7 +24,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.fd_rank1 import central_difference
+from tests.fd_rank1 import _scale, central_difference
 from workloads import jitter, make_config
 
 torch = pytest.importorskip("torch")
@@ -41,6 +48,54 @@ def sample_uv(Mu, Mp, k, seed):
     us = np.concatenate([[1, 0, 1, 2], rng.integers(0, Mu, k - 4)])
     ps = np.concatenate([[0, 1, 1, 3], rng.integers(0, Mp, k - 4)])
     return us, ps
+
+
+def seeded_coeffs(Mu, Mp, seed):
+    """Synthetic coefficients with the spectrum of real ones (falling like 1/(u^2 + p^2)), a_00 = 0."""
+    rng = np.random.default_rng(seed)
+    u, p = np.meshgrid(np.arange(Mu), np.arange(Mp), indexing="ij")
+    a = rng.normal(size=(Mu, Mp)) / (1.0 + u * u + p * p)
+    a[0, 0] = 0.0
+    return a
+
+
+def test_bench_workload_cells2m_macros500_M2048():
+    wl = make_config(4)
+    say(f"[workload] {wl.name} n={wl.n} Mu={wl.Mu} Mp={wl.Mp}, bf16x3 recompute")
+    x, y, w, h = (torch.as_tensor(v, device=DEV) for v in wl.arrays())
+    need = pp.workspace_size(wl.W, wl.H, wl.n, wl.Mu, wl.Mp, precision="bf16x3")
+    ws = torch.empty(need, dtype=torch.uint8, device=DEV)
+    E, a = pp.energy(x, y, w, h, W=wl.W, H=wl.H, Mu=wl.Mu, Mp=wl.Mp, precision="bf16x3", workspace=ws)
+    gx, gy = pp.field(x, y, w, h, a, W=wl.W, H=wl.H, precision="bf16x3", workspace=ws)
+    torch.cuda.synchronize()
+    an = a.cpu().numpy()
+    assert bool(torch.isfinite(gx).all()) and bool(torch.isfinite(gy).all())
+    # coefficients: sampled (u, p), each a direct oracle sum over all 2,000,500 blocks
+    us, ps = sample_uv(wl.Mu, wl.Mp, 32, 4)
+    us[-2:], ps[-2:] = (wl.Mu - 1, 0), (0, wl.Mp - 1)
+    ao, _ = oracle.coeffs_sampled(wl.W, wl.H, *wl.arrays(), us, ps)
+    ea = rel(an[us, ps], ao)
+    # energy over the GPU's own coefficients: E = 1/2 sum a^2 / s (a = s A)
+    s = _scale(wl.W, wl.H, wl.Mu, wl.Mp)
+    nz = s > 0
+    Ev = float(E.cpu())
+    eE = abs(0.5 * np.sum(an[nz] ** 2 / s[nz]) - Ev) / Ev
+    say(f"   sampled coefficients vs oracle {ea:.2e}; |E - 1/2 sum a^2/s| / E = {eE:.2e}")
+    assert ea < 1e-3 and eE < 1e-6
+    # gradient of seeded coefficients at sampled blocks, the 16 largest macros among them
+    a_syn = seeded_coeffs(wl.Mu, wl.Mp, 44)
+    a_dev = torch.as_tensor(a_syn, device=DEV)
+    idx = np.unique(np.concatenate([np.random.default_rng(44).choice(wl.n, 48, replace=False),
+                                    np.argsort(wl.w * wl.h)[-16:]]))
+    gxo, gyo = oracle.grad_sampled(wl.W, wl.H, *wl.arrays(), a_syn, idx)
+    go = np.concatenate([gxo, gyo])
+    for prec, tol in (("bf16x3", 1e-3), ("fp64", 1e-10)):
+        gxs, gys = pp.field(x, y, w, h, a_dev, W=wl.W, H=wl.H, precision=prec, workspace=ws if prec == "bf16x3"
+                            else None)
+        torch.cuda.synchronize()
+        eg = rel(np.concatenate([gxs.cpu().numpy()[idx], gys.cpu().numpy()[idx]]), go)
+        say(f"   {prec} gradient of seeded coefficients at {len(idx)} blocks vs oracle {eg:.2e}")
+        assert eg < tol, (prec, eg)
 
 
 def test_clusters_1m_autograd_forces_vs_central_differences():
@@ -106,6 +161,14 @@ def test_clusters_10m_jittered_iterations():
             g = np.concatenate([gx.cpu().numpy()[idx], gy.cpu().numpy()[idx]])
             eg = rel(g, np.concatenate([fx, fy]))
             say(f"   forces vs central differences of the same coefficients: {eg:.2e}")
+            assert eg < 1e-3
+            a_syn = seeded_coeffs(wl.Mu, wl.Mp, 55)
+            gxs, gys = pp.field(x, y, w, h, torch.as_tensor(a_syn, device=DEV), W=wl.W, H=wl.H,
+                                precision="bf16x3", workspace=ws)
+            torch.cuda.synchronize()
+            gxo, gyo = oracle.grad_sampled(wl.W, wl.H, *wl.arrays(), a_syn, idx)
+            eg = rel(np.concatenate([gxs.cpu().numpy()[idx], gys.cpu().numpy()[idx]]), np.concatenate([gxo, gyo]))
+            say(f"   gradient of seeded coefficients vs oracle: {eg:.2e}")
             assert eg < 1e-3
     # jitter of sigma = 1 on 32768 x 16384 barely moves the energy
     assert max(energies) / min(energies) < 1.01
