@@ -123,9 +123,9 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
+        print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
               "the multi-GPU sharding (blocks split over GPUs, one all-reduce of the Mu x Mp moments) is a "
-              "design, not part of this build", file=sys.stderr)
+              "design, not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch

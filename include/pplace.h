@@ -54,7 +54,7 @@ typedef enum pp_status {
     PP_OK = 0,
     PP_ERR_ARG = -1,          /* NULL pointer, bad size, non-finite or non-positive W/H, misalignment */
     PP_ERR_WORKSPACE = -2,    /* ws_bytes smaller than pp_workspace_size() */
-    PP_ERR_UNSUPPORTED = -3,  /* precision / basis mode not available in this build */
+    PP_ERR_UNSUPPORTED = -3,  /* precision / basis mode not implemented by the library */
     PP_ERR_DEVICE = -4        /* a HIP launch or runtime call failed */
 } pp_status;
 

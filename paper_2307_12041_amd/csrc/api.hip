@@ -437,7 +437,7 @@ const char *pp_strerror(int status) {
         case PP_OK: return "success";
         case PP_ERR_ARG: return "invalid argument (NULL or misaligned pointer, bad size, non-finite or non-positive region)";
         case PP_ERR_WORKSPACE: return "workspace smaller than pp_workspace_size()";
-        case PP_ERR_UNSUPPORTED: return "precision or basis mode not supported by this build";
+        case PP_ERR_UNSUPPORTED: return "precision or basis mode not implemented by the library";
         case PP_ERR_DEVICE: return "HIP launch or runtime error";
         default: return "unknown status";
     }
