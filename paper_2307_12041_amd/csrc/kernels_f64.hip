@@ -192,10 +192,13 @@ __global__ __launch_bounds__(256) void k_fwd_mat(int64_t n, int Mu, int Mp, doub
 // with Bas of kind KK_KIND along the K axis and E of kind EP1 (and, if EP2 >= 0, a second
 // epilogue of kind EP2 on the same Z into gpart2).  Grid (tiles_b, tiles_n), 256 threads as 2 x 2
 // waves.  LDS: As[k][i] (generated basis), Bs[k][j] (prepared operand); after the K loop the same
-// space holds the epilogue basis of one half of the N tile, Es[j][i].
+// space holds the epilogue basis of one half of the N tile, Es[j][i].  Two waves per SIMD (at most
+// 256 registers per lane; FP64 fits without spills): the LDS (68 KB in FP64) admits two workgroups
+// per CU, so one workgroup's MFMAs run while the other generates its next basis chunk and loads
+// its next operand chunk, which sit between barriers.
 // ------------------------------------------------------------------------------------------------
 template <typename T, int TB, int TN, int KK, int KA_KIND, int EP1, int EP2>
-__global__ __launch_bounds__(256) void k_bwd_mat(int64_t n, BwdAxis ax) {
+__global__ __launch_bounds__(256, 2) void k_bwd_mat(int64_t n, BwdAxis ax) {
     typedef typename Mat<T>::v4 v4;
     constexpr int LB = TB + 1, LN = TN + 1;
     constexpr int HALF = TN / 2;

@@ -95,6 +95,17 @@ def test_extreme_aspect_ratios(prec, W, H, Mu, Mp):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("W,H,Mu,Mp", [(1000.0, 300.0, 65536, 2), (500.0, 2000.0, 3, 65536)])
+def test_maximum_frequency_count(prec, W, H, Mu, Mp):
+    """The largest truncation the ABI accepts along one axis (65536 frequencies: 256 tiles of the
+    bf16 kernels, 1024 K chunks of the gy contraction), 41 blocks (one whole chunk and a ragged one)."""
+    wl = make_random(41, W, H, Mu, Mp, seed=59, wmax=W / 8, hmax=H / 8)
+    errs = full_check(wl, prec)
+    say(f"[edge] {W}x{H} M={Mu}x{Mp} {prec}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    assert max(errs.values()) <= TOL[prec], errs
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_tiny_huge_and_boundary_blocks(prec):
     """Blocks of width 1e-3, blocks as large as the region, and blocks whose edge lies on the
     region boundary, mixed with ordinary ones."""
