@@ -45,7 +45,7 @@ FwdPlan fwd_plan(const pp_problem &P) {
     if (is_bf16(P.precision)) {
         pl.tu = 256; pl.tp = 256; pl.kb = 32;
     } else if (P.Mu >= 128 && P.Mp >= 128) {
-        pl.tu = 128; pl.tp = 128; pl.kb = 16;
+        pl.tu = 128; pl.tp = 128; pl.kb = 32;
     } else {
         pl.tu = 64; pl.tp = 64; pl.kb = 32;
     }

@@ -307,8 +307,8 @@ template <typename T>
 hipError_t launch_fwd_mat(const FwdPlan &pl, int64_t n, int Mu, int Mp, double W, double H, const double *x,
                           const double *y, const double *w, const double *h, T *part, hipStream_t s) {
     dim3 grid(pl.tiles_u * pl.tiles_p, pl.splits);
-    if (pl.tu == 128 && pl.tp == 128 && pl.kb == 16)
-        hipLaunchKernelGGL((k_fwd_mat<T, 128, 128, 16>), grid, dim3(256), 0, s, n, Mu, Mp, W, H, x, y, w, h, part,
+    if (pl.tu == 128 && pl.tp == 128 && pl.kb == 32)
+        hipLaunchKernelGGL((k_fwd_mat<T, 128, 128, 32>), grid, dim3(256), 0, s, n, Mu, Mp, W, H, x, y, w, h, part,
                            pl.tiles_p, pl.chunks, pl.chunks_per_split);
     else if (pl.tu == 64 && pl.tp == 64 && pl.kb == 32)
         hipLaunchKernelGGL((k_fwd_mat<T, 64, 64, 32>), grid, dim3(256), 0, s, n, Mu, Mp, W, H, x, y, w, h, part,
