@@ -112,6 +112,76 @@ __device__ __forceinline__ void gen_run(double c, double sz, double L, int k0, b
     }
 }
 
+// A run of R consecutive frequencies of one block that moves on by J frequencies every K chunk (the
+// row-form contraction, where a thread keeps its block for the whole K loop): the seed phasors at
+// the run's first frequency, the one-frequency step and the J-frequency jump come from FP64
+// sincospi of exactly reduced arguments once; after each chunk the seeds are rotated by the jump
+// instead of being evaluated again (one complex product per edge against two sincospi).
+template <int KIND>
+struct KRun {
+    static constexpr bool kEdge = KIND == RUN_SINDIFF || KIND == RUN_COSDIFF;
+    double cp, sp, cm, sm;        // seeds (point kinds use cp, sp)
+    double c1p, s1p, c1m, s1m;    // one-frequency step
+    double cjp, sjp, cjm, sjm;    // J-frequency jump
+    double sz, pil;
+
+    __device__ __forceinline__ void init(double c, double size, double L, int k0, int J) {
+        sz = size;
+        pil = kPi / L;
+        const double tp = kEdge ? (c + 0.5 * size) / L : c / L;
+        sincospi(reduce_half_turns((double)k0 * tp), &sp, &cp);
+        sincospi(reduce_half_turns(tp), &s1p, &c1p);
+        sincospi(reduce_half_turns((double)J * tp), &sjp, &cjp);
+        if constexpr (kEdge) {
+            const double tm = (c - 0.5 * size) / L;
+            sincospi(reduce_half_turns((double)k0 * tm), &sm, &cm);
+            sincospi(reduce_half_turns(tm), &s1m, &c1m);
+            sincospi(reduce_half_turns((double)J * tm), &sjm, &cjm);
+        }
+    }
+
+    // The R values at frequencies k0 .. k0 + R - 1, written at dst[k * stride] (rounded to T).
+    template <int R, typename T>
+    __device__ __forceinline__ void gen(int k0, bool valid, T *dst, int stride) const {
+        if (!valid) {
+#pragma unroll
+            for (int k = 0; k < R; ++k) dst[k * stride] = (T)0;
+            return;
+        }
+        double a = cp, b = sp, e = cm, f = sm;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            if constexpr (KIND == RUN_SINDIFF)
+                dst[k * stride] = (T)((k0 + k == 0) ? sz : (b - f));
+            else if constexpr (KIND == RUN_COSDIFF)
+                dst[k * stride] = (T)(a - e);
+            else if constexpr (KIND == RUN_COS)
+                dst[k * stride] = (T)a;
+            else
+                dst[k * stride] = (T)((double)(k0 + k) * pil * b);
+            const double t = a * c1p - b * s1p;
+            b = b * c1p + a * s1p;
+            a = t;
+            if constexpr (kEdge) {
+                const double u = e * c1m - f * s1m;
+                f = f * c1m + e * s1m;
+                e = u;
+            }
+        }
+    }
+
+    __device__ __forceinline__ void jump() {
+        const double t = cp * cjp - sp * sjp;
+        sp = sp * cjp + cp * sjp;
+        cp = t;
+        if constexpr (kEdge) {
+            const double u = cm * cjm - sm * sjm;
+            sm = sm * cjm + cm * sjm;
+            cm = u;
+        }
+    }
+};
+
 // ------------------------------------------------------------------------------------------------
 // Forward: grid (tiles_u * tiles_p, splits), 256 threads as 2 x 2 waves over a TU x TP tile.
 // LDS holds the K chunk of the two basis tiles, k-major: Xs[kb][u], Ys[kb][p].
@@ -228,9 +298,12 @@ __global__ __launch_bounds__(256, 2) void k_bwd_mat(int64_t n, BwdAxis ax) {
 #pragma unroll
         for (int b = 0; b < SJ; ++b) acc[a][b] = v4{(T)0, (T)0, (T)0, (T)0};
 
+    KRun<KA_KIND> krun{};
+    if (valid) krun.init(ca, sa, ax.La, grun * RA, KK);
     for (int k0 = 0; k0 < ax.Ka; k0 += KK) {
         __syncthreads();
-        gen_run<KA_KIND, RA>(ca, sa, ax.La, k0 + grun * RA, valid, &As[(grun * RA) * LB + gi], LB);
+        krun.template gen<RA>(k0 + grun * RA, valid, &As[(grun * RA) * LB + gi], LB);
+        krun.jump();
         for (int idx = tid; idx < KK * TN; idx += 256) {
             const int k = idx / TN, jj = idx % TN;
             const bool in = (k0 + k < ax.Ka) && (n0 + jj < ax.Nb);
