@@ -346,6 +346,18 @@ def main():
                                          f"direct summation; {tc:.1f} s",
                                "seconds": tc}
         log(f"[bench] oracle: {tc:.1f} s for {cp:.3e} pairs on {oracle.num_threads()} threads")
+        # one core, beside the paper's single-threaded setting: a smaller sample of the same work
+        threads = oracle.num_threads()
+        k1 = max(1, args.cpu_sample // 30)
+        oracle.set_num_threads(1)
+        t0 = time.perf_counter()
+        _, a1, _ = oracle.energy(wl.W, wl.H, xs[:k1], ys[:k1], wsz[:k1], hs[:k1], wl.Mu, wl.Mp)
+        oracle.grad(wl.W, wl.H, xs[:k1], ys[:k1], wsz[:k1], hs[:k1], a1)
+        t1 = time.perf_counter() - t0
+        oracle.set_num_threads(threads)
+        out["cpu_baseline"]["single_thread"] = {"value": k1 * wl.Mu * wl.Mp / t1, "unit": "pairs/s", "cores": 1,
+                                                "sample": f"the first {k1} blocks of the same sample; {t1:.1f} s"}
+        log(f"[bench] oracle on one thread: {t1:.1f} s for {k1 * wl.Mu * wl.Mp:.3e} pairs")
 
     print(json.dumps(out), flush=True)
 

@@ -64,6 +64,8 @@ def _load():
     lib.oracle_bin_coeffs_at.argtypes = [d, d, i32, _dp, i64, _ip, _ip, _dp]
     lib.oracle_bin_interp.argtypes = [d, d, i64, _dp, _dp, _dp, _dp, i32, _dp, _dp, _dp, _dp, _dp, _dp]
     lib.oracle_num_threads.argtypes = []
+    lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_num_threads.restype = None
     for f in ("oracle_coeffs", "oracle_energy", "oracle_grad", "oracle_grad_sampled",
               "oracle_coeffs_sampled", "oracle_point_field", "oracle_block_potential",
               "oracle_num_threads"):
@@ -84,6 +86,11 @@ def _check(st, what):
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(k: int) -> None:
+    """Threads of the oracle's later parallel loops (OpenMP); k <= 0 leaves the setting unchanged."""
+    _load().oracle_set_num_threads(int(k))
 
 
 def coeffs(W, H, x, y, w, h, Mu, Mp):

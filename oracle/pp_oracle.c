@@ -111,6 +111,15 @@ static double edge_integral(long k, double centre, double size, double L)
     return L / ((double)k * ORACLE_PI) * S;
 }
 
+void oracle_set_num_threads(int k)
+{
+#ifdef _OPENMP
+    if (k > 0) omp_set_num_threads(k);
+#else
+    (void)k;
+#endif
+}
+
 int oracle_num_threads(void)
 {
 #ifdef _OPENMP
