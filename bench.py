@@ -39,14 +39,19 @@ def rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b))) / (nb if nb > 0 else 1.0)
 
 
+# The sources that build the bf16 contraction kernels and their launches (the kernels whose HBM
+# traffic profiles/traffic_* records).
+TRAFFIC_SOURCES = ("api.hip", "common.h", "kernels_bf16.hip", "kernels_common.hip")
+
+
 def kernel_source_hash():
-    """sha256 of the HIP sources; traffic figures are reported only for the kernels they were taken on."""
+    """sha256 of the sources of the measured kernels; traffic figures are reported only for the
+    kernels they were taken on."""
     import hashlib
     d = os.path.join(ROOT, "paper_2307_12041_amd", "csrc")
     hs = hashlib.sha256()
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h")):
-            hs.update(open(os.path.join(d, f), "rb").read())
+    for f in TRAFFIC_SOURCES:
+        hs.update(open(os.path.join(d, f), "rb").read())
     return hs.hexdigest()
 
 

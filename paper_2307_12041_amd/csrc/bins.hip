@@ -225,30 +225,33 @@ __device__ __forceinline__ double disa_factor(int u, int p, double W, double H, 
            sinpi(u / (2.0 * m)) * sinpi(p / (2.0 * m));
 }
 
-constexpr int GT = 64, GK = 16, GPAD = GT + 1;
+// 128 x 128 output tile per workgroup of 8 waves (2 x 4 sub-tiles of 64 x 32, eight 16 x 16
+// accumulators each); K chunks of 32 in LDS ([k][i] and [k][j], rows padded by one double).  The
+// operands of chunk c + 1 are fetched into registers while the MFMAs of chunk c run, then stored
+// between two barriers.
+constexpr int GT = 128, GK = 32, GPAD = GT + 1, GTHREADS = 512;
 
 template <bool DISA>
-__global__ __launch_bounds__(256) void k_bin_gemm(int M, int N, int K, BinOp A, BinOp B, const double *__restrict__ tab,
-                                                  int m4, double *__restrict__ C, int ldc, double W, double H, int m) {
-    __shared__ double As[2][GK * GPAD];   // [buffer][k][i]
-    __shared__ double Bs[2][GK * GPAD];   // [buffer][k][j]
+__global__ __launch_bounds__(GTHREADS) void k_bin_gemm(int M, int N, int K, BinOp A, BinOp B,
+                                                       const double *__restrict__ tab, int m4,
+                                                       double *__restrict__ C, int ldc, double W, double H, int m) {
+    __shared__ double As[GK * GPAD];   // [k][i]
+    __shared__ double Bs[GK * GPAD];   // [k][j]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r0 = blockIdx.y * GT, c0 = blockIdx.x * GT;
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-    f64x4 acc[2][2];
+    const int wr = (wave >> 2) * 64, wc = (wave & 3) * 32;
+    f64x4 acc[4][2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-    // K chunks are double-buffered: the operands of chunk c + 1 are fetched into registers while
-    // the MFMAs of chunk c run, then stored to the other LDS buffer; one barrier per chunk.
-    constexpr int PER = GT * GK / 256;
+    constexpr int PER = GT * GK / GTHREADS;
     double na[PER], nb[PER];
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const int e = tid + 256 * q;
+            const int e = tid + GTHREADS * q;
             const int ia = e / GK, ka = e % GK;      // A element (r0 + ia, k0 + ka)
             const int kb = e / GT, jb = e % GT;      // B element (k0 + kb, c0 + jb)
             const int ra = r0 + ia, ca = k0 + ka, rb = k0 + kb, cb = c0 + jb;
@@ -256,40 +259,43 @@ __global__ __launch_bounds__(256) void k_bin_gemm(int M, int N, int K, BinOp A, 
             nb[q] = (rb < K && cb < N) ? binop_at(B, tab, m4, rb, cb) : 0.0;
         }
     };
-    auto stash = [&](int buf) {
+    auto stash = [&]() {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const int e = tid + 256 * q;
-            As[buf][(e % GK) * GPAD + e / GK] = na[q];
-            Bs[buf][(e / GT) * GPAD + e % GT] = nb[q];
+            const int e = tid + GTHREADS * q;
+            As[(e % GK) * GPAD + e / GK] = na[q];
+            Bs[(e / GT) * GPAD + e % GT] = nb[q];
         }
     };
     fetch(0);
-    stash(0);
+    stash();
     __syncthreads();
-    for (int k0 = 0, buf = 0; k0 < K; k0 += GK, buf ^= 1) {
+    for (int k0 = 0; k0 < K; k0 += GK) {
         const bool more = k0 + GK < K;
         if (more) fetch(k0 + GK);
 #pragma unroll
         for (int ks = 0; ks < GK / 4; ++ks) {
             const int kr = 4 * ks + (lane >> 4);
-            double av[2], bv[2];
+            double av[4], bv[2];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) av[a] = As[buf][kr * GPAD + wr + 16 * a + (lane & 15)];
+            for (int a = 0; a < 4; ++a) av[a] = As[kr * GPAD + wr + 16 * a + (lane & 15)];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) bv[b] = Bs[buf][kr * GPAD + wc + 16 * b + (lane & 15)];
+            for (int b = 0; b < 2; ++b) bv[b] = Bs[kr * GPAD + wc + 16 * b + (lane & 15)];
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < 4; ++a)
 #pragma unroll
                 for (int b = 0; b < 2; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
         }
-        if (more) stash(buf ^ 1);
+        if (more) {
+            __syncthreads();
+            stash();
+        }
         __syncthreads();
     }
     // D layout of v_mfma_f64_16x16x4f64: row 4 r + lane / 16, column lane % 16.
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -309,9 +315,9 @@ hipError_t gemm(int M, int N, int K, const BinOp &A, const BinOp &B, const doubl
     if (M <= 0 || N <= 0) return hipSuccess;
     dim3 grid((unsigned)((N + GT - 1) / GT), (unsigned)((M + GT - 1) / GT));
     if (disa)
-        hipLaunchKernelGGL(k_bin_gemm<true>, grid, dim3(256), 0, s, M, N, K, A, B, tab, 4 * m, C, ldc, W, H, m);
+        hipLaunchKernelGGL(k_bin_gemm<true>, grid, dim3(GTHREADS), 0, s, M, N, K, A, B, tab, 4 * m, C, ldc, W, H, m);
     else
-        hipLaunchKernelGGL(k_bin_gemm<false>, grid, dim3(256), 0, s, M, N, K, A, B, tab, 4 * m, C, ldc, W, H, m);
+        hipLaunchKernelGGL(k_bin_gemm<false>, grid, dim3(GTHREADS), 0, s, M, N, K, A, B, tab, 4 * m, C, ldc, W, H, m);
     return hipGetLastError();
 }
 
