@@ -193,9 +193,8 @@ __global__ void k_bin_trig(int m, double *__restrict__ tab) {
 }
 
 // ------------------------------------------------------------------------------------------------
-// GEMM C[M x N] = A[M x K] B[K x N] on v_mfma_f64_16x16x4f64, with either operand a dense
-// row-major matrix or a trigonometric view.  64 x 64 output tile per workgroup (4 waves of
-// 32 x 32), K chunks of 16 staged in LDS.
+// GEMM C[M x N] = A[M x K] B[K x N] on v_mfma_f64_16x16x4f64, one operand a dense row-major
+// matrix and the other a trigonometric view read from the table.
 // ------------------------------------------------------------------------------------------------
 struct BinOp {
     const double *ptr;   // dense: element (r, c) at ptr[r * ld + c]
@@ -205,14 +204,22 @@ struct BinOp {
     double wscale;       // trig: value times f * wscale, unless 0
 };
 
-__device__ __forceinline__ double binop_at(const BinOp &o, const double *__restrict__ tab, int m4, int r, int c) {
-    if (o.trig == 0) return o.ptr[(size_t)r * o.ld + c];
-    const int f = o.freq_is_row ? r : c, s = o.freq_is_row ? c : r;
-    // f < m and 2s + 1 < 2m, so the product is below 2 m^2 <= 2^29: exact in 32-bit unsigned
-    const int q = (int)(((unsigned)f * (unsigned)(2 * s + 1)) % (unsigned)m4);
-    double v = tab[(o.trig - 1) * m4 + q];
-    if (o.wscale != 0.0) v *= (double)f * o.wscale;
-    return v;
+// The load of element (r, c) of an operand whose kind (dense or trigonometric) is known at compile
+// time, split so that nothing waits for it before it is stored: v receives the raw load (from a
+// valid address even outside the matrix), sc the factor it is to be multiplied by.
+template <bool TRIG>
+__device__ __forceinline__ void binop_issue(const BinOp &o, const double *__restrict__ tab, int m4, int r, int c,
+                                            bool valid, double &v, double &sc) {
+    if constexpr (!TRIG) {
+        v = o.ptr[valid ? (size_t)r * o.ld + c : 0];
+        sc = 1.0;
+    } else {
+        const int f = o.freq_is_row ? r : c, s = o.freq_is_row ? c : r;
+        // f < m and 2s + 1 < 2m, so the product is below 2 m^2 <= 2^29: exact in 32-bit unsigned
+        const unsigned q = valid ? ((unsigned)f * (unsigned)(2 * s + 1)) % (unsigned)m4 : 0u;
+        v = tab[(o.trig - 1) * m4 + (int)q];
+        sc = o.wscale != 0.0 ? (double)f * o.wscale : 1.0;
+    }
 }
 
 // Epilogue factor of the binned coefficients (eqs. disa-a..d) for row u, column p.
@@ -226,17 +233,19 @@ __device__ __forceinline__ double disa_factor(int u, int p, double W, double H, 
 }
 
 // 128 x 128 output tile per workgroup of 8 waves (2 x 4 sub-tiles of 64 x 32, eight 16 x 16
-// accumulators each); K chunks of 32 in LDS ([k][i] and [k][j], rows padded by one double).  The
-// operands of chunk c + 1 are fetched into registers while the MFMAs of chunk c run, then stored
-// between two barriers.
-constexpr int GT = 128, GK = 32, GPAD = GT + 1, GTHREADS = 512;
+// accumulators each); K chunks of 32 in LDS, A as [i][k] with rows of KP = 34 doubles and B as
+// [k][j] with rows of JP = 144 doubles.  With 64 banks of 4 bytes, the MFMA operand reads (16
+// lanes along i or j, the next 16 lanes one k further) and the stores (consecutive threads along
+// k for A, along j for B) are then free of bank conflicts.  The operands of chunk c + 1 are
+// fetched into registers while the MFMAs of chunk c run, then stored between two barriers.
+constexpr int GT = 128, GK = 32, KP = GK + 2, JP = GT + 16, GTHREADS = 512;
 
-template <bool DISA>
+template <bool DISA, bool ATRIG>
 __global__ __launch_bounds__(GTHREADS) void k_bin_gemm(int M, int N, int K, BinOp A, BinOp B,
                                                        const double *__restrict__ tab, int m4,
                                                        double *__restrict__ C, int ldc, double W, double H, int m) {
-    __shared__ double As[GK * GPAD];   // [k][i]
-    __shared__ double Bs[GK * GPAD];   // [k][j]
+    __shared__ double As[GT * KP];   // [i][k]
+    __shared__ double Bs[GK * JP];   // [k][j]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r0 = blockIdx.y * GT, c0 = blockIdx.x * GT;
     const int wr = (wave >> 2) * 64, wc = (wave & 3) * 32;
@@ -246,8 +255,10 @@ __global__ __launch_bounds__(GTHREADS) void k_bin_gemm(int M, int N, int K, BinO
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
 
+    // One operand is trigonometric (ATRIG: A, else B), the other dense.
     constexpr int PER = GT * GK / GTHREADS;
-    double na[PER], nb[PER];
+    double na[PER], nb[PER], sa[PER], sb[PER];
+    bool oka[PER], okb[PER];
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
@@ -255,16 +266,18 @@ __global__ __launch_bounds__(GTHREADS) void k_bin_gemm(int M, int N, int K, BinO
             const int ia = e / GK, ka = e % GK;      // A element (r0 + ia, k0 + ka)
             const int kb = e / GT, jb = e % GT;      // B element (k0 + kb, c0 + jb)
             const int ra = r0 + ia, ca = k0 + ka, rb = k0 + kb, cb = c0 + jb;
-            na[q] = (ra < M && ca < K) ? binop_at(A, tab, m4, ra, ca) : 0.0;
-            nb[q] = (rb < K && cb < N) ? binop_at(B, tab, m4, rb, cb) : 0.0;
+            oka[q] = ra < M && ca < K;
+            okb[q] = rb < K && cb < N;
+            binop_issue<ATRIG>(A, tab, m4, ra, ca, oka[q], na[q], sa[q]);
+            binop_issue<!ATRIG>(B, tab, m4, rb, cb, okb[q], nb[q], sb[q]);
         }
     };
     auto stash = [&]() {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int e = tid + GTHREADS * q;
-            As[(e % GK) * GPAD + e / GK] = na[q];
-            Bs[(e / GT) * GPAD + e % GT] = nb[q];
+            As[(e / GK) * KP + e % GK] = oka[q] ? na[q] * sa[q] : 0.0;
+            Bs[(e / GT) * JP + e % GT] = okb[q] ? nb[q] * sb[q] : 0.0;
         }
     };
     fetch(0);
@@ -278,9 +291,9 @@ __global__ __launch_bounds__(GTHREADS) void k_bin_gemm(int M, int N, int K, BinO
             const int kr = 4 * ks + (lane >> 4);
             double av[4], bv[2];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) av[a] = As[kr * GPAD + wr + 16 * a + (lane & 15)];
+            for (int a = 0; a < 4; ++a) av[a] = As[(wr + 16 * a + (lane & 15)) * KP + kr];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) bv[b] = Bs[kr * GPAD + wc + 16 * b + (lane & 15)];
+            for (int b = 0; b < 2; ++b) bv[b] = Bs[kr * JP + wc + 16 * b + (lane & 15)];
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -314,10 +327,20 @@ hipError_t gemm(int M, int N, int K, const BinOp &A, const BinOp &B, const doubl
                 bool disa, double W, double H, hipStream_t s) {
     if (M <= 0 || N <= 0) return hipSuccess;
     dim3 grid((unsigned)((N + GT - 1) / GT), (unsigned)((M + GT - 1) / GT));
-    if (disa)
-        hipLaunchKernelGGL(k_bin_gemm<true>, grid, dim3(GTHREADS), 0, s, M, N, K, A, B, tab, 4 * m, C, ldc, W, H, m);
+    // every transform has exactly one trigonometric operand
+    if ((A.trig != 0) == (B.trig != 0)) return hipErrorInvalidValue;
+    if (disa && A.trig)
+        hipLaunchKernelGGL((k_bin_gemm<true, true>), grid, dim3(GTHREADS), 0, s, M, N, K, A, B, tab, 4 * m, C, ldc, W,
+                           H, m);
+    else if (disa)
+        hipLaunchKernelGGL((k_bin_gemm<true, false>), grid, dim3(GTHREADS), 0, s, M, N, K, A, B, tab, 4 * m, C, ldc,
+                           W, H, m);
+    else if (A.trig)
+        hipLaunchKernelGGL((k_bin_gemm<false, true>), grid, dim3(GTHREADS), 0, s, M, N, K, A, B, tab, 4 * m, C, ldc,
+                           W, H, m);
     else
-        hipLaunchKernelGGL(k_bin_gemm<false>, grid, dim3(GTHREADS), 0, s, M, N, K, A, B, tab, 4 * m, C, ldc, W, H, m);
+        hipLaunchKernelGGL((k_bin_gemm<false, false>), grid, dim3(GTHREADS), 0, s, M, N, K, A, B, tab, 4 * m, C, ldc,
+                           W, H, m);
     return hipGetLastError();
 }
 
