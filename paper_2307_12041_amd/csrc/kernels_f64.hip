@@ -300,14 +300,25 @@ __global__ __launch_bounds__(256, 2) void k_bwd_mat(int64_t n, BwdAxis ax) {
 
     KRun<KA_KIND> krun{};
     if (valid) krun.init(ca, sa, ax.La, grun * RA, KK);
+    constexpr int PB = KK * TN / 256;
     for (int k0 = 0; k0 < ax.Ka; k0 += KK) {
+        // The operand chunk is loaded first (unconditionally, from a valid address; the bounds are
+        // applied when it is stored), so that its latency overlaps the basis generation.
+        T bv[PB];
+#pragma unroll
+        for (int q = 0; q < PB; ++q) {
+            const int idx = tid + 256 * q, k = idx / TN, jj = idx % TN;
+            const bool in = (k0 + k < ax.Ka) && (n0 + jj < ax.Nb);
+            bv[q] = B[in ? (size_t)(k0 + k) * ax.Nb + n0 + jj : 0];
+        }
         __syncthreads();
         krun.template gen<RA>(k0 + grun * RA, valid, &As[(grun * RA) * LB + gi], LB);
         krun.jump();
-        for (int idx = tid; idx < KK * TN; idx += 256) {
-            const int k = idx / TN, jj = idx % TN;
+#pragma unroll
+        for (int q = 0; q < PB; ++q) {
+            const int idx = tid + 256 * q, k = idx / TN, jj = idx % TN;
             const bool in = (k0 + k < ax.Ka) && (n0 + jj < ax.Nb);
-            Bs[k * LN + jj] = in ? B[(size_t)(k0 + k) * ax.Nb + n0 + jj] : (T)0;
+            Bs[k * LN + jj] = in ? bv[q] : (T)0;
         }
         __syncthreads();
 #pragma unroll
