@@ -182,6 +182,39 @@ struct KRun {
     }
 };
 
+// R consecutive sine-difference integrals S_k = sin(w_k x+) - sin(w_k x-) of one block (S_0 = its
+// size), k = k0 .. k0 + R - 1, in the product form 2 cos(k a) sin(k b), a = pi c / L,
+// b = pi size / (2L), each factor by its three-term recurrence f_{k+1} = 2 cos(t) f_k - f_{k-1}
+// from FP64 seeds at k0 and k0 - 1: two FMAs and one product per value (two phasor rotations cost
+// eight), with no cancellation for narrow blocks.  Written at dst[k * stride], rounded to T.
+template <int R, typename T>
+__device__ __forceinline__ void gen_sindiff(double c, double sz, double L, int k0, bool valid, T *dst, int stride) {
+    if (!valid) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) dst[k * stride] = (T)0;
+        return;
+    }
+    const double ta = c / L, tb = 0.5 * sz / L;
+    double sa, ca, s1a, c1a, sb, cb, s1b, c1b;
+    sincospi(reduce_half_turns((double)k0 * ta), &sa, &ca);
+    sincospi(reduce_half_turns(ta), &s1a, &c1a);
+    sincospi(reduce_half_turns((double)k0 * tb), &sb, &cb);
+    sincospi(reduce_half_turns(tb), &s1b, &c1b);
+    double C = ca, Cm = ca * c1a + sa * s1a;                  // cos(k0 a), cos((k0 - 1) a)
+    double S = 2.0 * sb, Sm = 2.0 * (sb * c1b - cb * s1b);    // 2 sin(k0 b), 2 sin((k0 - 1) b)
+    const double ta2 = 2.0 * c1a, tb2 = 2.0 * c1b;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        dst[k * stride] = (T)((k0 + k == 0) ? sz : C * S);
+        const double Cn = fma(ta2, C, -Cm);
+        Cm = C;
+        C = Cn;
+        const double Sn = fma(tb2, S, -Sm);
+        Sm = S;
+        S = Sn;
+    }
+}
+
 // ------------------------------------------------------------------------------------------------
 // Forward: grid (tiles_u * tiles_p, splits), 256 threads as 2 x 2 waves over a TU x TP tile.
 // LDS holds the K chunk of the two basis tiles, k-major: Xs[kb][u], Ys[kb][p].
@@ -220,10 +253,10 @@ __global__ __launch_bounds__(256) void k_fwd_mat(int64_t n, int Mu, int Mp, doub
         __syncthreads();
         if (side == 0) {
             const double cx = valid ? x[ib] : 0.0, sx = valid ? w[ib] : 0.0;
-            gen_run<RUN_SINDIFF, RX>(cx, sx, W, tu0 + run * RX, valid, &Xs[kb * LU + run * RX], 1);
+            gen_sindiff<RX>(cx, sx, W, tu0 + run * RX, valid, &Xs[kb * LU + run * RX], 1);
         } else {
             const double cy = valid ? y[ib] : 0.0, sy = valid ? h[ib] : 0.0;
-            gen_run<RUN_SINDIFF, RY>(cy, sy, H, tp0 + run * RY, valid, &Ys[kb * LP + run * RY], 1);
+            gen_sindiff<RY>(cy, sy, H, tp0 + run * RY, valid, &Ys[kb * LP + run * RY], 1);
         }
         __syncthreads();
 #pragma unroll
