@@ -113,30 +113,33 @@ __device__ __forceinline__ void gen_run(double c, double sz, double L, int k0, b
 }
 
 // A run of R consecutive frequencies of one block that moves on by J frequencies every K chunk (the
-// row-form contraction, where a thread keeps its block for the whole K loop): the seed phasors at
-// the run's first frequency, the one-frequency step and the J-frequency jump come from FP64
-// sincospi of exactly reduced arguments once; after each chunk the seeds are rotated by the jump
-// instead of being evaluated again (one complex product per edge against two sincospi).
+// row-form contraction, where a thread keeps its block for the whole K loop), for the K-side kinds
+// RUN_SINDIFF (the product form 2 cos(k a) sin(k b), a = pi c / L, b = pi size / (2L)) and RUN_COS
+// (cos(k a), a = pi c / L).  The phasors e^{i k0 a} (and e^{i k0 b}) at the run's first frequency,
+// the one-frequency step and the J-frequency jump come from FP64 sincospi of exactly reduced
+// arguments once; each run is then produced by the three-term recurrence f_{k+1} = 2 cos(t) f_k -
+// f_{k-1} of each factor, and after each chunk the seed phasors are rotated by the jump instead of
+// being evaluated again.
 template <int KIND>
 struct KRun {
-    static constexpr bool kEdge = KIND == RUN_SINDIFF || KIND == RUN_COSDIFF;
-    double cp, sp, cm, sm;        // seeds (point kinds use cp, sp)
-    double c1p, s1p, c1m, s1m;    // one-frequency step
-    double cjp, sjp, cjm, sjm;    // J-frequency jump
-    double sz, pil;
+    static_assert(KIND == RUN_SINDIFF || KIND == RUN_COS, "K-side kinds of the row-form contraction");
+    static constexpr bool kProd = KIND == RUN_SINDIFF;
+    double ca, sa, cb, sb;        // seed phasors at the run's first frequency (b: RUN_SINDIFF only)
+    double c1a, s1a, c1b, s1b;    // one-frequency step
+    double cja, sja, cjb, sjb;    // J-frequency jump
+    double sz;
 
     __device__ __forceinline__ void init(double c, double size, double L, int k0, int J) {
         sz = size;
-        pil = kPi / L;
-        const double tp = kEdge ? (c + 0.5 * size) / L : c / L;
-        sincospi(reduce_half_turns((double)k0 * tp), &sp, &cp);
-        sincospi(reduce_half_turns(tp), &s1p, &c1p);
-        sincospi(reduce_half_turns((double)J * tp), &sjp, &cjp);
-        if constexpr (kEdge) {
-            const double tm = (c - 0.5 * size) / L;
-            sincospi(reduce_half_turns((double)k0 * tm), &sm, &cm);
-            sincospi(reduce_half_turns(tm), &s1m, &c1m);
-            sincospi(reduce_half_turns((double)J * tm), &sjm, &cjm);
+        const double ta = c / L;
+        sincospi(reduce_half_turns((double)k0 * ta), &sa, &ca);
+        sincospi(reduce_half_turns(ta), &s1a, &c1a);
+        sincospi(reduce_half_turns((double)J * ta), &sja, &cja);
+        if constexpr (kProd) {
+            const double tb = 0.5 * size / L;
+            sincospi(reduce_half_turns((double)k0 * tb), &sb, &cb);
+            sincospi(reduce_half_turns(tb), &s1b, &c1b);
+            sincospi(reduce_half_turns((double)J * tb), &sjb, &cjb);
         }
     }
 
@@ -148,36 +151,39 @@ struct KRun {
             for (int k = 0; k < R; ++k) dst[k * stride] = (T)0;
             return;
         }
-        double a = cp, b = sp, e = cm, f = sm;
+        double C = ca, Cm = ca * c1a + sa * s1a;                  // cos(k0 a), cos((k0 - 1) a)
+        const double ta2 = 2.0 * c1a;
+        double S = 0.0, Sm = 0.0, tb2 = 0.0;
+        if constexpr (kProd) {
+            S = 2.0 * sb;                                         // 2 sin(k0 b), 2 sin((k0 - 1) b)
+            Sm = 2.0 * (sb * c1b - cb * s1b);
+            tb2 = 2.0 * c1b;
+        }
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            if constexpr (KIND == RUN_SINDIFF)
-                dst[k * stride] = (T)((k0 + k == 0) ? sz : (b - f));
-            else if constexpr (KIND == RUN_COSDIFF)
-                dst[k * stride] = (T)(a - e);
-            else if constexpr (KIND == RUN_COS)
-                dst[k * stride] = (T)a;
+            if constexpr (kProd)
+                dst[k * stride] = (T)((k0 + k == 0) ? sz : C * S);
             else
-                dst[k * stride] = (T)((double)(k0 + k) * pil * b);
-            const double t = a * c1p - b * s1p;
-            b = b * c1p + a * s1p;
-            a = t;
-            if constexpr (kEdge) {
-                const double u = e * c1m - f * s1m;
-                f = f * c1m + e * s1m;
-                e = u;
+                dst[k * stride] = (T)C;
+            const double Cn = fma(ta2, C, -Cm);
+            Cm = C;
+            C = Cn;
+            if constexpr (kProd) {
+                const double Sn = fma(tb2, S, -Sm);
+                Sm = S;
+                S = Sn;
             }
         }
     }
 
     __device__ __forceinline__ void jump() {
-        const double t = cp * cjp - sp * sjp;
-        sp = sp * cjp + cp * sjp;
-        cp = t;
-        if constexpr (kEdge) {
-            const double u = cm * cjm - sm * sjm;
-            sm = sm * cjm + cm * sjm;
-            cm = u;
+        const double t = ca * cja - sa * sja;
+        sa = sa * cja + ca * sja;
+        ca = t;
+        if constexpr (kProd) {
+            const double u = cb * cjb - sb * sjb;
+            sb = sb * cjb + cb * sjb;
+            cb = u;
         }
     }
 };
