@@ -87,7 +87,7 @@ typedef enum pp_basis_mode {
 /* Problem description (Sec. II-A: region and blocks; truncation of the series, Sec. III-B/C). */
 typedef struct pp_problem {
     double W, H;         /* region [0, W] x [0, H]; finite, > 0 */
-    int64_t n;           /* number of blocks, >= 0 */
+    int64_t n;           /* number of blocks, 0 <= n <= 2^40 */
     int32_t Mu, Mp;      /* frequencies u in [0, Mu), p in [0, Mp); 1 <= Mu, Mp <= 65536 */
     int32_t precision;   /* pp_precision */
     int32_t basis_mode;  /* pp_basis_mode */

@@ -10,6 +10,8 @@
 // Each is one FP64 MFMA GEMM whose trigonometric operand is read from a table of cos and sin of
 // k pi / (2m), k in [0, 4m), indexed by f (2s+1) mod 4m (exact integer reduction, so every entry
 // carries only the table's one rounding).
+#include <math.h>
+
 #include "common.h"
 #include "pplace.h"
 
@@ -365,7 +367,7 @@ BinLayout bin_layout(const pp_bin_problem &B) {
     return L;
 }
 
-bool finite_pos(double v) { return v > 0.0 && v < 1e300; }
+bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 bool al8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
 
 int check_bin_problem(const pp_bin_problem *B) {

@@ -216,3 +216,48 @@ def test_bin_entry_points_validate_before_launch(lib):
     assert bi(ctypes.byref(BP(n=0)), nul, nul, nul, nul, fake, nul, nul, nul, nul, nul, nul, 0, nul) == 0
     assert bi(ctypes.byref(BP(n=0, m=0)), nul, nul, nul, nul, fake, nul, nul, nul, nul, nul, nul, 0, nul) == -1
     assert bi(ctypes.byref(prob), *blocks, nul, nul, nul, nul, nul, nul, fake, need, nul) == 0
+
+
+# ---------------------------------------------------------------------------------------------
+# Property: the host-side validation accepts exactly the problems the header documents.
+# ---------------------------------------------------------------------------------------------
+from hypothesis import given, settings, strategies as st  # noqa: E402
+
+_FLOATS = st.one_of(st.floats(allow_nan=True, allow_infinity=True),
+                    st.sampled_from([0.0, -0.0, -1.0, 5e-324, 1e-300, 1e300, 16384.0]))
+
+
+def _documented_status(W, H, n, Mu, Mp, prec, basis):
+    ok = lambda v: math.isfinite(v) and v > 0.0
+    if (not ok(W) or not ok(H) or n < 0 or n > 2 ** 40 or not 1 <= Mu <= 65536 or not 1 <= Mp <= 65536
+            or not 0 <= prec <= 5 or basis not in (0, 1)):
+        return -1
+    if prec in (4, 5) or (basis == 1 and prec not in (2, 3)):
+        return -3
+    return 0
+
+
+@settings(max_examples=300, deadline=None)
+@given(W=_FLOATS, H=_FLOATS, n=st.integers(-5, 2 ** 41), Mu=st.integers(-3, 70000), Mp=st.integers(-3, 70000),
+       prec=st.integers(-2, 7), basis=st.integers(-1, 2))
+def test_workspace_size_accepts_exactly_the_documented_problems(lib, W, H, n, Mu, Mp, prec, basis):
+    st_, v = ws_size(lib, P(W=W, H=H, n=n, Mu=Mu, Mp=Mp, precision=prec, basis_mode=basis))
+    assert st_ == _documented_status(W, H, n, Mu, Mp, prec, basis)
+    if st_ == 0:
+        assert v > 0 and v % 256 == 0
+    else:
+        assert v == 12345
+
+
+@settings(max_examples=300, deadline=None)
+@given(W=_FLOATS, H=_FLOATS, n=st.integers(-5, 2 ** 32), m=st.integers(-3, 20000), Mu=st.integers(-3, 20000),
+       Mp=st.integers(-3, 20000))
+def test_bin_workspace_size_accepts_exactly_the_documented_problems(lib, W, H, n, m, Mu, Mp):
+    st_, v = bin_ws(lib, BP(W=W, H=H, n=n, m=m, Mu=Mu, Mp=Mp))
+    ok = lambda x: math.isfinite(x) and x > 0.0
+    valid = ok(W) and ok(H) and 0 <= n < 2 ** 31 and 1 <= m <= 16384 and 1 <= Mu <= m and 1 <= Mp <= m
+    assert st_ == (0 if valid else -1)
+    if valid:
+        assert v > 0 and v % 256 == 0
+    else:
+        assert v == 12345
