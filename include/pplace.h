@@ -52,7 +52,8 @@ extern "C" {
 
 typedef enum pp_status {
     PP_OK = 0,
-    PP_ERR_ARG = -1,          /* NULL pointer, bad size, non-finite or non-positive W/H, misalignment */
+    PP_ERR_ARG = -1,          /* NULL pointer, bad or too large size, non-finite or non-positive W/H,
+                                 misalignment */
     PP_ERR_WORKSPACE = -2,    /* ws_bytes smaller than pp_workspace_size() */
     PP_ERR_UNSUPPORTED = -3,  /* precision / basis mode not implemented by the library */
     PP_ERR_DEVICE = -4        /* a HIP launch or runtime call failed */
@@ -84,11 +85,16 @@ typedef enum pp_basis_mode {
     PP_BASIS_STORE = 1
 } pp_basis_mode;
 
-/* Problem description (Sec. II-A: region and blocks; truncation of the series, Sec. III-B/C). */
+/* Problem description (Sec. II-A: region and blocks; truncation of the series, Sec. III-B/C).
+ * The limits keep every launch grid of the library below 2^32 work-items per dimension; a problem
+ * beyond them is rejected with PP_ERR_ARG before anything is enqueued:
+ *   0 <= n <= 2^31 - 512;  1 <= Mu, Mp <= 65536 and Mu * Mp <= 2^30;
+ *   PP_BASIS_STORE also needs ceil(n / 256) * ceil(max(Mu, Mp) / 256) < 2^21 (the table build).
+ * (Memory is the caller's: pp_workspace_size() may ask for more than a device holds.) */
 typedef struct pp_problem {
     double W, H;         /* region [0, W] x [0, H]; finite, > 0 */
-    int64_t n;           /* number of blocks, 0 <= n <= 2^40 */
-    int32_t Mu, Mp;      /* frequencies u in [0, Mu), p in [0, Mp); 1 <= Mu, Mp <= 65536 */
+    int64_t n;           /* number of blocks */
+    int32_t Mu, Mp;      /* frequencies u in [0, Mu), p in [0, Mp) */
     int32_t precision;   /* pp_precision */
     int32_t basis_mode;  /* pp_basis_mode */
 } pp_problem;

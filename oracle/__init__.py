@@ -55,6 +55,9 @@ def _load():
     lib.oracle_grad.argtypes = [d, d, i64, _dp, _dp, _dp, _dp, i32, i32, _dp, _dp, _dp]
     lib.oracle_grad_sampled.argtypes = [d, d, _dp, _dp, _dp, _dp, i32, i32, _dp, i64, _lp, _dp, _dp]
     lib.oracle_coeffs_sampled.argtypes = [d, d, i64, _dp, _dp, _dp, _dp, i32, _ip, _ip, _dp, _dp]
+    lib.oracle_coeffs_sampled_full.argtypes = [d, d, i64, _dp, _dp, _dp, _dp, i32, _ip, _ip, _dp, _dp, _dp, _dp]
+    lib.oracle_raw_moments.argtypes = [d, d, i64, _dp, _dp, _dp, _dp, i32, i32, _dp]
+    lib.oracle_coef_factors.argtypes = [d, d, i32, i32, _dp]
     lib.oracle_point_field.argtypes = [d, d, i32, i32, _dp, i64, _dp, _dp, _dp, _dp, _dp]
     lib.oracle_block_potential.argtypes = [d, d, i64, _dp, _dp, _dp, _dp, i32, i32, _dp, _dp]
     lib.oracle_bin_density.argtypes = [d, d, i64, _dp, _dp, _dp, _dp, i32, _dp]
@@ -67,7 +70,8 @@ def _load():
     lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
     lib.oracle_set_num_threads.restype = None
     for f in ("oracle_coeffs", "oracle_energy", "oracle_grad", "oracle_grad_sampled",
-              "oracle_coeffs_sampled", "oracle_point_field", "oracle_block_potential",
+              "oracle_coeffs_sampled", "oracle_coeffs_sampled_full", "oracle_raw_moments",
+              "oracle_coef_factors", "oracle_point_field", "oracle_block_potential", "oracle_bin_field",
               "oracle_num_threads"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
@@ -163,6 +167,40 @@ def coeffs_sampled(W, H, x, y, w, h, us, ps):
                                      ps.ctypes.data_as(_ip), a.ctypes.data_as(_dp),
                                      I.ctypes.data_as(_dp)), "coeffs_sampled")
     return a, I
+
+
+def raw_moments(W, H, x, y, w, h, Mu, Mp):
+    """Raw block sums R[u, p] = sum_i S'_iu T'_ip (S'_i0 = w_i, T'_i0 = h_i): the moments with
+    their frequency factors taken out, of the same magnitude over the whole (u, p) plane."""
+    lib = _load()
+    xs = [_f64(v) for v in (x, y, w, h)]
+    n = xs[0][0].shape[0]
+    R = np.zeros((Mu, Mp))
+    _check(lib.oracle_raw_moments(W, H, n, *[p for _, p in xs], Mu, Mp, R.ctypes.data_as(_dp)), "raw_moments")
+    return R
+
+
+def coef_factors(W, H, Mu, Mp):
+    """Prefactors f[u, p] of the closed-form coefficients, a_up = f_up R_up (f_00 = 0)."""
+    f = np.zeros((Mu, Mp))
+    _check(_load().oracle_coef_factors(W, H, Mu, Mp, f.ctypes.data_as(_dp)), "coef_factors")
+    return f
+
+
+def coeffs_sampled_full(W, H, x, y, w, h, us, ps):
+    """(a, R, Rabs) at the sampled (us[k], ps[k]): the coefficient, the raw sum R = sum_i S'_iu T'_ip
+    and its absolute counterpart Rabs = sum_i |S'_iu T'_ip| (the scale of the sum's rounding errors)."""
+    lib = _load()
+    xs = [_f64(v) for v in (x, y, w, h)]
+    n = xs[0][0].shape[0]
+    us = np.ascontiguousarray(np.asarray(us, dtype=np.int32))
+    ps = np.ascontiguousarray(np.asarray(ps, dtype=np.int32))
+    k = us.shape[0]
+    a, R, Ra = np.zeros(k), np.zeros(k), np.zeros(k)
+    _check(lib.oracle_coeffs_sampled_full(W, H, n, *[p for _, p in xs], k, us.ctypes.data_as(_ip),
+                                          ps.ctypes.data_as(_ip), a.ctypes.data_as(_dp), None,
+                                          R.ctypes.data_as(_dp), Ra.ctypes.data_as(_dp)), "coeffs_sampled_full")
+    return a, R, Ra
 
 
 def point_field(W, H, a, px, py):

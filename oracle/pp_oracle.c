@@ -210,6 +210,33 @@ int oracle_coeffs(double W, double H, int64_t n, const double *x, const double *
     return 0;
 }
 
+/*
+ * The raw block sums R[u*Mp+p] = sum_i S'_iu T'_ip themselves (S'_i0 = w_i, T'_i0 = h_i).  They are
+ * the cosine moments with the frequency factors taken out (R_up = I_up u p pi^2 / (W H) for
+ * u, p >= 1, and likewise for the axis rows), so their magnitude does not fall with (u, p): every
+ * part of the (u, p) plane weighs alike in a comparison.  R_00 = sum w h (no mean subtraction here).
+ */
+int oracle_raw_moments(double W, double H, int64_t n, const double *x, const double *y,
+                       const double *w, const double *h, int Mu, int Mp, double *Rout)
+{
+    if (!(W > 0) || !(H > 0) || Mu < 1 || Mp < 1 || n < 0 || !Rout) return -2;
+    long double *R = (long double *)malloc(sizeof(long double) * (size_t)Mu * (size_t)Mp);
+    if (!R) return -1;
+    if (raw_sums(W, H, n, x, y, w, h, Mu, Mp, R)) { free(R); return -1; }
+    for (size_t k = 0; k < (size_t)Mu * (size_t)Mp; ++k) Rout[k] = (double)R[k];
+    free(R);
+    return 0;
+}
+
+/* The prefactors f[u*Mp+p] of the three closed forms, a_up = f_up R_up (f_00 = 0). */
+int oracle_coef_factors(double W, double H, int Mu, int Mp, double *f)
+{
+    if (!(W > 0) || !(H > 0) || Mu < 1 || Mp < 1 || !f) return -2;
+    for (int u = 0; u < Mu; ++u)
+        for (int p = 0; p < Mp; ++p) f[(size_t)u * Mp + p] = coef_factor(u, p, W, H);
+    return 0;
+}
+
 /* E = 1/2 sum_up a_up I_up. */
 double oracle_energy_from(const double *a, const double *I, int Mu, int Mp)
 {
@@ -313,37 +340,56 @@ int oracle_grad_sampled(double W, double H, const double *x, const double *y, co
  * (used to check the largest workloads, whose full coefficient set is too costly here).
  * Also returns the moments I (may be NULL).
  */
-int oracle_coeffs_sampled(double W, double H, int64_t n, const double *x, const double *y,
-                          const double *w, const double *h, int ns, const int *us, const int *ps,
-                          double *a, double *I)
+int oracle_coeffs_sampled_full(double W, double H, int64_t n, const double *x, const double *y,
+                               const double *w, const double *h, int ns, const int *us, const int *ps,
+                               double *a, double *I, double *R, double *Rabs)
 {
     if (!(W > 0) || !(H > 0) || n < 0 || ns < 0) return -2;
     const int64_t CH = 8192;
     int64_t nch = (n + CH - 1) / CH;
-    long double *part = (long double *)malloc(sizeof(long double) * (size_t)(nch > 0 ? nch : 1) * (size_t)ns);
-    if (!part) return -1;
+    size_t np = (size_t)(nch > 0 ? nch : 1) * (size_t)(ns > 0 ? ns : 1);
+    long double *part = (long double *)malloc(sizeof(long double) * np);
+    long double *pabs = (long double *)malloc(sizeof(long double) * np);
+    if (!part || !pabs) { free(part); free(pabs); return -1; }
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t c = 0; c < nch; ++c) {
         int64_t i0 = c * CH, i1 = (i0 + CH < n) ? i0 + CH : n;
         for (int k = 0; k < ns; ++k) {
-            long double s = 0.0L;
+            long double s = 0.0L, sa = 0.0L;
             for (int64_t i = i0; i < i1; ++i) {
                 double Sx, Kx, Ty, Ly;
                 if (us[k] == 0) Sx = w[i]; else edge_diffs(us[k], x[i], w[i], W, &Sx, &Kx);
                 if (ps[k] == 0) Ty = h[i]; else edge_diffs(ps[k], y[i], h[i], H, &Ty, &Ly);
                 s += (long double)Sx * (long double)Ty;
+                sa += fabsl((long double)Sx * (long double)Ty);
             }
             part[(size_t)c * ns + k] = s;
+            pabs[(size_t)c * ns + k] = sa;
         }
     }
     for (int k = 0; k < ns; ++k) {
-        long double r = 0.0L;
-        for (int64_t c = 0; c < nch; ++c) r += part[(size_t)c * ns + k];
-        a[k] = (double)(coef_factor(us[k], ps[k], W, H) * r);
+        long double r = 0.0L, ra = 0.0L;
+        for (int64_t c = 0; c < nch; ++c) {
+            r += part[(size_t)c * ns + k];
+            ra += pabs[(size_t)c * ns + k];
+        }
+        if (a) a[k] = (double)(coef_factor(us[k], ps[k], W, H) * r);
         if (I) I[k] = (double)(moment_factor(us[k], ps[k], W, H) * r);
+        if (R) R[k] = (double)r;
+        if (Rabs) Rabs[k] = (double)ra;
     }
     free(part);
+    free(pabs);
     return 0;
+}
+
+/* Coefficients and moments only (the raw sums and their absolute counterparts are the
+ * sampled-full call's). */
+int oracle_coeffs_sampled(double W, double H, int64_t n, const double *x, const double *y,
+                          const double *w, const double *h, int ns, const int *us, const int *ps,
+                          double *a, double *I)
+{
+    return oracle_coeffs_sampled_full(W, H, n, x, y, w, h, ns, us, ps, a, I, NULL, NULL);
 }
 
 /*
@@ -505,9 +551,15 @@ int oracle_bin_field(double W, double H, int m, int Mu, int Mp, const double *a,
 {
     if (m <= 0 || Mu <= 0 || Mp <= 0) return -1;
     const double pi = ORACLE_PI;
+    int fail = 0;
 #pragma omp parallel for schedule(dynamic)
     for (int l = 0; l < m; ++l) {
         double *cu = (double *)malloc(sizeof(double) * (size_t)(2 * Mu + 2 * Mp));
+        if (!cu) {
+#pragma omp atomic write
+            fail = 1;
+            continue;
+        }
         double *su = cu + Mu, *cp = su + Mu, *sp = cp + Mp;
         for (int u = 0; u < Mu; ++u) bin_trig(u, l, m, &cu[u], &su[u]);
         for (int j = 0; j < m; ++j) {
@@ -526,7 +578,7 @@ int oracle_bin_field(double W, double H, int m, int Mu, int Mp, const double *a,
         }
         free(cu);
     }
-    return 0;
+    return fail ? -2 : 0;
 }
 
 /* Selected bin densities P[ls[k], js[k]] (the same sums as oracle_bin_density, for large grids). */

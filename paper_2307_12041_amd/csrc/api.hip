@@ -10,6 +10,11 @@ namespace pp {
 namespace {
 
 constexpr int kMaxFreq = 65536;
+// Largest block count and frequency-pair count: every launch grid of the library then stays below
+// 2^32 work-items per dimension (the gradient launches take ceil(n / 256) x 512 or ceil(n / 128) x 256
+// work-items, the coefficient-side launches about 2 Mu Mp); grids_fit() checks each one exactly.
+constexpr int64_t kMaxBlocks = ((int64_t)1 << 31) - 512;
+constexpr int64_t kMaxPairs = (int64_t)1 << 30;
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -19,15 +24,19 @@ bool supported_precision(int prec) {
 }
 bool is_bf16(int prec) { return prec == PP_BF16 || prec == PP_BF16X3; }
 
+bool grids_fit(const pp_problem &P);
+
 int validate_problem(const pp_problem *P) {
     if (!P) return PP_ERR_ARG;
     if (!(isfinite(P->W) && P->W > 0.0) || !(isfinite(P->H) && P->H > 0.0)) return PP_ERR_ARG;
-    if (P->n < 0 || P->n > ((int64_t)1 << 40)) return PP_ERR_ARG;
+    if (P->n < 0 || P->n > kMaxBlocks) return PP_ERR_ARG;
     if (P->Mu < 1 || P->Mp < 1 || P->Mu > kMaxFreq || P->Mp > kMaxFreq) return PP_ERR_ARG;
+    if ((int64_t)P->Mu * (int64_t)P->Mp > kMaxPairs) return PP_ERR_ARG;
     if (P->precision < PP_FP64 || P->precision > PP_FP8X3) return PP_ERR_ARG;
     if (P->basis_mode != PP_BASIS_RECOMPUTE && P->basis_mode != PP_BASIS_STORE) return PP_ERR_ARG;
     if (!supported_precision(P->precision)) return PP_ERR_UNSUPPORTED;
     if (P->basis_mode == PP_BASIS_STORE && !is_bf16(P->precision)) return PP_ERR_UNSUPPORTED;
+    if (!grids_fit(*P)) return PP_ERR_ARG;
     return PP_OK;
 }
 
@@ -148,15 +157,58 @@ StoreTables store_tables(const pp_problem &P, const Layout &L, char *base) {
     return t;
 }
 
+// Work-items of one grid dimension: blocks x threads, which must stay below 2^32.
+bool dim_ok(uint64_t blocks, uint64_t threads) { return blocks * threads <= 0xffffffffull; }
+
+uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+// Every launch that any entry point may enqueue for P fits its grid (checked before any enqueue;
+// the kMaxBlocks and kMaxPairs bounds keep every product here far from 64-bit overflow).
+bool grids_fit(const pp_problem &P) {
+    const uint64_t n = (uint64_t)P.n, MM = (uint64_t)P.Mu * (uint64_t)P.Mp;
+    const FwdPlan f = fwd_plan(P);
+    const BwdPlan b = bwd_plan(P);
+    const bool bf = is_bf16(P.precision);
+    const uint64_t tiles = (uint64_t)f.tiles_u * (uint64_t)f.tiles_p;
+    bool ok = dim_ok(tiles, bf && P.precision == PP_BF16 ? 512 : 256) && (uint64_t)f.splits <= 0xffffffffull;
+    ok = ok && dim_ok((uint64_t)reduce_scale_blocks(P.Mu, P.Mp), 256);   // split-K reduction
+    ok = ok && dim_ok(cdiv(MM, 256), 256);                                 // row-form operands (FP64 / FP32)
+    ok = ok && dim_ok(cdiv(n, 256), 256);                                  // final per-block sums
+    if (bf) {
+        ok = ok && dim_ok(cdiv((uint64_t)phase_rows(P.n), 256), 256);
+        for (int axis = 0; axis < 2; ++axis) {
+            const int Nb = axis == 0 ? P.Mu : P.Mp, Ka = axis == 0 ? P.Mp : P.Mu;
+            const uint64_t elems = bwd_bf16_operand_elems((Nb + 255) / 256 * 256, bf16_kh(Ka));
+            ok = ok && dim_ok(cdiv(elems, 256), 256);                       // tiled gradient operands
+        }
+        ok = ok && dim_ok(cdiv(n, 256), 512) && (uint64_t)b.tiles_nx <= 65535 && (uint64_t)b.tiles_ny <= 65535;
+        if (P.basis_mode == PP_BASIS_STORE) {
+            const uint64_t rows = (uint64_t)store_rows(P.n);
+            const uint64_t tb = cdiv(cdiv(n, 256), 8) * 8;
+            for (int M : {P.Mu, P.Mp}) {
+                ok = ok && dim_ok(cdiv(rows * ((uint64_t)store_ld(M) / 32), 256), 256);   // table build
+                ok = ok && dim_ok(tb * cdiv((uint64_t)M, 256), 512);                      // gradient from tables
+            }
+            ok = ok && dim_ok(tiles * cdiv((uint64_t)f.splits, 8) * 8, 512);               // forward from tables
+        }
+    } else {
+        ok = ok && dim_ok(cdiv(n, (uint64_t)b.tb), 256) && (uint64_t)b.tiles_nx <= 65535 &&
+             (uint64_t)b.tiles_ny <= 65535;
+    }
+    return ok;
+}
+
 int check_ws(const Layout &L, void *ws, size_t ws_bytes) {
     if (ws_bytes < L.total) return PP_ERR_WORKSPACE;
     if (L.total > 0 && (!ws || ((uintptr_t)ws % kAlign) != 0)) return PP_ERR_ARG;
     return PP_OK;
 }
 
-// Forward pipeline: partial contractions -> coefficients (+ energy partials) -> energy.
+// Forward pipeline: partial contractions -> coefficients (+ energy partials) -> energy.  With
+// timed = false no launch is ever bracketed by timing events.
 int run_forward(const pp_problem &P, const double *x, const double *y, const double *w, const double *h,
-                double *a, double *E, void *ws, hipStream_t s) {
+                double *a, double *E, void *ws, hipStream_t s, bool timed = true) {
+    auto T = [timed](const char *name) { return timed ? name : nullptr; };
     const FwdPlan f = fwd_plan(P);
     const Layout L = layout(P);
     char *base = (char *)ws;
@@ -166,35 +218,35 @@ int run_forward(const pp_problem &P, const double *x, const double *y, const dou
     if (is_bf16(P.precision)) {
         const bool x3 = P.precision == PP_BF16X3;
         PhaseRec *tx = (PhaseRec *)(base + L.tx), *ty = (PhaseRec *)(base + L.ty);
-        { TimedLaunch t("tables", s); err = launch_phase_tables(P.n, x, y, w, h, P.W, P.H, tx, ty, s); }
+        { TimedLaunch t(T("tables"), s); err = launch_phase_tables(P.n, x, y, w, h, P.W, P.H, tx, ty, s); }
         if (err != hipSuccess) return PP_ERR_DEVICE;
         if (P.basis_mode == PP_BASIS_STORE) {
             const StoreTables st = store_tables(P, L, base);
             {
-                TimedLaunch t("build", s);
+                TimedLaunch t(T("build"), s);
                 err = launch_build_table(x3, P.n, P.Mu, tx, (unsigned short *)st.xh, (unsigned short *)st.xl, s);
                 if (err == hipSuccess)
                     err = launch_build_table(x3, P.n, P.Mp, ty, (unsigned short *)st.yh, (unsigned short *)st.yl, s);
             }
             if (err != hipSuccess) return PP_ERR_DEVICE;
-            { TimedLaunch t("fwd", s); err = launch_fwd_bf16_st(f, x3, P.n, P.Mu, P.Mp, st, (float *)part, s); }
+            { TimedLaunch t(T("fwd"), s); err = launch_fwd_bf16_st(f, x3, P.n, P.Mu, P.Mp, st, (float *)part, s); }
         } else {
-            TimedLaunch t("fwd", s);
+            TimedLaunch t(T("fwd"), s);
             err = launch_fwd_bf16(f, x3, P.n, P.Mu, P.Mp, tx, ty, (float *)part, s);
         }
     } else if (P.precision == PP_FP32) {
-        TimedLaunch t("fwd", s);
+        TimedLaunch t(T("fwd"), s);
         err = launch_fwd_f32(f, P.n, P.Mu, P.Mp, P.W, P.H, x, y, w, h, (float *)part, s);
     } else {
-        TimedLaunch t("fwd", s);
+        TimedLaunch t(T("fwd"), s);
         err = launch_fwd_f64(f, P.n, P.Mu, P.Mp, P.W, P.H, x, y, w, h, (double *)part, s);
     }
     if (err != hipSuccess) return PP_ERR_DEVICE;
     int nb = 0;
-    { TimedLaunch t("reduce", s); err = launch_reduce_scale(part, f.part_elem == 4, f.splits, P.Mu, P.Mp, P.W, P.H, a, epart, &nb, s); }
+    { TimedLaunch t(T("reduce"), s); err = launch_reduce_scale(part, f.part_elem == 4, f.splits, P.Mu, P.Mp, P.W, P.H, a, epart, &nb, s); }
     if (err != hipSuccess) return PP_ERR_DEVICE;
     if (E) {
-        { TimedLaunch t("energy", s); err = launch_energy_final(epart, nb, E, s); }
+        { TimedLaunch t(T("energy"), s); err = launch_energy_final(epart, nb, E, s); }
         if (err != hipSuccess) return PP_ERR_DEVICE;
     }
     return PP_OK;

@@ -109,7 +109,8 @@ struct StoreTables {
     int ldx, ldy;
 };
 
-// Brackets one kernel launch with HIP events when event timing is on (timing.hip).
+// Brackets one kernel launch with HIP events when event timing is on (timing.hip); a NULL name
+// marks a launch that is never timed (no event is created for it).
 class TimedLaunch {
   public:
     TimedLaunch(const char *name, hipStream_t s);

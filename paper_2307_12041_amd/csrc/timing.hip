@@ -31,6 +31,7 @@ void clear_locked() {
 }  // namespace
 
 TimedLaunch::TimedLaunch(const char *name, hipStream_t s) : name_(name), s_(s) {
+    if (!name) return;   // an untimed launch site
     std::lock_guard<std::mutex> lk(g_mu);
     if (!g_on) return;
     if (hipEventCreate((hipEvent_t *)&start_) != hipSuccess) return;

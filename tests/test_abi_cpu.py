@@ -57,6 +57,16 @@ def ws_size(lib, prob):
     return st, out.value
 
 
+def test_limits_are_inclusive(lib):
+    """The largest documented problems are accepted (their grids fit): n = 2^31 - 512 blocks,
+    Mu * Mp = 2^30 frequency pairs, and the largest stored-basis problem of one shape."""
+    for prec in (0, 1, 2, 3):
+        assert ws_size(lib, P(n=2 ** 31 - 512, precision=prec))[0] == 0
+        assert ws_size(lib, P(Mu=65536, Mp=16384, precision=prec))[0] == 0
+        assert ws_size(lib, P(Mu=32768, Mp=32768, precision=prec, n=100))[0] == 0
+    assert ws_size(lib, P(precision=3, basis_mode=1, n=256 * (2 ** 21 // 4 - 1), Mu=1024, Mp=8))[0] == 0
+
+
 def test_workspace_size_monotone_and_host_only(lib):
     st, a = ws_size(lib, P(n=1000))
     assert st == 0 and a > 0 and a % 256 == 0
@@ -72,6 +82,8 @@ def test_workspace_size_monotone_and_host_only(lib):
     (dict(W=0.0), -1), (dict(W=-1.0), -1), (dict(H=math.nan), -1), (dict(W=math.inf), -1),
     (dict(Mu=0), -1), (dict(Mp=-3), -1), (dict(Mu=70000), -1), (dict(n=-1), -1),
     (dict(precision=9), -1), (dict(basis_mode=5), -1),
+    (dict(n=2 ** 31 - 511), -1), (dict(Mu=65536, Mp=16385), -1), (dict(Mu=32768, Mp=32769), -1),
+    (dict(precision=3, basis_mode=1, n=2 ** 29, Mu=1024, Mp=8), -1),
 ])
 def test_workspace_size_rejects(lib, bad, code):
     st, v = ws_size(lib, P(**bad))
@@ -228,18 +240,25 @@ _FLOATS = st.one_of(st.floats(allow_nan=True, allow_infinity=True),
 
 
 def _documented_status(W, H, n, Mu, Mp, prec, basis):
+    """The status include/pplace.h documents for a problem (its limits: n <= 2^31 - 512,
+    Mu * Mp <= 2^30, and for the stored basis ceil(n / 256) * ceil(max(Mu, Mp) / 256) < 2^21)."""
     ok = lambda v: math.isfinite(v) and v > 0.0
-    if (not ok(W) or not ok(H) or n < 0 or n > 2 ** 40 or not 1 <= Mu <= 65536 or not 1 <= Mp <= 65536
-            or not 0 <= prec <= 5 or basis not in (0, 1)):
+    if (not ok(W) or not ok(H) or n < 0 or n > 2 ** 31 - 512 or not 1 <= Mu <= 65536 or not 1 <= Mp <= 65536
+            or Mu * Mp > 2 ** 30 or not 0 <= prec <= 5 or basis not in (0, 1)):
         return -1
     if prec in (4, 5) or (basis == 1 and prec not in (2, 3)):
         return -3
+    if basis == 1 and -(-n // 256) * -(-max(Mu, Mp) // 256) >= 2 ** 21:
+        return -1
     return 0
 
 
-@settings(max_examples=300, deadline=None)
-@given(W=_FLOATS, H=_FLOATS, n=st.integers(-5, 2 ** 41), Mu=st.integers(-3, 70000), Mp=st.integers(-3, 70000),
-       prec=st.integers(-2, 7), basis=st.integers(-1, 2))
+_N = st.one_of(st.integers(-5, 2 ** 41), st.integers(2 ** 31 - 600, 2 ** 31 + 100), st.integers(0, 2 ** 27))
+_M = st.one_of(st.integers(-3, 70000), st.integers(16000, 65536), st.integers(32760, 32776))
+
+
+@settings(max_examples=600, deadline=None)
+@given(W=_FLOATS, H=_FLOATS, n=_N, Mu=_M, Mp=_M, prec=st.integers(-2, 7), basis=st.integers(-1, 2))
 def test_workspace_size_accepts_exactly_the_documented_problems(lib, W, H, n, Mu, Mp, prec, basis):
     st_, v = ws_size(lib, P(W=W, H=H, n=n, Mu=Mu, Mp=Mp, precision=prec, basis_mode=basis))
     assert st_ == _documented_status(W, H, n, Mu, Mp, prec, basis)

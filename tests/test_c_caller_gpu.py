@@ -1,6 +1,7 @@
 """The C ABI from a plain C++ caller (tests/c_abi/abi_caller.cpp): HIP runtime allocations and
 stream, pp_workspace_size, pp_energy and pp_field, no Python binding and no torch on the path,
-against the FP64 oracle.  The caller is a shared library built by build() and driven in-process."""
+against the FP64 oracle (whole arrays and worst tiles of the flat-spectrum raw sums and of the
+gradient).  The caller is a shared library built by build() and driven in-process."""
 import ctypes
 import os
 import sys
@@ -9,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests import parity
 from workloads import make_random
 
 pytestmark = pytest.mark.gpu
@@ -57,8 +59,12 @@ def test_plain_cpp_caller_matches_oracle(caller, prec):
     assert st == 0, msg
     Eo, ao, _ = oracle.energy(wl.W, wl.H, *wl.arrays(), wl.Mu, wl.Mp)
     gxo, gyo = oracle.grad(wl.W, wl.H, *wl.arrays(), ao)
-    errs = (abs(E - Eo) / Eo, rel(a, ao), rel(np.concatenate([gx, gy]), np.concatenate([gxo, gyo])))
-    say(f"   E {errs[0]:.2e}  a {errs[1]:.2e}  g {errs[2]:.2e}")
+    f = oracle.coef_factors(wl.W, wl.H, wl.Mu, wl.Mp)
+    ce = parity.coeff_errors(a, parity.raw_from_coeffs(ao, f), f)
+    g, go = np.stack([gx, gy], axis=1), np.stack([gxo, gyo], axis=1)
+    errs = (abs(E - Eo) / Eo, rel(a, ao), ce["flat"], ce["flat_tile"], rel(g, go), parity.row_tile_rel_max(g, go))
+    say(f"   E {errs[0]:.2e}  a {errs[1]:.2e}  flat a {errs[2]:.2e} (worst 64x64 tile {errs[3]:.2e})  "
+        f"g {errs[4]:.2e} (worst 256-block tile {errs[5]:.2e})")
     assert max(errs) <= PREC[prec][1], errs
 
 

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests import gpu_parity, parity
 from workloads import Workload, make_random
 
 torch = pytest.importorskip("torch")
@@ -33,33 +34,35 @@ def rel(a, b):
 
 
 def oracle_of(wl, with_eval=True):
-    Eo, ao, _ = oracle.energy(wl.W, wl.H, *wl.arrays(), wl.Mu, wl.Mp)
-    gxo, gyo = oracle.grad(wl.W, wl.H, *wl.arrays(), ao)
-    ref = {"E": Eo, "a": ao, "g": np.concatenate([gxo, gyo])}
+    """The oracle's coefficients, energy and gradients (tests/gpu_parity.py) and, with_eval, its
+    block potentials and centre field of flat-spectrum coefficients (any coefficients are valid
+    inputs of these linear maps; flat ones weigh every frequency tile alike)."""
+    ref = gpu_parity.OracleRef(wl)
     if with_eval:
-        ref["N"] = oracle.block_potential(wl.W, wl.H, *wl.arrays(), ao)
-        po, exo, eyo = oracle.point_field(wl.W, wl.H, ao, wl.x, wl.y)
-        ref["psi"], ref["xi"] = po, np.concatenate([exo, eyo])
+        ref.a_pt = parity.flat_point_coeffs(wl.Mu, wl.Mp, 23)
+        ref.a_pot = parity.flat_potential_coeffs(wl.W, wl.H, wl.Mu, wl.Mp, 29)
+        ref.N = oracle.block_potential(wl.W, wl.H, *wl.arrays(), ref.a_pot)
+        po, exo, eyo = oracle.point_field(wl.W, wl.H, ref.a_pt, wl.x, wl.y)
+        ref.psi, ref.xi = po, np.stack([exo, eyo], axis=1)
     return ref
 
 
 def full_check(wl, prec, ref=None, with_eval=True):
-    """Coefficients, energy, gradient (and, with_eval, block potentials and the centre field of the
-    oracle's coefficients) against the oracle."""
+    """Every metric of tests/gpu_parity.py (and, with_eval, the block potentials and the centre
+    field of flat-spectrum coefficients, whole and per 256-block tile) against the oracle."""
     ref = oracle_of(wl, with_eval) if ref is None else ref
-    x, y, w, h = dev(*wl.arrays())
-    E, a = pp.energy(x, y, w, h, W=wl.W, H=wl.H, Mu=wl.Mu, Mp=wl.Mp, precision=prec)
-    gx, gy = pp.field(x, y, w, h, a, W=wl.W, H=wl.H, precision=prec)
-    Eo = ref["E"]
-    errs = {"a": rel(a.cpu().numpy(), ref["a"]), "E": abs(float(E.cpu()) - Eo) / (abs(Eo) if Eo else 1.0),
-            "g": rel(np.concatenate([gx.cpu().numpy(), gy.cpu().numpy()]), ref["g"])}
+    outs = gpu_parity.run_gpu(wl, prec, ref=ref)
+    errs = {k: v for k, v in gpu_parity.errors(ref, *outs).items() if not k.startswith("_")}
     if with_eval:
-        ta = dev(ref["a"])[0]
-        N = pp.block_potential(x, y, w, h, ta, W=wl.W, H=wl.H, precision=prec)
-        psi, ex, ey = pp.point_field(x, y, ta, W=wl.W, H=wl.H, precision=prec)
-        errs["N"] = rel(N.cpu().numpy(), ref["N"])
-        errs["xi"] = rel(np.concatenate([ex.cpu().numpy(), ey.cpu().numpy()]), ref["xi"])
-        errs["psi"] = rel(psi.cpu().numpy(), ref["psi"])
+        x, y, w, h = dev(*wl.arrays())
+        tpt, tpot = dev(ref.a_pt, ref.a_pot)
+        N = pp.block_potential(x, y, w, h, tpot, W=wl.W, H=wl.H, precision=prec).cpu().numpy()
+        psi, ex, ey = pp.point_field(x, y, tpt, W=wl.W, H=wl.H, precision=prec)
+        xi = np.stack([ex.cpu().numpy(), ey.cpu().numpy()], axis=1)
+        psi = psi.cpu().numpy()
+        errs["N"], errs["N_tile"] = rel(N, ref.N), parity.row_tile_rel_max(N, ref.N)
+        errs["xi"], errs["xi_tile"] = rel(xi, ref.xi), parity.row_tile_rel_max(xi, ref.xi)
+        errs["psi"], errs["psi_tile"] = rel(psi, ref.psi), parity.row_tile_rel_max(psi, ref.psi)
     return errs
 
 

@@ -46,6 +46,8 @@ MUTANTS = {
     "bin interpolation drops the gradient sign": ("if (xix) gx[i] = (double)-sx;", "if (xix) gx[i] = (double)sx;"),
     "bin interpolation area uses the width twice": ("const long double area = (long double)ox * oy;",
                                                     "const long double area = (long double)ox * ox;"),
+    "sampled absolute sums lose the absolute value": ("sa += fabsl((long double)Sx * (long double)Ty);",
+                                                      "sa += (long double)Sx * (long double)Ty;"),
     "block potential y integral": ("for (int p = 0; p < Mp; ++p) Yb[p] = edge_integral(p, y[i], h[i], H);",
                                    "for (int p = 0; p < Mp; ++p) Yb[p] = edge_integral(p, y[i], w[i], H);"),
 }

@@ -596,3 +596,41 @@ def test_bin_scheme_block_values_converge_to_the_direct_ones():
                         np.abs(gx - gx_dir).max() / np.abs(gx_dir).max(),
                         np.abs(gy - gy_dir).max() / np.abs(gy_dir).max()))
     assert errs[0] < 2e-2 and errs[1] < 2e-3 and errs[1] < errs[0] / 8, errs
+
+
+# ---------------------------------------------------------------------------------------------
+# Raw block sums, their absolute counterparts and the closed-form prefactors (the quantities the
+# tile-resolving parity metrics compare): S'_iu is w_u times the integral of cos(w_u t) over the
+# block (the block width at u = 0), taken here by Gauss-Legendre quadrature rather than by the
+# oracle's sine differences; R = sum_i S' T', Rabs = sum_i |S' T'|, and f R = a with the pinned a.
+# ---------------------------------------------------------------------------------------------
+def _quad_basis(c, s, L, M, nodes=64):
+    t, wq = np.polynomial.legendre.leggauss(nodes)
+    out = np.zeros((len(c), M))
+    for i, (ci, si) in enumerate(zip(c, s)):
+        pts = ci + 0.5 * si * t
+        for k in range(M):
+            wk = k * PI / L
+            integ = 0.5 * si * np.sum(wq * np.cos(wk * pts))
+            out[i, k] = integ * (wk if k > 0 else 1.0)
+    return out
+
+
+def test_raw_moments_and_absolute_sums_by_quadrature():
+    wl = make_random(7, 30.0, 20.0, 11, 9, seed=71, wmax=6.0, hmax=5.0)
+    Sx = _quad_basis(wl.x, wl.w, wl.W, wl.Mu)
+    Ty = _quad_basis(wl.y, wl.h, wl.H, wl.Mp)
+    Rq = Sx.T @ Ty
+    Raq = np.abs(Sx).T @ np.abs(Ty)
+    R = oracle.raw_moments(wl.W, wl.H, *wl.arrays(), wl.Mu, wl.Mp)
+    assert np.allclose(R, Rq, rtol=0, atol=1e-12 * np.abs(Rq).max())
+    us, ps = np.meshgrid(np.arange(wl.Mu), np.arange(wl.Mp), indexing="ij")
+    us, ps = us.ravel(), ps.ravel()
+    a_s, R_s, Ra_s = oracle.coeffs_sampled_full(wl.W, wl.H, *wl.arrays(), us, ps)
+    assert np.allclose(R_s, Rq.ravel(), rtol=0, atol=1e-12 * np.abs(Rq).max())
+    assert np.allclose(Ra_s, Raq.ravel(), rtol=1e-12, atol=1e-13 * Raq.max())
+    a, _ = oracle.coeffs(wl.W, wl.H, *wl.arrays(), wl.Mu, wl.Mp)
+    f = oracle.coef_factors(wl.W, wl.H, wl.Mu, wl.Mp)
+    assert f[0, 0] == 0.0 and np.all(f.ravel()[1:] > 0)
+    assert np.allclose(f * Rq, a, rtol=0, atol=1e-12 * np.abs(a).max())
+    assert np.allclose(a_s, a.ravel(), rtol=1e-14, atol=0)

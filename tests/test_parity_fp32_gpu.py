@@ -5,13 +5,16 @@ The FP32 path rounds every basis value (generated in FP64) once to FP32 (relativ
 accumulates on v_mfma_f32_16x16x4f32 in FP32 within one K split (at most a few thousand blocks),
 FP64 across splits.  With table rounding u = 6e-8 and FP32 summation of k terms bounded by
 ~sqrt(k) u in the norm (random rounding), the coefficient, energy and gradient errors are a few
-1e-7 at k ~ 1e3; the bar is 1e-5."""
+1e-7 at k ~ 1e3; the bar is 1e-5 for every metric of tests/gpu_parity.py (whole and per-tile
+errors of the flat-spectrum raw sums and of the gradients of the run's own and of flat-spectrum
+coefficients)."""
 import sys
 
 import numpy as np
 import pytest
 
 import oracle
+from tests import gpu_parity
 from workloads import make_config, make_random
 
 torch = pytest.importorskip("torch")
@@ -52,43 +55,22 @@ def run(wl, prec):
     (700, 40, 600, 64.0, 800.0, 5),
 ])
 def test_fp32_parity_shapes(n, Mu, Mp, W, H, seed):
-    wl = make_random(n, W, H, Mu, Mp, seed=seed)
-    say(f"[parity] {wl.name} n={wl.n} Mu={wl.Mu} Mp={wl.Mp} prec=fp32")
-    E, a, gx, gy = run(wl, "fp32")
-    Eo, ao, _ = oracle.energy(wl.W, wl.H, *wl.arrays(), wl.Mu, wl.Mp)
-    gxo, gyo = oracle.grad(wl.W, wl.H, *wl.arrays(), ao)
-    ea, eE = rel(a, ao), abs(E - Eo) / abs(Eo)
-    eg = rel(np.concatenate([gx, gy]), np.concatenate([gxo, gyo]))
-    say(f"   rel err a={ea:.3e} E={eE:.3e} g={eg:.3e}")
-    assert ea <= TOL["fp32"] and eE <= TOL["fp32"] and eg <= TOL["fp32"], (ea, eE, eg)
+    gpu_parity.check(make_random(n, W, H, Mu, Mp, seed=seed), "fp32", TOL["fp32"])
 
 
 def test_fp32_parity_overhanging_and_macros():
     wl = make_random(800, 400.0, 300.0, 96, 80, seed=8, wmax=60.0, hmax=40.0, inside=False)
-    say(f"[parity] {wl.name} overhanging, prec=fp32")
-    E, a, gx, gy = run(wl, "fp32")
-    Eo, ao, _ = oracle.energy(wl.W, wl.H, *wl.arrays(), wl.Mu, wl.Mp)
-    gxo, gyo = oracle.grad(wl.W, wl.H, *wl.arrays(), ao)
-    errs = (rel(a, ao), abs(E - Eo) / abs(Eo), rel(np.concatenate([gx, gy]), np.concatenate([gxo, gyo])))
-    say(f"   rel err a={errs[0]:.3e} E={errs[1]:.3e} g={errs[2]:.3e}")
-    assert max(errs) <= TOL["fp32"], errs
+    gpu_parity.check(wl, "fp32", TOL["fp32"])
 
 
 def test_precisions_cells200k_macros50_M512():
     """FP32 against the BF16 split on the coefficient contraction (and energy, gradient), with the
-    FP64 path beside them; one oracle evaluation serves all three."""
+    FP64 path beside them; one oracle evaluation (gradients at 3000 sampled blocks) serves all three."""
     wl = make_config(2)
     say(f"[parity] {wl.name} n={wl.n} Mu={wl.Mu} Mp={wl.Mp}: fp64, fp32, bf16x3 vs oracle")
-    Eo, ao, _ = oracle.energy(wl.W, wl.H, *wl.arrays(), wl.Mu, wl.Mp)
-    idx = np.sort(np.random.default_rng(0).choice(wl.n, 3000, replace=False))
-    gxo, gyo = oracle.grad_sampled(wl.W, wl.H, *wl.arrays(), ao, idx)
-    go = np.concatenate([gxo, gyo])
+    ref = gpu_parity.OracleRef(wl, grad_sample=3000)
     for prec in ("fp64", "fp32", "bf16x3"):
-        E, a, gx, gy = run(wl, prec)
-        ea, eE = rel(a, ao), abs(E - Eo) / abs(Eo)
-        eg = rel(np.concatenate([gx[idx], gy[idx]]), go)
-        say(f"   {prec:7s} rel err a={ea:.3e} E={eE:.3e} g={eg:.3e}")
-        assert ea <= TOL[prec] and eE <= TOL[prec] and eg <= TOL[prec], (prec, ea, eE, eg)
+        gpu_parity.check(wl, prec, TOL[prec], ref=ref)
 
 
 def test_fp32_zero_blocks_and_autograd():
