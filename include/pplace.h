@@ -56,7 +56,8 @@ typedef enum pp_status {
                                  misalignment */
     PP_ERR_WORKSPACE = -2,    /* ws_bytes smaller than pp_workspace_size() */
     PP_ERR_UNSUPPORTED = -3,  /* precision / basis mode not implemented by the library */
-    PP_ERR_DEVICE = -4        /* a HIP launch or runtime call failed */
+    PP_ERR_DEVICE = -4,       /* a HIP launch or runtime call failed */
+    PP_ERR_SCRATCH = -5       /* pp_energy_static: the problem needs more than PP_STATIC_SCRATCH_BYTES */
 } pp_status;
 
 /* Arithmetic of the basis tables and the three contractions.  Seeds of the basis recurrences are
@@ -113,6 +114,23 @@ int pp_coeffs(const pp_problem *P, const double *x, const double *y, const doubl
  * coefficients.  E: out, one FP64 value in device memory.  a: out [Mu * Mp] FP64, or NULL. */
 int pp_energy(const pp_problem *P, const double *x, const double *y, const double *w, const double *h,
               double *E, double *a, void *ws, size_t ws_bytes, void *stream);
+
+/* Bytes of the device array that serves pp_energy_static as its workspace (128 MiB). */
+#define PP_STATIC_SCRATCH_BYTES (128u << 20)
+
+/* pp_energy for callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same computation, kernels and results as
+ * pp_energy, with the workspace taken from an array of PP_STATIC_SCRATCH_BYTES that the library
+ * holds on each device it runs on until the process ends, instead of a caller workspace.  The call
+ * allocates nothing (no hipMalloc, no allocating library routine; the first call on a device only
+ * looks up the array's address there) and records no timing events.
+ * Arguments, outputs and errors as for pp_energy; P->basis_mode must be PP_BASIS_RECOMPUTE
+ * (PP_ERR_UNSUPPORTED otherwise); a problem whose pp_workspace_size() exceeds
+ * PP_STATIC_SCRATCH_BYTES gives PP_ERR_SCRATCH before anything is enqueued.
+ * Every call on one device shares that device's array: calls that may overlap on a device (other
+ * streams, other host threads) race and must be serialised by the caller. */
+int pp_energy_static(const pp_problem *P, const double *x, const double *y, const double *w, const double *h,
+                     double *E, double *a, void *stream);
 
 /* Per-block energy gradient, scaled by an upstream derivative (Sec. III-A field, eq. ksi,
  * integrated over each block).

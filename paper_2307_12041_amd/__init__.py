@@ -18,7 +18,7 @@ import os
 import torch
 
 __all__ = ["PRECISIONS", "BASIS_MODES", "PPError", "library_path", "load", "workspace_size", "coeffs",
-           "energy", "field", "point_field", "block_potential", "PPEnergy", "energy_autograd", "timing_enable",
+           "energy", "energy_static", "field", "point_field", "block_potential", "PPEnergy", "energy_autograd", "timing_enable",
            "timing_query", "bin_workspace_size", "bin_density", "bin_coeffs", "bin_field"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -28,7 +28,8 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "fp8": 4, "fp8x3": 5
 BASIS_MODES = {"recompute": 0, "store": 1}
 
 PP_OK = 0
-EXPORTS = ("pp_workspace_size", "pp_coeffs", "pp_energy", "pp_field", "pp_point_field", "pp_block_potential",
+EXPORTS = ("pp_workspace_size", "pp_coeffs", "pp_energy", "pp_energy_static", "pp_field", "pp_point_field",
+           "pp_block_potential",
            "pp_strerror", "pp_timing_enable", "pp_timing_query", "pp_bin_workspace_size", "pp_bin_density",
            "pp_bin_coeffs", "pp_bin_field", "pp_bin_interp")
 
@@ -70,6 +71,7 @@ def load():
     lib.pp_workspace_size.argtypes = [P, ctypes.POINTER(sz)]
     lib.pp_coeffs.argtypes = [P, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.pp_energy.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.pp_energy_static.argtypes = [P, vp, vp, vp, vp, vp, vp, vp]
     lib.pp_field.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.pp_point_field.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.pp_block_potential.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, sz, vp]
@@ -85,7 +87,8 @@ def load():
     lib.pp_bin_coeffs.argtypes = [B, vp, vp, vp, sz, vp]
     lib.pp_bin_field.argtypes = [B, vp, vp, vp, vp, vp, sz, vp]
     lib.pp_bin_interp.argtypes = [B, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
-    for f in ("pp_workspace_size", "pp_coeffs", "pp_energy", "pp_field", "pp_point_field", "pp_block_potential",
+    for f in ("pp_workspace_size", "pp_coeffs", "pp_energy", "pp_energy_static", "pp_field", "pp_point_field",
+              "pp_block_potential",
               "pp_bin_workspace_size", "pp_bin_density", "pp_bin_coeffs", "pp_bin_field", "pp_bin_interp"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
@@ -177,6 +180,20 @@ def energy(x, y, w, h, *, W, H, Mu, Mp, precision="fp64", basis="recompute", wan
                               _stream(dev))
     if st != PP_OK:
         raise PPError(st, "pp_energy")
+    return E, a
+
+
+def energy_static(x, y, w, h, *, W, H, Mu, Mp, precision="fp64", want_coeffs=True):
+    """energy() through pp_energy_static: the library's own per-device static scratch serves as the
+    workspace (no allocation inside the call; at most PP_STATIC_SCRATCH_BYTES)."""
+    dev, n = _blocks(x, y, w, h)
+    P = _problem(W, H, n, Mu, Mp, precision, "recompute")
+    E = torch.empty((), dtype=torch.float64, device=dev)
+    a = torch.empty((Mu, Mp), dtype=torch.float64, device=dev) if want_coeffs else None
+    with torch.cuda.device(dev):
+        st = load().pp_energy_static(ctypes.byref(P), _vp(x), _vp(y), _vp(w), _vp(h), _vp(E), _vp(a), _stream(dev))
+    if st != PP_OK:
+        raise PPError(st, "pp_energy_static")
     return E, a
 
 

@@ -3,8 +3,16 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "../../include/pplace.h"
 #include "common.h"
+
+// Workspace of pp_energy_static, for callers that cannot allocate: one copy of this array on
+// every device the library runs on, held until the process ends.  Host code never uses the name
+// itself (on the host it is only a stand-in); it uses the device address that
+// hipGetSymbolAddress gives once per device (scratch_on_current_device below).
+static __device__ __align__(256) char scratch[PP_STATIC_SCRATCH_BYTES];
 
 namespace pp {
 namespace {
@@ -252,6 +260,24 @@ int run_forward(const pp_problem &P, const double *x, const double *y, const dou
     return PP_OK;
 }
 
+// Device address of `scratch` on each device, resolved once per device with that device current.
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxScratchDevices] = {};
+
+int scratch_on_current_device(void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxScratchDevices) return PP_ERR_DEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return PP_ERR_DEVICE;
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return PP_OK;
+}
+
 // FP64 / FP32 row-form contractions (FP32 operands for PP_FP32, FP64 otherwise).
 hipError_t prep_rowform(const pp_problem &P, RowForm f, const double *a, void *bx, void *by, hipStream_t s) {
     TimedLaunch t("prep", s);
@@ -299,6 +325,23 @@ int pp_energy(const pp_problem *P, const double *x, const double *y, const doubl
     const Layout L = layout(*P);
     if ((st = check_ws(L, ws, ws_bytes)) != PP_OK) return st;
     return run_forward(*P, x, y, w, h, a, E, ws, (hipStream_t)stream);
+}
+
+int pp_energy_static(const pp_problem *P, const double *x, const double *y, const double *w, const double *h,
+                     double *E, double *a, void *stream) {
+    int st = validate_problem(P);
+    if (st != PP_OK) return st;
+    if (P->basis_mode != PP_BASIS_RECOMPUTE) return PP_ERR_UNSUPPORTED;
+    if ((st = validate_blocks(P, x, y, w, h)) != PP_OK) return st;
+    if (!E || !aligned8(E) || (a && !aligned8(a))) return PP_ERR_ARG;
+    const Layout L = layout(*P);
+    if (L.total > (size_t)PP_STATIC_SCRATCH_BYTES) return PP_ERR_SCRATCH;
+    void *ws = nullptr;
+    if ((st = scratch_on_current_device(&ws)) != PP_OK) return st;
+    // Every byte of the workspace that the forward reads is written earlier in the same call (phase
+    // records with their zero padding, every split's partial tile, every energy partial), so what an
+    // earlier call left in the shared array needs no clearing.  No launch of this call is timed.
+    return run_forward(*P, x, y, w, h, a, E, ws, (hipStream_t)stream, false);
 }
 
 int pp_field(const pp_problem *P, const double *x, const double *y, const double *w, const double *h,
@@ -491,6 +534,7 @@ const char *pp_strerror(int status) {
         case PP_ERR_WORKSPACE: return "workspace smaller than pp_workspace_size()";
         case PP_ERR_UNSUPPORTED: return "precision or basis mode not implemented by the library";
         case PP_ERR_DEVICE: return "HIP launch or runtime error";
+        case PP_ERR_SCRATCH: return "problem needs more workspace than the static scratch (PP_STATIC_SCRATCH_BYTES)";
         default: return "unknown status";
     }
 }

@@ -40,7 +40,7 @@ def test_exports_match_header(lib):
 
 
 def test_strerror(lib):
-    for st in (0, -1, -2, -3, -4, 7):
+    for st in (0, -1, -2, -3, -4, -5, 7):
         s = lib.pp_strerror(st)
         assert isinstance(s, bytes) and len(s) > 3
 
