@@ -41,7 +41,7 @@ def rel(a, b):
 
 # The sources that build the bf16 contraction kernels and their launches (the kernels whose HBM
 # traffic profiles/traffic_* records).
-TRAFFIC_SOURCES = ("api.hip", "common.h", "kernels_bf16.hip", "kernels_common.hip")
+TRAFFIC_SOURCES = ("api.hip", "common.h", "basis_gen.h", "kernels_bf16.hip", "kernels_common.hip")
 
 
 def kernel_source_hash():
@@ -91,7 +91,7 @@ def timed_steps(pp, torch, t, wl, prec, steps, warmup, ws, positions=None, basis
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stages = {}
-    for st in ("tables", "build", "fwd", "reduce", "energy", "prep", "bwd", "final", "point", "potential"):
+    for st in ("tables", "seeds", "build", "fwd", "reduce", "energy", "prep", "bwd", "final", "point", "potential"):
         ms, cnt = pp.timing_query(st)
         if cnt:
             stages[st] = (ms, cnt)

@@ -61,8 +61,9 @@ typedef enum pp_status {
 } pp_status;
 
 /* Arithmetic of the basis tables and the three contractions.  Seeds of the basis recurrences are
- * always reduced in FP64; the final reductions (coefficients, energy, per-block gradient sums)
- * are always FP64. */
+ * always reduced in FP64; the final reductions (coefficients, energy) are FP64; the per-block
+ * gradient sums add runs of 32 columns in FP32 (bf16 paths; every column in the FP64 path) and
+ * the runs in FP64. */
 typedef enum pp_precision {
     PP_FP64 = 0,    /* FP64 tables, FP64 MFMA */
     PP_FP32 = 1,    /* FP32 tables (FP64 values rounded once), FP32 MFMA, FP32 accumulation */
@@ -236,7 +237,7 @@ const char *pp_strerror(int status);
  * call first discards all earlier records and their events.
  * pp_timing_query(name, &ms, &count) waits for the recorded events of one stage and returns their
  * summed duration in milliseconds and the number of launches.  Stage names: "tables" (per-block
- * phase records), "fwd" (coefficient contraction), "reduce" (split-K sum, scale, energy
+ * phase records), "seeds" (run seeds of the bf16 forward), "fwd" (coefficient contraction), "reduce" (split-K sum, scale, energy
  * partials), "energy" (final energy sum), "prep" (row-form operands), "bwd" (the two gradient
  * contractions, one record each), "final" (per-block partial sums), "build" (store-mode basis
  * tables), "point" (pp_point_field

@@ -107,6 +107,7 @@ int bf16_kh(int Ka) { return (Ka + 63) / 64 * 32; }
 struct Layout {
     size_t tx, ty;                       // bf16 path: per-block phase records
     size_t sxh, sxl, syh, syl;           // store mode: basis tables (kept from the forward to the backward)
+    size_t sdx, sdy;                     // bf16 forward: run seeds of both axes
     size_t part, epart;                  // forward region
     size_t bx, by, gpx, gpy, gpz;        // backward region (gpz: second epilogue of the point field)
     size_t fwd_bytes, bwd_bytes, total;
@@ -132,6 +133,11 @@ Layout layout(const pp_problem &P) {
         if (x3) { L.syl = off; off = align_up(off + by); }
     }
     const size_t common = off;
+    if (is_bf16(P.precision)) {
+        const size_t rows = (size_t)phase_rows(P.n);
+        L.sdx = off; off = align_up(off + (size_t)seed_runs(P.Mu) * rows * sizeof(RunSeed));
+        L.sdy = off; off = align_up(off + (size_t)seed_runs(P.Mp) * rows * sizeof(RunSeed));
+    }
     L.part = off;  off = align_up(off + (size_t)f.splits * MM * f.part_elem);
     L.epart = off; off = align_up(off + (size_t)reduce_scale_blocks(P.Mu, P.Mp) * sizeof(double));
     L.fwd_bytes = off;
@@ -226,21 +232,29 @@ int run_forward(const pp_problem &P, const double *x, const double *y, const dou
     if (is_bf16(P.precision)) {
         const bool x3 = P.precision == PP_BF16X3;
         PhaseRec *tx = (PhaseRec *)(base + L.tx), *ty = (PhaseRec *)(base + L.ty);
+        RunSeed *sx = (RunSeed *)(base + L.sdx), *sy = (RunSeed *)(base + L.sdy);
         { TimedLaunch t(T("tables"), s); err = launch_phase_tables(P.n, x, y, w, h, P.W, P.H, tx, ty, s); }
+        if (err != hipSuccess) return PP_ERR_DEVICE;
+        {
+            TimedLaunch t(T("seeds"), s);
+            err = launch_seed_table(P.n, seed_runs(P.Mu), tx, sx, s);
+            if (err == hipSuccess) err = launch_seed_table(P.n, seed_runs(P.Mp), ty, sy, s);
+        }
         if (err != hipSuccess) return PP_ERR_DEVICE;
         if (P.basis_mode == PP_BASIS_STORE) {
             const StoreTables st = store_tables(P, L, base);
             {
                 TimedLaunch t(T("build"), s);
-                err = launch_build_table(x3, P.n, P.Mu, tx, (unsigned short *)st.xh, (unsigned short *)st.xl, s);
+                err = launch_build_table(x3, P.n, P.Mu, tx, sx, (unsigned short *)st.xh, (unsigned short *)st.xl, s);
                 if (err == hipSuccess)
-                    err = launch_build_table(x3, P.n, P.Mp, ty, (unsigned short *)st.yh, (unsigned short *)st.yl, s);
+                    err = launch_build_table(x3, P.n, P.Mp, ty, sy, (unsigned short *)st.yh, (unsigned short *)st.yl,
+                                             s);
             }
             if (err != hipSuccess) return PP_ERR_DEVICE;
             { TimedLaunch t(T("fwd"), s); err = launch_fwd_bf16_st(f, x3, P.n, P.Mu, P.Mp, st, (float *)part, s); }
         } else {
             TimedLaunch t(T("fwd"), s);
-            err = launch_fwd_bf16(f, x3, P.n, P.Mu, P.Mp, tx, ty, (float *)part, s);
+            err = launch_fwd_bf16(f, x3, P.n, P.Mu, P.Mp, tx, ty, sx, sy, (float *)part, s);
         }
     } else if (P.precision == PP_FP32) {
         TimedLaunch t(T("fwd"), s);

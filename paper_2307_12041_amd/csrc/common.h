@@ -71,20 +71,34 @@ enum RowForm {
 // Per-block phase record of one axis, built once per call (80 bytes): for centre c, size sz and
 // axis length L, ta = c / L and tb = sz / (2L) are the phases of the centre and half size in half
 // turns per unit frequency; (ca, sa) = (cos, sin)(pi ta), c2a = 2 cos(pi ta) = c2ah + c2al, the
-// same for tb, the 32-frequency phasors (ca32, sa32) and (cb32, sb32), and the size itself.
+// same for tb, the 32-frequency phasors (ca32, sa32) and (cb32, sb32), and the size itself.  The
+// four recurrence coefficients share one aligned 16-byte group (one load for the generators).
 struct __attribute__((aligned(16))) PhaseRec {
     double ta, tb;
-    float ca, sa, c2ah, c2al;
-    float cb, sb, c2bh, c2bl;
+    float ca, sa, cb, sb;
+    float c2ah, c2al, c2bh, c2bl;
     float ca32, sa32, cb32, sb32;
     float size, pad0, pad1, pad2;
 };
 static_assert(sizeof(PhaseRec) == 80, "PhaseRec layout");
 
+// Start values of one run of 32 basis frequencies u0 = 32 r .. 32 r + 31 of one block (16 bytes):
+// the two recurrences of the product form S_u = cos(u alpha) * 2 sin(u beta) begin from
+// cf = cos(u0 alpha), cfm = cos((u0 - 1) alpha), sf = 2 sin(u0 beta), sfm = 2 sin((u0 - 1) beta),
+// computed in FP64 and rounded once.  Table layout [run][row] (rows = phase_rows(n), zero past n),
+// so that the 32 blocks of a chunk read one run's seeds from one contiguous 512-byte span.
+struct __attribute__((aligned(16))) RunSeed {
+    float cf, cfm, sf, sfm;
+};
+static_assert(sizeof(RunSeed) == 16, "RunSeed layout");
+
+// Runs of a seed table for M frequencies: whole 256-frequency tiles of 8 runs each.
+inline int seed_runs(int M) { return (M + 255) / 256 * 8; }
+
 // Rows of a phase-record table: n rounded up to whole chunks of 32 blocks, plus two more chunks, all
 // past n zero (an absent block: every basis value vanishes).  The bf16x3 forward fetches the
 // records of the chunk after next without a bounds test.
-inline int64_t phase_rows(int64_t n) { return (n + 31) / 32 * 32 + 64; }
+__host__ __device__ inline int64_t phase_rows(int64_t n) { return (n + 31) / 32 * 32 + 64; }
 
 // One backward contraction of the bf16 path (gx or gy).
 struct BwdAxisBf16 {
@@ -136,8 +150,10 @@ hipError_t launch_rowform_f32(RowForm f, const BwdPlan &pl, int64_t n, const Bwd
 // Phase records of both axes (w, h may be NULL for points: size 0).
 hipError_t launch_phase_tables(int64_t n, const double *x, const double *y, const double *w, const double *h,
                                double W, double H, PhaseRec *tx, PhaseRec *ty, hipStream_t s);
+// Run seeds of one axis from its phase records (runs = seed_runs(M)).
+hipError_t launch_seed_table(int64_t n, int runs, const PhaseRec *tab, RunSeed *seeds, hipStream_t s);
 hipError_t launch_fwd_bf16(const FwdPlan &pl, bool x3, int64_t n, int Mu, int Mp, const PhaseRec *tx,
-                           const PhaseRec *ty, float *part, hipStream_t s);
+                           const PhaseRec *ty, const RunSeed *sx, const RunSeed *sy, float *part, hipStream_t s);
 hipError_t launch_prep_bwd_bf16(RowForm f, const double *a, int Mu, int Mp, double W, double H, int trans, int Np,
                                 int Kh, unsigned short *B, hipStream_t s);
 size_t bwd_bf16_operand_elems(int Np, int Kh);   // bf16 elements of one tiled backward operand
@@ -146,8 +162,8 @@ hipError_t launch_bwd_bf16(RowForm f, bool x3, int64_t n, const BwdAxisBf16 &ax,
 // one axis from its phase records (lo table only for x3); the forward from both axes' tables.
 int64_t store_rows(int64_t n);
 int store_ld(int M);
-hipError_t launch_build_table(bool x3, int64_t n, int M, const PhaseRec *tab, unsigned short *th, unsigned short *tl,
-                              hipStream_t s);
+hipError_t launch_build_table(bool x3, int64_t n, int M, const PhaseRec *tab, const RunSeed *seeds,
+                              unsigned short *th, unsigned short *tl, hipStream_t s);
 hipError_t launch_fwd_bf16_st(const FwdPlan &pl, bool x3, int64_t n, int Mu, int Mp, const StoreTables &t,
                               float *part, hipStream_t s);
 

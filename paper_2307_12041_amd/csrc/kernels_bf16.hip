@@ -19,11 +19,14 @@
 //
 // LDS transpose read ds_read_b64_tr_b16 (per group of 16 lanes): result lane i, element j is
 // element i % 4 of the 64 bits addressed by source lane 4 j + i / 4.
-#include "common.h"
+#include "basis_gen.h"
 
 #include <utility>
 
 namespace pp {
+
+using namespace gen;
+
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -33,32 +36,6 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ double reduce_half_turns(double t) { return t - 2.0 * rint(0.5 * t); }
-
-// sin(pi r), cos(pi r) for |r| <= 1 in fp32: quarter-turn reduction f = r - q/2, |f| <= 1/4, then
-// odd/even polynomials in f^2 (coefficients fitted by csrc/fit_sincospi.py; max error < 9e-8).
-__device__ __forceinline__ void sincospi_seed(float r, float &s, float &c) {
-    const float q = rintf(2.0f * r);
-    const float f = fmaf(-0.5f, q, r);
-    const float x = f * f;
-    const float sp = f * fmaf(x, fmaf(x, fmaf(x, -5.893013400e-01f, 2.549791082e+00f), -5.167708535e+00f),
-                              3.141592649e+00f);
-    const float cp = fmaf(x, fmaf(x, fmaf(x, fmaf(x, 2.314641957e-01f, -1.335062776e+00f), 4.058708069e+00f),
-                                  -4.934802175e+00f), 1.0f);
-    const int iq = (int)q;
-    const bool sw = iq & 1;
-    const float s0 = sw ? cp : sp, c0 = sw ? sp : cp;
-    // quadrant signs: q = 0: (s, c); 1: (c, -s); 2: (-s, -c); 3 (= -1): (-c, s)
-    const unsigned ns = ((unsigned)iq & 2u) << 30, nc = ((unsigned)(iq + 1) & 2u) << 30;
-    s = __builtin_bit_cast(float, __builtin_bit_cast(unsigned, s0) ^ ns);
-    c = __builtin_bit_cast(float, __builtin_bit_cast(unsigned, c0) ^ nc);
-}
-
-// cos/sin of pi*(k*t) for integer k, with the product reduced in FP64 to [-1, 1] half turns.
-__device__ __forceinline__ void seed_phasor(int k, double t, float &c, float &s) {
-    const float r = (float)reduce_half_turns((double)k * t);
-    sincospi_seed(r, s, c);
-}
 
 __device__ __forceinline__ unsigned pack_bf16(float a, float b) {
     bf16x2 v = {(__bf16)a, (__bf16)b};
@@ -83,16 +60,6 @@ __device__ __forceinline__ void split2(float a, float b, unsigned &hi, unsigned 
     lo = split_lo(a, b, hi << 16, hi & 0xffff0000u);
 }
 
-// Three-term recurrence state for cos(k alpha) (or any sinusoid) with a hi/lo coefficient.
-struct Cheb {
-    float f, fm, ch, cl;  // f_k, f_{k-1}, 2cos(theta) = ch + cl
-    __device__ __forceinline__ float next() {
-        const float nx = fmaf(ch, f, fmaf(cl, f, -fm));
-        fm = f;
-        f = nx;
-        return nx;
-    }
-};
 
 }  // namespace
 
@@ -124,6 +91,43 @@ __global__ void k_phase_table(int64_t n, int64_t rows, const double *__restrict_
     r.size = (float)szi;
     r.pad0 = r.pad1 = r.pad2 = 0.0f;
     out[i] = r;
+}
+
+// Run seeds of one axis (see RunSeed in common.h): one thread per row walks the runs, rotating the
+// FP64 phasors of u0 alpha and u0 beta by 32 frequencies per run and reseeding them exactly (FP64
+// reduction and sincospi) every 16 runs; rows n .. rows - 1 get zero seeds (an absent block).
+__global__ void k_seed_table(int64_t n, int64_t rows, int runs, const PhaseRec *__restrict__ tab,
+                             RunSeed *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows) return;
+    if (i >= n) {
+        for (int r = 0; r < runs; ++r) out[(size_t)r * (size_t)rows + (size_t)i] = RunSeed{0.0f, 0.0f, 0.0f, 0.0f};
+        return;
+    }
+    const double ta = tab[i].ta, tb = tab[i].tb;
+    double sa1, ca1, sb1, cb1, sj, cj, sjb, cjb;
+    sincospi(reduce_half_turns(ta), &sa1, &ca1);
+    sincospi(reduce_half_turns(tb), &sb1, &cb1);
+    sincospi(reduce_half_turns(32.0 * ta), &sj, &cj);
+    sincospi(reduce_half_turns(32.0 * tb), &sjb, &cjb);
+    double ca = 1.0, sa = 0.0, cb = 1.0, sb = 0.0;   // phasors of u0 alpha and u0 beta
+    for (int r = 0; r < runs; ++r) {
+        if ((r & 15) == 0) {
+            sincospi(reduce_half_turns((double)(32 * r) * ta), &sa, &ca);
+            sincospi(reduce_half_turns((double)(32 * r) * tb), &sb, &cb);
+        }
+        RunSeed q;
+        q.cf = (float)ca;
+        q.cfm = (float)(ca * ca1 + sa * sa1);           // cos((u0 - 1) alpha)
+        q.sf = (float)(2.0 * sb);
+        q.sfm = (float)(2.0 * (sb * cb1 - cb * sb1));   // 2 sin((u0 - 1) beta)
+        out[(size_t)r * (size_t)rows + (size_t)i] = q;
+        const double ta2 = ca * cj - sa * sj, tb2 = cb * cjb - sb * sjb;
+        sa = sa * cj + ca * sj;
+        ca = ta2;
+        sb = sb * cjb + cb * sjb;
+        cb = tb2;
+    }
 }
 
 namespace {
@@ -168,59 +172,49 @@ __device__ __forceinline__ int fswz_mask(int k) {
 }
 __device__ __forceinline__ int fswz(int k, int seg) { return k * FROW + ((seg ^ fswz_mask(k)) << 4); }
 
-// The fields of a phase record that a generating thread needs, held in registers so that the
-// record can be fetched one phase ahead of its use.
+// What a generating thread needs for one run of 32 frequencies of one block, held in registers so
+// that it can be fetched one phase ahead of its use: the run's seeds (RunSeed) and the block's
+// recurrence coefficients and size.
 struct GenRec {
-    double ta, tb;
-    float ca, sa, c2ah, c2al, cb, sb, c2bh, c2bl, size;
+    RunSeed s;
+    float c2ah, c2al, c2bh, c2bl, size;
 };
 
-__device__ __forceinline__ GenRec load_rec_at(const PhaseRec *__restrict__ tab, int64_t n, int64_t ib) {
+__device__ __forceinline__ GenRec gen_rec_zero() {
     GenRec g;
-    if (ib < n) {
-        const PhaseRec *p = tab + ib;
-        g.ta = p->ta; g.tb = p->tb;
-        g.ca = p->ca; g.sa = p->sa; g.c2ah = p->c2ah; g.c2al = p->c2al;
-        g.cb = p->cb; g.sb = p->sb; g.c2bh = p->c2bh; g.c2bl = p->c2bl;
-        g.size = p->size;
-    } else {
-        // An absent block: every basis value is zero (the sine factor and the size vanish).
-        g.ta = g.tb = 0.0;
-        g.ca = g.sa = g.c2ah = g.c2al = g.cb = g.sb = g.c2bh = g.c2bl = g.size = 0.0f;
-    }
+    g.s = RunSeed{0.0f, 0.0f, 0.0f, 0.0f};
+    g.c2ah = g.c2al = g.c2bh = g.c2bl = g.size = 0.0f;
     return g;
 }
 
-__device__ __forceinline__ GenRec load_rec(const PhaseRec *__restrict__ tab, int64_t n, int64_t chunk, int k) {
-    return load_rec_at(tab, n, chunk * FKB + k);
-}
-
-// The same from a table padded with zero records (phase_rows): no bounds test, so that the fetch
-// issues the same loads on every path (a conditional fetch makes the compiler's later waits for
-// it, and for everything in flight with it, conservative).
-__device__ __forceinline__ GenRec load_rec_padded(const PhaseRec *__restrict__ tab, int64_t chunk, int k) {
-    const PhaseRec *p = tab + (chunk * FKB + k);
+// Run `run` of table row ib (the rows are padded: a row past n holds zero seeds, an absent block).
+__device__ __forceinline__ GenRec load_gen(const PhaseRec *__restrict__ tab, const RunSeed *__restrict__ seeds,
+                                           int64_t rows, int run, int64_t ib) {
     GenRec g;
-    g.ta = p->ta; g.tb = p->tb;
-    g.ca = p->ca; g.sa = p->sa; g.c2ah = p->c2ah; g.c2al = p->c2al;
-    g.cb = p->cb; g.sb = p->sb; g.c2bh = p->c2bh; g.c2bl = p->c2bl;
-    g.size = p->size;
+    g.s = seeds[(size_t)run * (size_t)rows + (size_t)ib];
+    const float4 c = *(const float4 *)&tab[ib].c2ah;
+    g.c2ah = c.x; g.c2al = c.y; g.c2bh = c.z; g.c2bl = c.w;
+    g.size = tab[ib].size;
     return g;
 }
 
-// The basis values S_u (u0 <= u < u0 + 32) of one record (S_0 = size); the same arithmetic as the
-// generating forward (fwd_gen), so stored and regenerated tables agree bit for bit.
+// The same with a bounds test (ib >= n gives an absent block).
+__device__ __forceinline__ GenRec load_gen_at(const PhaseRec *__restrict__ tab, const RunSeed *__restrict__ seeds,
+                                              int64_t rows, int run, int64_t n, int64_t ib) {
+    return ib < n ? load_gen(tab, seeds, rows, run, ib) : gen_rec_zero();
+}
+
+// Start both recurrences of a run (cos(u alpha) and 2 sin(u beta) at u0 and u0 - 1).
+__device__ __forceinline__ void start_run(const GenRec &R, Cheb &ca, Cheb &sb) {
+    ca.f = R.s.cf; ca.fm = R.s.cfm; ca.ch = R.c2ah; ca.cl = R.c2al;
+    sb.f = R.s.sf; sb.fm = R.s.sfm; sb.ch = R.c2bh; sb.cl = R.c2bl;
+}
+
+// The basis values S_u (u0 <= u < u0 + 32) of one run (S_0 = size); the same arithmetic as the
+// generating forwards (fwd_gen, RunStages), so stored and regenerated tables agree bit for bit.
 __device__ __forceinline__ void gen32(const GenRec &R, int u0, float (&v)[32]) {
     Cheb ca, sb;
-    float c0, s0, cb0, sb0;
-    seed_phasor(u0, R.ta, c0, s0);
-    seed_phasor(u0, R.tb, cb0, sb0);
-    ca.f = c0;
-    ca.fm = c0 * R.ca + s0 * R.sa;            // cos((u0 - 1) alpha)
-    ca.ch = R.c2ah; ca.cl = R.c2al;
-    sb.f = 2.0f * sb0;                         // 2 sin(u0 beta); an all-zero record gives 0 throughout
-    sb.fm = 2.0f * (sb0 * R.cb - cb0 * R.sb);  // 2 sin((u0 - 1) beta)
-    sb.ch = R.c2bh; sb.cl = R.c2bl;
+    start_run(R, ca, sb);
     v[0] = ca.f * sb.f;
 #pragma unroll
     for (int j = 1; j < 32; ++j) v[j] = ca.next() * sb.next();
@@ -228,27 +222,13 @@ __device__ __forceinline__ void gen32(const GenRec &R, int u0, float (&v)[32]) {
 }
 
 // 32 consecutive frequencies f0 + 32 r .. + 31 of block k of the chunk, split hi/lo and stored.
-// Thread gt of the generating group handles block k = gt % 32 and run r = gt / 32, so the 16 lanes
-// of each store share the segment and cover 16 consecutive rows.
+// Thread gt of the generating group handles block k = gt % 32 and run r = gt / 32 (R: that run's
+// seeds), so the 16 lanes of each store share the segment and cover 16 consecutive rows.
 template <bool X3>
 __device__ __forceinline__ void fwd_gen(const GenRec &R, int f0, char *arr_h, char *arr_l, int gt) {
     const int k = gt & 31, r = gt >> 5;
-    const int u0 = f0 + 32 * r;
-    Cheb ca, sb;
-    float c0, s0, cb0, sb0;
-    seed_phasor(u0, R.ta, c0, s0);
-    seed_phasor(u0, R.tb, cb0, sb0);
-    ca.f = c0;
-    ca.fm = c0 * R.ca + s0 * R.sa;            // cos((u0 - 1) alpha)
-    ca.ch = R.c2ah; ca.cl = R.c2al;
-    sb.f = 2.0f * sb0;                         // 2 sin(u0 beta); an all-zero record gives 0 throughout
-    sb.fm = 2.0f * (sb0 * R.cb - cb0 * R.sb);  // 2 sin((u0 - 1) beta)
-    sb.ch = R.c2bh; sb.cl = R.c2bl;
     float v[32];
-    v[0] = ca.f * sb.f;
-#pragma unroll
-    for (int j = 1; j < 32; ++j) v[j] = ca.next() * sb.next();
-    if (u0 == 0) v[0] = R.size;
+    gen32(R, f0 + 32 * r, v);
     // Split and store one 16-byte segment (8 frequencies) at a time.
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
@@ -382,11 +362,13 @@ __device__ __forceinline__ void fwd_mma(const char *buf, const OpBase &ox, const
 
 template <bool X3>
 __global__ __launch_bounds__(512) void k_fwd_bf16(int64_t n, int Mu, int Mp, const PhaseRec *__restrict__ tx,
-                                                  const PhaseRec *__restrict__ ty, float *__restrict__ part,
+                                                  const PhaseRec *__restrict__ ty, const RunSeed *__restrict__ sx,
+                                                  const RunSeed *__restrict__ sy, float *__restrict__ part,
                                                   int tiles_p, int64_t chunks, int64_t chunks_per_split) {
     __shared__ __attribute__((aligned(16))) char smem[2 * FBUF];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int group = wave >> 2, gt = tid & 255;
+    const int64_t rows = phase_rows(n);
     const int tu0 = (int)(blockIdx.x / tiles_p) * FT, tp0 = (int)(blockIdx.x % tiles_p) * FT;
     const int wu = 128 * (wave >> 2), wp = 64 * (wave & 3);
     const int64_t c_begin = (int64_t)blockIdx.y * chunks_per_split;
@@ -405,14 +387,16 @@ __global__ __launch_bounds__(512) void k_fwd_bf16(int64_t n, int Mu, int Mp, con
 
     // Group 0 generates the X tile (u), group 1 the Y tile (p).
     const PhaseRec *tab = group == 0 ? tx : ty;
+    const RunSeed *seeds = group == 0 ? sx : sy;
     const int f0 = group == 0 ? tu0 : tp0;
     const int aoff = group == 0 ? 0 : 2 * FARR;
-    const int kk = gt & 31;
+    const int kk = gt & 31, run = f0 / 32 + (gt >> 5);
+    auto load_rec = [&](int64_t chunk) { return load_gen_at(tab, seeds, rows, run, n, chunk * FKB + kk); };
     GenRec rec;
     if (c_begin < c_end) {
-        rec = load_rec(tab, n, c_begin, kk);
+        rec = load_rec(c_begin);
         fwd_gen<X3>(rec, f0, smem + aoff, smem + aoff + FARR, gt);
-        if (group == 1 && c_begin + 1 < c_end) rec = load_rec(tab, n, c_begin + 1, kk);
+        if (group == 1 && c_begin + 1 < c_end) rec = load_rec(c_begin + 1);
     }
     __syncthreads();
     for (int64_t c = c_begin; c < c_end; ++c) {
@@ -426,7 +410,7 @@ __global__ __launch_bounds__(512) void k_fwd_bf16(int64_t n, int Mu, int Mp, con
         // second contraction runs alone.)
         if (group == 0) {
             // fetch the next chunk's records before the MFMAs; they are used in phase 2
-            if (more) rec = load_rec(tab, n, c + 1, kk);
+            if (more) rec = load_rec(c + 1);
             fwd_mma<X3>(cur, ox, oy, acc);
         } else {
             if (more) fwd_gen<X3>(rec, f0, nxt + aoff, nxt + aoff + FARR, gt);
@@ -436,7 +420,7 @@ __global__ __launch_bounds__(512) void k_fwd_bf16(int64_t n, int Mu, int Mp, con
             if (more) fwd_gen<X3>(rec, f0, nxt + aoff, nxt + aoff + FARR, gt);
         } else {
             // fetch the records of the chunk after next before the MFMAs
-            if (c + 2 < c_end) rec = load_rec(tab, n, c + 2, kk);
+            if (c + 2 < c_end) rec = load_rec(c + 2);
             fwd_mma<X3>(cur, ox, oy, acc);
         }
         lds_barrier();
@@ -468,14 +452,13 @@ struct FwdOps1 {
     bf16x8 ah[4], al[4], bh[4], bl[4];
 };
 
-// One run of 32 basis values generated in stages, one stage per MFMA slot of the chunk, so that its
-// VALU work spreads evenly over the matrix work.  Stage map: 0-7 seeds (FP64 reduction, the
-// sincospi polynomials, quadrant fix-up, recurrence set-up and the first two values); 8-37 one
-// value each; the hi/lo split of value pair q in two halves at stages 2q + 8 and 2q + 9; the four
-// 16-byte segments (hi and lo) stored at stages 16, 24, 32, 40.
+// One run of 32 basis values generated in stages spread over the MFMA slots of the chunk, so that
+// its VALU work interleaves with the matrix work.  Stage map: 0 starts both recurrences from the
+// run's seeds and gives the first two values; 1-30 one value each; the hi/lo split of value pair q
+// in two halves at stages 2q + 1 and 2q + 2; the four 16-byte segments (hi and lo) stored at stages
+// 8, 16, 24, 32.
 struct RunStages {
     GenRec R;
-    float ra, rb, qa, qb, fa, fb, xa, xb, spa, spb, cpa, cpb;
     Cheb C, S;
     float v[32];
     unsigned h[16], l[16], hah[16], hbh[16];
@@ -485,40 +468,17 @@ struct RunStages {
     __device__ __forceinline__ void stage(int u0, char *arr_h, char *arr_l, int k, int r) {
         constexpr int st = ST;
         if constexpr (st == 0) {
-            ra = (float)reduce_half_turns((double)u0 * R.ta);
-            rb = (float)reduce_half_turns((double)u0 * R.tb);
-        } else if constexpr (st == 1) {
-            qa = rintf(2.0f * ra); fa = fmaf(-0.5f, qa, ra); xa = fa * fa;
-            qb = rintf(2.0f * rb); fb = fmaf(-0.5f, qb, rb); xb = fb * fb;
-        } else if constexpr (st == 2) {
-            spa = sin_poly(fa, xa);
-        } else if constexpr (st == 3) {
-            spb = sin_poly(fb, xb);
-        } else if constexpr (st == 4) {
-            cpa = cos_poly(xa);
-        } else if constexpr (st == 5) {
-            cpb = cos_poly(xb);
-        } else if constexpr (st == 6) {
-            quadrant(qa, spa, cpa);   // spa, cpa <- sin, cos of pi ra
-            quadrant(qb, spb, cpb);
-        } else if constexpr (st == 7) {
-            C.f = cpa;
-            C.fm = cpa * R.ca + spa * R.sa;              // cos((u0 - 1) alpha)
-            C.ch = R.c2ah; C.cl = R.c2al;
-            S.f = 2.0f * spb;                            // 2 sin(u0 beta)
-            S.fm = 2.0f * (spb * R.cb - cpb * R.sb);     // 2 sin((u0 - 1) beta)
-            S.ch = R.c2bh; S.cl = R.c2bl;
+            start_run(R, C, S);
             v[0] = C.f * S.f;
             if (u0 == 0) v[0] = R.size;
             v[1] = C.next() * S.next();
-        } else if constexpr (st < 38) {
-            constexpr int jv = st - 6;
-            v[jv] = C.next() * S.next();
+        } else if constexpr (st <= 30) {
+            v[st + 1] = C.next() * S.next();
         }
-        // split of pair q: hi at stage 2q + 8, lo at 2q + 9
-        if constexpr (st >= 8 && st < 40) {
-            constexpr int q = (st - 8) >> 1;
-            if constexpr (((st - 8) & 1) == 0) {
+        // split of pair q: hi at stage 2q + 1, lo at 2q + 2
+        if constexpr (st >= 1 && st <= 32) {
+            constexpr int q = (st - 1) >> 1;
+            if constexpr (((st - 1) & 1) == 0) {
                 h[q] = pack_bf16(v[2 * q], v[2 * q + 1]);
                 asm("" : "+v"(h[q]));   // keeps the shift below on h (else it re-converts v[2q] alone)
                 hah[q] = h[q] << 16;
@@ -527,32 +487,25 @@ struct RunStages {
                 l[q] = split_lo(v[2 * q], v[2 * q + 1], hah[q], hbh[q]);
             }
         }
-        if constexpr (st >= 16 && st <= 40 && (st & 7) == 0) {
-            constexpr int m = (st - 16) >> 3;
+        if constexpr (st >= 8 && (st & 7) == 0) {
+            constexpr int m = (st - 8) >> 3;
             *(u32x4 *)(arr_h + fswz(k, 4 * r + m)) = u32x4{h[4 * m], h[4 * m + 1], h[4 * m + 2], h[4 * m + 3]};
             *(u32x4 *)(arr_l + fswz(k, 4 * r + m)) = u32x4{l[4 * m], l[4 * m + 1], l[4 * m + 2], l[4 * m + 3]};
         }
     }
-    static constexpr int kStages = 41;
-
-    // The pieces of sincospi_seed, separated so that they can be spread over slots.
-    static __device__ __forceinline__ float sin_poly(float f, float x) {
-        return f * fmaf(x, fmaf(x, fmaf(x, -5.893013400e-01f, 2.549791082e+00f), -5.167708535e+00f),
-                        3.141592649e+00f);
-    }
-    static __device__ __forceinline__ float cos_poly(float x) {
-        return fmaf(x, fmaf(x, fmaf(x, fmaf(x, 2.314641957e-01f, -1.335062776e+00f), 4.058708069e+00f),
-                            -4.934802175e+00f), 1.0f);
-    }
-    static __device__ __forceinline__ void quadrant(float q, float &sp, float &cp) {
-        const int iq = (int)q;
-        const bool sw = iq & 1;
-        const float s0 = sw ? cp : sp, c0 = sw ? sp : cp;
-        const unsigned ns = ((unsigned)iq & 2u) << 30, nc = ((unsigned)(iq + 1) & 2u) << 30;
-        sp = __builtin_bit_cast(float, __builtin_bit_cast(unsigned, s0) ^ ns);
-        cp = __builtin_bit_cast(float, __builtin_bit_cast(unsigned, c0) ^ nc);
-    }
+    static constexpr int kStages = 33;
 };
+
+// Slots of the run stages in a chunk of 96 MFMA slots: the X run's stages spread over slots 0-40,
+// the Y run's over slots 41-81 (stage s at slot offset floor(41 s / 33)), so that no slot holds more
+// than one stage and the last store precedes the chunk's barrier after slot 81.
+constexpr int kRunSlots = 41;
+constexpr int run_stage_at(int slot) {
+    for (int st = 0; st < RunStages::kStages; ++st)
+        if (st * kRunSlots / RunStages::kStages == slot) return st;
+    return -1;
+}
+static_assert((RunStages::kStages - 1) * kRunSlots / RunStages::kStages < kRunSlots, "stage plan");
 
 // LDS layout of the one-wave forward: the hi and lo arrays of both buffers interleaved,
 // [Xh0 Xh1 Xl0 Xl1 | Yh0 Yh1 Yl0 Yl1], 16 KB each, so that with one lane base for the X arrays
@@ -613,14 +566,14 @@ __device__ __forceinline__ void fwd1_slot(Fwd1Ctx &c) {
     if constexpr (I < 48) fwd1_mfma<I>(c.o0, c.acc);
     else fwd1_mfma<I - 48>(c.o1, c.acc);
     if constexpr (I >= 12 && I < 44 && (I & 1) == 0) fwd1_read<1, (I - 12) / 2, B>(c.smem, c.ox, c.oy, c.o1);
-    constexpr int Y0 = RunStages::kStages;   // the Y run's stages follow the X run's
-    if constexpr (I < Y0) c.gx.template stage<I>(c.ux, c.smem + F1_XH(N), c.smem + F1_XL(N), c.k, c.r);
-    if constexpr (I >= Y0 && I < 2 * Y0)
-        c.gy.template stage<I - Y0>(c.uy, c.smem + F1_YH(N), c.smem + F1_YL(N), c.k, c.r);
-    // The generator's last store is in slot 2 Y0 - 1 = 81: after the barrier the next chunk's tiles
-    // are complete (its first step-0 operands are read in the following slots, well before the
+    constexpr int XS = I < kRunSlots ? run_stage_at(I) : -1;
+    constexpr int YS = I >= kRunSlots && I < 2 * kRunSlots ? run_stage_at(I - kRunSlots) : -1;
+    if constexpr (XS >= 0) c.gx.template stage<XS>(c.ux, c.smem + F1_XH(N), c.smem + F1_XL(N), c.k, c.r);
+    if constexpr (YS >= 0) c.gy.template stage<YS>(c.uy, c.smem + F1_YH(N), c.smem + F1_YL(N), c.k, c.r);
+    // The generator's last store is in slot 81 at the latest: after the barrier the next chunk's
+    // tiles are complete (its first step-0 operands are read in the following slots, well before the
     // next chunk's first MFMA) and this chunk's buffer is free for the next chunk's generator.
-    static_assert(2 * RunStages::kStages - 1 == 81, "slot plan");
+    static_assert(2 * kRunSlots - 1 <= 81, "slot plan");
     if constexpr (I == 81) lds_barrier();
     if constexpr (I >= 84 && I <= 88) fwd1_reads0_at<I, N>(c, std::make_integer_sequence<int, 5>{});
     if constexpr (I <= 10) fwd1_reads0_at<I, B>(c, std::make_integer_sequence<int, 16>{});
@@ -635,8 +588,8 @@ __device__ __forceinline__ void fwd1_slots(Fwd1Ctx &c, std::integer_sequence<int
 // One chunk: contract buffer B into acc while generating the next chunk's X and Y runs into
 // buffer 1 - B.  96 slots of one MFMA each; the step-0 operands are read in slots 84-88 of the
 // previous chunk and 0-10 of this one, the step-1 operands one every two slots from slot 12; the
-// X run's stages occupy slots 0-40, the Y run's slots 41-81; the chunk's one barrier follows
-// slot 81.
+// X run's stages spread over slots 0-40, the Y run's over slots 41-81; the chunk's one barrier
+// follows slot 81.
 template <int B>
 __device__ __forceinline__ void fwd1_chunk(char *smem, const OpBase &ox, const OpBase &oy, f32x16 (&acc)[4][4],
                                            RunStages &gx, RunStages &gy, FwdOps1 &o0, int ux, int uy, int k,
@@ -647,10 +600,12 @@ __device__ __forceinline__ void fwd1_chunk(char *smem, const OpBase &ox, const O
 }
 
 __global__ __launch_bounds__(256) void k_fwd1_bf16(int64_t n, int Mu, int Mp, const PhaseRec *__restrict__ tx,
-                                                   const PhaseRec *__restrict__ ty, float *__restrict__ part,
+                                                   const PhaseRec *__restrict__ ty, const RunSeed *__restrict__ sx,
+                                                   const RunSeed *__restrict__ sy, float *__restrict__ part,
                                                    int tiles_p, int64_t chunks, int64_t chunks_per_split) {
     __shared__ __attribute__((aligned(16))) char smem[2 * FBUF];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t rows = phase_rows(n);
     const int tu0 = (int)(blockIdx.x / tiles_p) * FT, tp0 = (int)(blockIdx.x % tiles_p) * FT;
     const int wu = 128 * (wave >> 1), wp = 128 * (wave & 1);
     const int64_t c_begin = (int64_t)blockIdx.y * chunks_per_split;
@@ -674,17 +629,21 @@ __global__ __launch_bounds__(256) void k_fwd1_bf16(int64_t n, int Mu, int Mp, co
     // Thread tid generates block k = tid % 32 of each chunk, frequencies 32 r .. + 31 of the tile.
     const int kk = tid & 31, rr = tid >> 5;
     const int ux = tu0 + 32 * rr, uy = tp0 + 32 * rr;
+    const int runx = ux / 32, runy = uy / 32;
+    // the records of chunk `ch` (the tables are padded with zero rows past the last chunk + 2)
+    auto recx = [&](int64_t ch) { return load_gen(tx, sx, rows, runx, ch * FKB + kk); };
+    auto recy = [&](int64_t ch) { return load_gen(ty, sy, rows, runy, ch * FKB + kk); };
     if (c_begin < c_end) {
-        fwd_gen<true>(load_rec_padded(tx, c_begin, kk), tu0, smem + F1_XH(0), smem + F1_XL(0), tid);
-        fwd_gen<true>(load_rec_padded(ty, c_begin, kk), tp0, smem + F1_YH(0), smem + F1_YL(0), tid);
+        fwd_gen<true>(recx(c_begin), tu0, smem + F1_XH(0), smem + F1_XL(0), tid);
+        fwd_gen<true>(recy(c_begin), tp0, smem + F1_YH(0), smem + F1_YL(0), tid);
     }
     // Two record sets alternate: the chunk at even offset from c_begin generates from set B and
     // fetches the records of the chunk after next into set A, the chunk at odd offset the reverse.
     // (Past the range: zero records or records of the next split, generated into the idle buffer
     // and never read.)
     RunStages gxA, gyA, gxB, gyB;
-    gxB.R = load_rec_padded(tx, c_begin + 1, kk);
-    gyB.R = load_rec_padded(ty, c_begin + 1, kk);
+    gxB.R = recx(c_begin + 1);
+    gyB.R = recy(c_begin + 1);
     lds_barrier();
     FwdOps1 o0;
     fwd1_read<0, 0, 0>(smem, ox, oy, o0);
@@ -697,11 +656,11 @@ __global__ __launch_bounds__(256) void k_fwd1_bf16(int64_t n, int Mu, int Mp, co
     asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
     int64_t c = c_begin;
     for (; c + 1 < c_end; c += 2) {
-        gxA.R = load_rec_padded(tx, c + 2, kk);
-        gyA.R = load_rec_padded(ty, c + 2, kk);
+        gxA.R = recx(c + 2);
+        gyA.R = recy(c + 2);
         fwd1_chunk<0>(smem, ox, oy, acc, gxB, gyB, o0, ux, uy, kk, rr);
-        gxB.R = load_rec_padded(tx, c + 3, kk);
-        gyB.R = load_rec_padded(ty, c + 3, kk);
+        gxB.R = recx(c + 3);
+        gyB.R = recy(c + 3);
         fwd1_chunk<1>(smem, ox, oy, acc, gxA, gyA, o0, ux, uy, kk, rr);
     }
     if (c < c_end) fwd1_chunk<0>(smem, ox, oy, acc, gxB, gyB, o0, ux, uy, kk, rr);
@@ -960,7 +919,8 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
     // E = -2 sin(nn alpha) sin(nn beta) of the epilogue axis, stepped by 32 columns.
     // The E2 epilogue (if any) shares the phasors with E1.
     constexpr bool DUAL = E2 >= 0;
-    float rs[16], rs2[16];
+    // each lane sums its 8 columns of a row in FP32; the 32 lanes of the row add in FP64
+    double rs[16], rs2[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int row = 8 * (r >> 2) + 4 * h + (r & 3);
@@ -989,10 +949,10 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
         rs[r] = sum;
         rs2[r] = sum2;
     }
-    auto reduce_store = [&](float (&x)[16], double *__restrict__ gp) {
+    auto reduce_store = [&](double (&x)[16], double *__restrict__ gp) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            float v = x[r];
+            double v = x[r];
             v += __shfl_xor(v, 1);
             v += __shfl_xor(v, 2);
             v += __shfl_xor(v, 4);
@@ -1004,7 +964,7 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int64_t ibe = i0 + 8 * (r >> 2) + 4 * h + (r & 3);
-                if (ibe < n) gp[(size_t)ntile * (size_t)n + (size_t)ibe] = (double)x[r];
+                if (ibe < n) gp[(size_t)ntile * (size_t)n + (size_t)ibe] = x[r];
             }
         }
     };
@@ -1210,54 +1170,6 @@ __device__ __forceinline__ void bwd1_gen_all(Bwd1Ctx<KA> &c, std::integer_sequen
     (bwd1_gen<KA, 1, FIRST0, T>(c), ...);
 }
 
-// Epilogue generator of one row (block) along the N axis: the recurrences of the epilogue kinds
-// (sines or cosines of nn alpha, sine of nn beta), reseeded every 32 columns from phasors that
-// advance by the 32-frequency rotations of the phase record.
-template <int E1, int E2>
-struct EGen {
-    static constexpr bool DUAL = E2 >= 0;
-    // chain 0 (alpha): cosine for SINDIFF and COS, sine for COSDIFF and WSIN; chain 1: sine of
-    // alpha for the dual COS + WSIN epilogue, else sine of beta (SINDIFF, COSDIFF)
-    static constexpr bool C0_COS = E1 == RUN_SINDIFF || E1 == RUN_COS;
-    static constexpr bool HAS_C1 = DUAL || E1 == RUN_SINDIFF || E1 == RUN_COSDIFF;
-    static constexpr bool C1_BETA = !DUAL;
-    Cheb c0, c1;
-    float pac, pas, pbc, pbs;     // phasors of alpha and beta at the current 32-column start
-    float ca1, sa1, cb1, sb1;     // cos, sin of alpha and beta (one-column step)
-    float ja_c, ja_s, jb_c, jb_s; // 32-column rotations
-    float size, pil;
-
-    __device__ __forceinline__ void init(const PhaseRec &R, int nn0, float pil_) {
-        seed_phasor(nn0, R.ta, pac, pas);
-        seed_phasor(nn0, R.tb, pbc, pbs);
-        ca1 = R.ca; sa1 = R.sa; cb1 = R.cb; sb1 = R.sb;
-        ja_c = R.ca32; ja_s = R.sa32; jb_c = R.cb32; jb_s = R.sb32;
-        c0.ch = R.c2ah; c0.cl = R.c2al;
-        if constexpr (C1_BETA) { c1.ch = R.c2bh; c1.cl = R.c2bl; }
-        else { c1.ch = R.c2ah; c1.cl = R.c2al; }
-        size = R.size;
-        pil = pil_;
-    }
-    // chain values at the current start column nn and nn - 1
-    __device__ __forceinline__ void seed() {
-        if constexpr (C0_COS) { c0.f = pac; c0.fm = pac * ca1 + pas * sa1; }
-        else { c0.f = pas; c0.fm = pas * ca1 - pac * sa1; }
-        if constexpr (HAS_C1) {
-            if constexpr (C1_BETA) { c1.f = pbs; c1.fm = pbs * cb1 - pbc * sb1; }
-            else { c1.f = pas; c1.fm = pas * ca1 - pac * sa1; }
-        }
-    }
-    __device__ __forceinline__ void rotate() {
-        const float t = pac * ja_c - pas * ja_s;
-        pas = pas * ja_c + pac * ja_s;
-        pac = t;
-        if constexpr (C1_BETA && HAS_C1) {
-            const float tb = pbc * jb_c - pbs * jb_s;
-            pbs = pbs * jb_c + pbc * jb_s;
-            pbc = tb;
-        }
-    }
-};
 
 template <int KA, int E1, int E2>
 __global__ __launch_bounds__(256) void k_bwd1_bf16(int64_t n, BwdAxisBf16 ax) {
@@ -1330,7 +1242,9 @@ __global__ __launch_bounds__(256) void k_bwd1_bf16(int64_t n, BwdAxisBf16 ax) {
     EGen<E1, E2> eg;
     if (rvalid) eg.init(ax.te[ibr], n0, ax.pil);
     else eg.init(PhaseRec{}, n0, ax.pil);
-    float sum = 0.0f, sum2 = 0.0f, g00 = 0.0f;
+    // Each 32-column run is summed in FP32, the runs of the tile in FP64.
+    double sum = 0.0, sum2 = 0.0;
+    float g00 = 0.0f;
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
 #pragma unroll
@@ -1346,31 +1260,34 @@ __global__ __launch_bounds__(256) void k_bwd1_bf16(int64_t n, BwdAxisBf16 ax) {
         if (b == 0) g00 = gv[0];
         eg.seed();
         float nnp = (float)(n0 + 32 * b) * eg.pil;   // nn pi / L for the w sin kind
+        float run = 0.0f, run2 = 0.0f;
 #pragma unroll
         for (int k = 0; k < 32; ++k) {
             if constexpr (E1 == RUN_COSDIFF || E1 == RUN_SINDIFF) {
-                sum = fmaf(eg.c0.f * eg.c1.f, gv[k], sum);
+                run = fmaf(eg.c0.f * eg.c1.f, gv[k], run);
             } else if constexpr (E1 == RUN_COS) {
-                sum = fmaf(eg.c0.f, gv[k], sum);
+                run = fmaf(eg.c0.f, gv[k], run);
             } else {   // RUN_WSIN
-                sum = fmaf(nnp * eg.c0.f, gv[k], sum);
+                run = fmaf(nnp * eg.c0.f, gv[k], run);
             }
-            if constexpr (EGen<E1, E2>::DUAL) sum2 = fmaf(nnp * eg.c1.f, gv[k], sum2);   // w sin of alpha
+            if constexpr (EGen<E1, E2>::DUAL) run2 = fmaf(nnp * eg.c1.f, gv[k], run2);   // w sin of alpha
             if constexpr (E1 == RUN_WSIN || EGen<E1, E2>::DUAL) nnp += eg.pil;
             eg.c0.next();
             if constexpr (EGen<E1, E2>::HAS_C1) eg.c1.next();
         }
+        sum += (double)run;
+        if constexpr (EGen<E1, E2>::DUAL) sum2 += (double)run2;
         eg.rotate();
     }
     // kind factors: -2 sin sin (cosine differences), 2 cos sin (sine differences, nn = 0: the size)
-    if constexpr (E1 == RUN_COSDIFF) sum *= -2.0f;
+    if constexpr (E1 == RUN_COSDIFF) sum *= -2.0;
     if constexpr (E1 == RUN_SINDIFF) {
-        sum *= 2.0f;
-        if (n0 == 0) sum = fmaf(eg.size, g00, sum);   // 2 cos sin vanishes at nn = 0
+        sum *= 2.0;
+        if (n0 == 0) sum += (double)eg.size * (double)g00;   // 2 cos sin vanishes at nn = 0
     }
     if (rvalid) {
-        ax.gpart[(size_t)ntile * (size_t)n + (size_t)ibr] = (double)sum;
-        if constexpr (EGen<E1, E2>::DUAL) ax.gpart2[(size_t)ntile * (size_t)n + (size_t)ibr] = (double)sum2;
+        ax.gpart[(size_t)ntile * (size_t)n + (size_t)ibr] = sum;
+        if constexpr (EGen<E1, E2>::DUAL) ax.gpart2[(size_t)ntile * (size_t)n + (size_t)ibr] = sum2;
     }
 }
 
@@ -1424,6 +1341,7 @@ __global__ void k_prep_bwd_bf16(int form, const double *__restrict__ a, int Mu, 
 template <bool X3>
 __global__ __launch_bounds__(256) void k_build_table(int64_t n, int64_t nrows, int ld,
                                                      const PhaseRec *__restrict__ tab,
+                                                     const RunSeed *__restrict__ seeds,
                                                      unsigned short *__restrict__ th,
                                                      unsigned short *__restrict__ tl) {
     const int runs = ld >> 5;
@@ -1431,7 +1349,7 @@ __global__ __launch_bounds__(256) void k_build_table(int64_t n, int64_t nrows, i
     if (idx >= nrows * runs) return;
     const int64_t ib = idx / runs;
     const int r = (int)(idx % runs);
-    const GenRec R = load_rec_at(tab, n, ib);
+    const GenRec R = load_gen_at(tab, seeds, phase_rows(n), r, n, ib);
     float v[32];
     gen32(R, 32 * r, v);
     unsigned short *dh = th + (size_t)ib * (size_t)ld + 32 * r;
@@ -1543,15 +1461,22 @@ hipError_t launch_phase_tables(int64_t n, const double *x, const double *y, cons
     return hipGetLastError();
 }
 
+hipError_t launch_seed_table(int64_t n, int runs, const PhaseRec *tab, RunSeed *seeds, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int64_t rows = phase_rows(n);
+    hipLaunchKernelGGL(k_seed_table, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, n, rows, runs, tab, seeds);
+    return hipGetLastError();
+}
+
 hipError_t launch_fwd_bf16(const FwdPlan &pl, bool x3, int64_t n, int Mu, int Mp, const PhaseRec *tx,
-                           const PhaseRec *ty, float *part, hipStream_t s) {
+                           const PhaseRec *ty, const RunSeed *sx, const RunSeed *sy, float *part, hipStream_t s) {
     if (pl.tu != FT || pl.tp != FT || pl.kb != FKB) return hipErrorInvalidValue;
     dim3 grid(pl.tiles_u * pl.tiles_p, pl.splits);
     if (x3)
-        hipLaunchKernelGGL(k_fwd1_bf16, grid, dim3(256), 0, s, n, Mu, Mp, tx, ty, part, pl.tiles_p, pl.chunks,
+        hipLaunchKernelGGL(k_fwd1_bf16, grid, dim3(256), 0, s, n, Mu, Mp, tx, ty, sx, sy, part, pl.tiles_p, pl.chunks,
                            pl.chunks_per_split);
     else
-        hipLaunchKernelGGL(k_fwd_bf16<false>, grid, dim3(512), 0, s, n, Mu, Mp, tx, ty, part, pl.tiles_p,
+        hipLaunchKernelGGL(k_fwd_bf16<false>, grid, dim3(512), 0, s, n, Mu, Mp, tx, ty, sx, sy, part, pl.tiles_p,
                            pl.chunks, pl.chunks_per_split);
     return hipGetLastError();
 }
@@ -1602,15 +1527,15 @@ hipError_t launch_bwd_bf16(RowForm f, bool x3, int64_t n, const BwdAxisBf16 &ax,
 int64_t store_rows(int64_t n) { return (n + 255) / 256 * 256; }
 int store_ld(int M) { return (M + 255) / 256 * 256; }
 
-hipError_t launch_build_table(bool x3, int64_t n, int M, const PhaseRec *tab, unsigned short *th, unsigned short *tl,
-                              hipStream_t s) {
+hipError_t launch_build_table(bool x3, int64_t n, int M, const PhaseRec *tab, const RunSeed *seeds,
+                              unsigned short *th, unsigned short *tl, hipStream_t s) {
     const int64_t rows = store_rows(n);
     const int ld = store_ld(M);
     const int64_t total = rows * (ld / 32);
     if (total == 0) return hipSuccess;
     const unsigned g = (unsigned)((total + 255) / 256);
-    if (x3) hipLaunchKernelGGL(k_build_table<true>, dim3(g), dim3(256), 0, s, n, rows, ld, tab, th, tl);
-    else hipLaunchKernelGGL(k_build_table<false>, dim3(g), dim3(256), 0, s, n, rows, ld, tab, th, tl);
+    if (x3) hipLaunchKernelGGL(k_build_table<true>, dim3(g), dim3(256), 0, s, n, rows, ld, tab, seeds, th, tl);
+    else hipLaunchKernelGGL(k_build_table<false>, dim3(g), dim3(256), 0, s, n, rows, ld, tab, seeds, th, tl);
     return hipGetLastError();
 }
 
