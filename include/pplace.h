@@ -69,8 +69,15 @@ typedef enum pp_precision {
     PP_FP32 = 1,    /* FP32 tables (FP64 values rounded once), FP32 MFMA, FP32 accumulation */
     PP_BF16 = 2,    /* BF16 tables, BF16 MFMA, FP32 accumulation */
     PP_BF16X3 = 3,  /* BF16 hi/lo split of FP32 tables: hi*hi + hi*lo + lo*hi, FP32 accumulation */
-    PP_FP8 = 4,     /* reserved: PP_ERR_UNSUPPORTED */
-    PP_FP8X3 = 5    /* reserved: PP_ERR_UNSUPPORTED */
+    PP_FP8 = 4,     /* OCP e4m3 operands with E8M0 scales (v_mfma_scale_f32_32x32x64_f8f6f4), FP32
+                       accumulation: the generated basis carried as v * 2^7 (scale 2^-7), the block sizes
+                       (u = 0 row, p = 0 column) scaled by the largest size of each 64-block chunk, the
+                       gradient's coefficient operand scaled per column and 64-value chunk; the k = 0 term
+                       of the gradient contraction added exactly in FP32.  Relative error ~3e-2. */
+    PP_FP8X3 = 5    /* e4m3 hi/lo split of the same operands: hi*hi + lo*hi + hi*lo; relative error ~1e-3
+                       (3 mantissa bits per part).  FP8 and FP8X3 serve pp_coeffs, pp_energy,
+                       pp_energy_static and pp_field in recompute mode; pp_point_field,
+                       pp_block_potential and the stored basis give PP_ERR_UNSUPPORTED. */
 } pp_precision;
 
 /* Where the basis values (the sine-difference factors of the Sec. III-A closed forms) live.

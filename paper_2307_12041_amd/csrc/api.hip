@@ -28,9 +28,13 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 bool supported_precision(int prec) {
-    return prec == PP_FP64 || prec == PP_FP32 || prec == PP_BF16 || prec == PP_BF16X3;
+    return prec == PP_FP64 || prec == PP_FP32 || prec == PP_BF16 || prec == PP_BF16X3 || prec == PP_FP8 ||
+           prec == PP_FP8X3;
 }
 bool is_bf16(int prec) { return prec == PP_BF16 || prec == PP_BF16X3; }
+bool is_fp8(int prec) { return prec == PP_FP8 || prec == PP_FP8X3; }
+// Operand types whose basis is generated from per-block phase records and run seeds.
+bool is_gen(int prec) { return is_bf16(prec) || is_fp8(prec); }
 
 bool grids_fit(const pp_problem &P);
 
@@ -61,6 +65,8 @@ FwdPlan fwd_plan(const pp_problem &P) {
     FwdPlan pl{};
     if (is_bf16(P.precision)) {
         pl.tu = 256; pl.tp = 256; pl.kb = 32;
+    } else if (is_fp8(P.precision)) {
+        pl.tu = 256; pl.tp = 256; pl.kb = 64;
     } else if (P.Mu >= 128 && P.Mp >= 128) {
         pl.tu = 128; pl.tp = 128; pl.kb = 32;
     } else {
@@ -86,7 +92,7 @@ FwdPlan fwd_plan(const pp_problem &P) {
 
 BwdPlan bwd_plan(const pp_problem &P) {
     BwdPlan pl{};
-    if (is_bf16(P.precision)) {
+    if (is_gen(P.precision)) {
         pl.tb = 256; pl.tn = 256; pl.kk = 32;
     } else {
         pl.tb = 128; pl.tn = 128; pl.kk = 32;
@@ -110,6 +116,7 @@ struct Layout {
     size_t sdx, sdy;                     // bf16 forward: run seeds of both axes
     size_t part, epart;                  // forward region
     size_t bx, by, gpx, gpy, gpz;        // backward region (gpz: second epilogue of the point field)
+    size_t b0x, b0y;                     // fp8 gradient: exact k = 0 rows of the operands
     size_t fwd_bytes, bwd_bytes, total;
 };
 
@@ -119,7 +126,7 @@ Layout layout(const pp_problem &P) {
     const size_t MM = (size_t)P.Mu * (size_t)P.Mp;
     Layout L{};
     size_t off = 0;
-    if (is_bf16(P.precision)) {
+    if (is_gen(P.precision)) {
         L.tx = off; off = align_up(off + (size_t)phase_rows(P.n) * sizeof(PhaseRec));
         L.ty = off; off = align_up(off + (size_t)phase_rows(P.n) * sizeof(PhaseRec));
     }
@@ -133,7 +140,7 @@ Layout layout(const pp_problem &P) {
         if (x3) { L.syl = off; off = align_up(off + by); }
     }
     const size_t common = off;
-    if (is_bf16(P.precision)) {
+    if (is_gen(P.precision)) {
         const size_t rows = (size_t)phase_rows(P.n);
         L.sdx = off; off = align_up(off + (size_t)seed_runs(P.Mu) * rows * sizeof(RunSeed));
         L.sdy = off; off = align_up(off + (size_t)seed_runs(P.Mp) * rows * sizeof(RunSeed));
@@ -147,6 +154,11 @@ Layout layout(const pp_problem &P) {
         const size_t ey = bwd_bf16_operand_elems(b.tiles_ny * 256, bf16_kh(P.Mu)) * 2;  // gy operand, bytes
         L.bx = off;  off = align_up(off + ex);
         L.by = off;  off = align_up(off + ey);
+    } else if (is_fp8(P.precision)) {
+        L.bx = off;  off = align_up(off + fp8_operand_bytes(b.tiles_nx * 256, bf16_kh(P.Mp)));
+        L.by = off;  off = align_up(off + fp8_operand_bytes(b.tiles_ny * 256, bf16_kh(P.Mu)));
+        L.b0x = off; off = align_up(off + (size_t)b.tiles_nx * 256 * sizeof(float));
+        L.b0y = off; off = align_up(off + (size_t)b.tiles_ny * 256 * sizeof(float));
     } else {
         L.bx = off;  off = align_up(off + MM * b.bmat_elem);
         L.by = off;  off = align_up(off + MM * b.bmat_elem);
@@ -182,9 +194,9 @@ bool grids_fit(const pp_problem &P) {
     const uint64_t n = (uint64_t)P.n, MM = (uint64_t)P.Mu * (uint64_t)P.Mp;
     const FwdPlan f = fwd_plan(P);
     const BwdPlan b = bwd_plan(P);
-    const bool bf = is_bf16(P.precision);
+    const bool bf = is_gen(P.precision);
     const uint64_t tiles = (uint64_t)f.tiles_u * (uint64_t)f.tiles_p;
-    bool ok = dim_ok(tiles, bf && P.precision == PP_BF16 ? 512 : 256) && (uint64_t)f.splits <= 0xffffffffull;
+    bool ok = dim_ok(tiles, P.precision == PP_BF16 ? 512 : 256) && (uint64_t)f.splits <= 0xffffffffull;
     ok = ok && dim_ok((uint64_t)reduce_scale_blocks(P.Mu, P.Mp), 256);   // split-K reduction
     ok = ok && dim_ok(cdiv(MM, 256), 256);                                 // row-form operands (FP64 / FP32)
     ok = ok && dim_ok(cdiv(n, 256), 256);                                  // final per-block sums
@@ -229,8 +241,8 @@ int run_forward(const pp_problem &P, const double *x, const double *y, const dou
     void *part = base + L.part;
     double *epart = (double *)(base + L.epart);
     hipError_t err;
-    if (is_bf16(P.precision)) {
-        const bool x3 = P.precision == PP_BF16X3;
+    if (is_gen(P.precision)) {
+        const bool x3 = P.precision == PP_BF16X3 || P.precision == PP_FP8X3;
         PhaseRec *tx = (PhaseRec *)(base + L.tx), *ty = (PhaseRec *)(base + L.ty);
         RunSeed *sx = (RunSeed *)(base + L.sdx), *sy = (RunSeed *)(base + L.sdy);
         { TimedLaunch t(T("tables"), s); err = launch_phase_tables(P.n, x, y, w, h, P.W, P.H, tx, ty, s); }
@@ -252,6 +264,9 @@ int run_forward(const pp_problem &P, const double *x, const double *y, const dou
             }
             if (err != hipSuccess) return PP_ERR_DEVICE;
             { TimedLaunch t(T("fwd"), s); err = launch_fwd_bf16_st(f, x3, P.n, P.Mu, P.Mp, st, (float *)part, s); }
+        } else if (is_fp8(P.precision)) {
+            TimedLaunch t(T("fwd"), s);
+            err = launch_fwd_fp8(f, x3, P.n, P.Mu, P.Mp, tx, ty, sx, sy, (float *)part, s);
         } else {
             TimedLaunch t(T("fwd"), s);
             err = launch_fwd_bf16(f, x3, P.n, P.Mu, P.Mp, tx, ty, sx, sy, (float *)part, s);
@@ -372,6 +387,30 @@ int pp_field(const pp_problem *P, const double *x, const double *y, const double
     const BwdPlan b = bwd_plan(*P);
     char *base = (char *)ws;
     double *gpx = (double *)(base + L.gpx), *gpy = (double *)(base + L.gpy);
+    if (is_fp8(P->precision)) {
+        const bool x3 = P->precision == PP_FP8X3;
+        PhaseRec *tx = (PhaseRec *)(base + L.tx), *ty = (PhaseRec *)(base + L.ty);
+        unsigned char *bxt = (unsigned char *)(base + L.bx), *byt = (unsigned char *)(base + L.by);
+        float *b0x = (float *)(base + L.b0x), *b0y = (float *)(base + L.b0y);
+        const int khx = bf16_kh(P->Mp), khy = bf16_kh(P->Mu);
+        { TimedLaunch t("tables", s); if (launch_phase_tables(P->n, x, y, w, h, P->W, P->H, tx, ty, s) != hipSuccess) return PP_ERR_DEVICE; }
+        {
+            TimedLaunch t("prep", s);
+            if (launch_prep_bwd_fp8(ROW_FIELD, a, P->Mu, P->Mp, P->W, P->H, 0, b.tiles_nx * 256, khx, bxt, b0x, s) !=
+                hipSuccess)
+                return PP_ERR_DEVICE;
+            if (launch_prep_bwd_fp8(ROW_FIELD, a, P->Mu, P->Mp, P->W, P->H, 1, b.tiles_ny * 256, khy, byt, b0y, s) !=
+                hipSuccess)
+                return PP_ERR_DEVICE;
+        }
+        // gx: K = p (basis of y), epilogue over u (x);  gy: K = u (basis of x), epilogue over p (y).
+        const BwdAxisFp8 axx{ty, tx, P->Mp, P->Mu, khx, bxt, b0x, gpx, nullptr, 0.0f};
+        const BwdAxisFp8 axy{tx, ty, P->Mu, P->Mp, khy, byt, b0y, gpy, nullptr, 0.0f};
+        { TimedLaunch t("bwd", s); if (launch_bwd_fp8(ROW_FIELD, x3, P->n, axx, s) != hipSuccess) return PP_ERR_DEVICE; }
+        { TimedLaunch t("bwd", s); if (launch_bwd_fp8(ROW_FIELD, x3, P->n, axy, s) != hipSuccess) return PP_ERR_DEVICE; }
+        { TimedLaunch t("final", s); if (launch_bwd_final(gpx, b.tiles_nx, gpy, b.tiles_ny, P->n, dE, gx, gy, s) != hipSuccess) return PP_ERR_DEVICE; }
+        return PP_OK;
+    }
     if (is_bf16(P->precision)) {
         const bool x3 = P->precision == PP_BF16X3;
         PhaseRec *tx = (PhaseRec *)(base + L.tx), *ty = (PhaseRec *)(base + L.ty);
@@ -420,7 +459,7 @@ int pp_point_field(const pp_problem *P, const double *px, const double *py, cons
                    double *xix, double *xiy, void *ws, size_t ws_bytes, void *stream) {
     int st = validate_problem(P);
     if (st != PP_OK) return st;
-    if (P->basis_mode != PP_BASIS_RECOMPUTE) return PP_ERR_UNSUPPORTED;
+    if (P->basis_mode != PP_BASIS_RECOMPUTE || is_fp8(P->precision)) return PP_ERR_UNSUPPORTED;
     if (P->n > 0 && (!px || !py || !aligned8(px) || !aligned8(py))) return PP_ERR_ARG;
     if (!a || !aligned8(a)) return PP_ERR_ARG;
     if ((psi && !aligned8(psi)) || (xix && !aligned8(xix)) || (xiy && !aligned8(xiy))) return PP_ERR_ARG;
@@ -496,7 +535,7 @@ int pp_block_potential(const pp_problem *P, const double *x, const double *y, co
                        const double *a, double *N, void *ws, size_t ws_bytes, void *stream) {
     int st = validate_problem(P);
     if (st != PP_OK) return st;
-    if (P->basis_mode != PP_BASIS_RECOMPUTE) return PP_ERR_UNSUPPORTED;
+    if (P->basis_mode != PP_BASIS_RECOMPUTE || is_fp8(P->precision)) return PP_ERR_UNSUPPORTED;
     if ((st = validate_blocks(P, x, y, w, h)) != PP_OK) return st;
     if (!a || !aligned8(a)) return PP_ERR_ARG;
     if (P->n > 0 && (!N || !aligned8(N))) return PP_ERR_ARG;

@@ -117,6 +117,19 @@ struct BwdAxisBf16 {
     float pil;
 };
 
+// One gradient contraction of the fp8 paths (gx or gy): as BwdAxisBf16 without store mode; B is the
+// prepared e4m3 operand (k_prep_bwd_fp8 layout), B0 its exact k = 0 row (one float per N column).
+struct BwdAxisFp8 {
+    const PhaseRec *ta;          // K-axis records
+    const PhaseRec *te;          // epilogue-axis records
+    int Ka, Nb, Kh;              // K frequencies, N frequencies, K half length (multiple of 32)
+    const unsigned char *B;
+    const float *B0;
+    double *gpart;               // out: [tiles_n][n]
+    double *gpart2;              // unused by the gradient (one epilogue)
+    float pil;
+};
+
 // Store-mode basis tables of both axes (bf16 hi and lo, row-major [block][frequency]).
 struct StoreTables {
     const unsigned short *xh, *xl, *yh, *yl;
@@ -166,6 +179,16 @@ hipError_t launch_build_table(bool x3, int64_t n, int M, const PhaseRec *tab, co
                               unsigned short *th, unsigned short *tl, hipStream_t s);
 hipError_t launch_fwd_bf16_st(const FwdPlan &pl, bool x3, int64_t n, int Mu, int Mp, const StoreTables &t,
                               float *part, hipStream_t s);
+
+// FP8 operand types (e4m3 on the scaled f8f6f4 MFMA): the coefficient contraction (chunks of 64
+// blocks, 256 x 256 tiles, FP32 partials), the prepared gradient operand (bytes of one axis's
+// tiles: fp8_operand_bytes; B0: Np floats) and the gradient contraction (ROW_FIELD only).
+hipError_t launch_fwd_fp8(const FwdPlan &pl, bool x3, int64_t n, int Mu, int Mp, const PhaseRec *tx,
+                          const PhaseRec *ty, const RunSeed *sx, const RunSeed *sy, float *part, hipStream_t s);
+size_t fp8_operand_bytes(int Np, int Kh);
+hipError_t launch_prep_bwd_fp8(RowForm f, const double *a, int Mu, int Mp, double W, double H, int trans, int Np,
+                               int Kh, unsigned char *B, float *B0, hipStream_t s);
+hipError_t launch_bwd_fp8(RowForm f, bool x3, int64_t n, const BwdAxisFp8 &ax, hipStream_t s);
 
 // Sum split-K partials (FP64 or FP32), scale, write a, per-block energy partials.
 hipError_t launch_reduce_scale(const void *part, bool part_f32, int splits, int Mu, int Mp, double W,

@@ -144,8 +144,14 @@ def test_evaluation_entry_points_validate_before_launch(lib):
 
 
 def test_unsupported_modes_reported(lib):
-    st, _ = ws_size(lib, P(precision=4))
-    assert st == -3
+    for prec in (4, 5):                  # the fp8 types run in recompute mode only
+        assert ws_size(lib, P(precision=prec))[0] == 0
+        assert ws_size(lib, P(precision=prec, basis_mode=1))[0] == -3
+    fake = ctypes.c_void_p(1 << 20)
+    q = P(precision=5)
+    st, need = ws_size(lib, q)
+    assert lib.pp_point_field(ctypes.byref(q), fake, fake, fake, fake, fake, fake, fake, need, None) == -3
+    assert lib.pp_block_potential(ctypes.byref(q), fake, fake, fake, fake, fake, fake, fake, need, None) == -3
     for prec in (0, 1):                  # stored tables exist for the bf16 operand types only
         st, _ = ws_size(lib, P(precision=prec, basis_mode=1))
         assert st == -3
@@ -246,7 +252,7 @@ def _documented_status(W, H, n, Mu, Mp, prec, basis):
     if (not ok(W) or not ok(H) or n < 0 or n > 2 ** 31 - 512 or not 1 <= Mu <= 65536 or not 1 <= Mp <= 65536
             or Mu * Mp > 2 ** 30 or not 0 <= prec <= 5 or basis not in (0, 1)):
         return -1
-    if prec in (4, 5) or (basis == 1 and prec not in (2, 3)):
+    if basis == 1 and prec not in (2, 3):
         return -3
     if basis == 1 and -(-n // 256) * -(-max(Mu, Mp) // 256) >= 2 ** 21:
         return -1
