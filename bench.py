@@ -26,8 +26,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "block·freq² pairs/s for energy+forces, BF16-split vs FP64 plain, at rel err"
-PEAK_TFLOPS = {"bf16x3": 2500.0, "bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}   # MI355X dense matrix peaks
-MFMA_MULT = {"bf16x3": 3, "bf16": 1, "fp32": 1, "fp64": 1}   # executed MFMA products per algorithmic one
+PEAK_TFLOPS = {"bf16x3": 2500.0, "bf16": 2500.0, "fp8x3": 5000.0, "fp8": 5000.0, "fp32": 157.3,
+               "fp64": 78.6}   # MI355X dense matrix peaks of each operand type
+MFMA_MULT = {"bf16x3": 3, "bf16": 1, "fp8x3": 3, "fp8": 1, "fp32": 1, "fp64": 1}   # executed products per algorithmic one
+DTYPE = {"bf16x3": "bf16", "bf16": "bf16", "fp8x3": "fp8", "fp8": "fp8", "fp32": "f32", "fp64": "f64"}
 
 
 def log(*a):
@@ -37,6 +39,48 @@ def log(*a):
 def rel(a, b):
     nb = float(np.linalg.norm(np.ravel(b)))
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b))) / (nb if nb > 0 else 1.0)
+
+
+def tile_rel_max(a, b, t=64):
+    """Largest relative error over t x t tiles of two coefficient arrays (each tile judged against its own
+    norm, so that no tile is hidden by the larger low-frequency coefficients)."""
+    worst = 0.0
+    for u0 in range(0, b.shape[0], t):
+        for p0 in range(0, b.shape[1], t):
+            nb = float(np.linalg.norm(b[u0:u0 + t, p0:p0 + t]))
+            if nb > 0:
+                worst = max(worst, float(np.linalg.norm(a[u0:u0 + t, p0:p0 + t] - b[u0:u0 + t, p0:p0 + t])) / nb)
+    return worst
+
+
+def row_tile_rel_max(g, gr, t=256):
+    """Largest relative error over tiles of t consecutive blocks of a per-block output."""
+    worst = 0.0
+    for i0 in range(0, gr.shape[0], t):
+        nb = float(np.linalg.norm(gr[i0:i0 + t]))
+        if nb > 0:
+            worst = max(worst, float(np.linalg.norm(g[i0:i0 + t] - gr[i0:i0 + t])) / nb)
+    return worst
+
+
+def errors_vs(ref, out):
+    """Errors of one run's (E, a, gx, gy) against a reference run on the same workload."""
+    E, a, gx, gy = (v.cpu().numpy() for v in out)
+    Er, ar, gxr, gyr = (v.cpu().numpy() for v in ref)
+    g, gr = np.stack([gx, gy], axis=1), np.stack([gxr, gyr], axis=1)
+    return {"E": abs(float(E) - float(Er)) / abs(float(Er)), "a": rel(a, ar), "a_tile64_max": tile_rel_max(a, ar),
+            "g": rel(g, gr), "g_tile256_max": row_tile_rel_max(g, gr),
+            "g_max_block": float(np.max(np.hypot(gx - gxr, gy - gyr)) / np.max(np.hypot(gxr, gyr)))}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 # The sources that build the bf16 contraction kernels and their launches (the kernels whose HBM
@@ -66,6 +110,18 @@ def measured_traffic(workload, precision, stage):
         return None
     st = rec.get("stages", {}).get(stage)
     return None if st is None else st.get("hbm_bytes_per_launch")
+
+
+def measured_mfma(workload, precision):
+    """Counter-measured MFMA utilisation of the contractions from the committed rocprofv3 summary
+    (profiles/mfma_<precision>_<workload>.json), or None if absent or taken on other sources."""
+    path = os.path.join(ROOT, "profiles", f"mfma_{precision}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return rec.get("kernels")
 
 
 def timed_steps(pp, torch, t, wl, prec, steps, warmup, ws, positions=None, basis="recompute"):
@@ -105,12 +161,14 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", type=int, default=4, help="workload index in workloads.CONFIGS")
-    ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "bf16", "fp32", "fp64"])
+    ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "bf16", "fp8x3", "fp8", "fp32", "fp64"])
     ap.add_argument("--basis", default="recompute", choices=["recompute", "store"],
                     help="basis tables regenerated on chip, or built in HBM once per step")
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--fp32-steps", type=int, default=2, help="steps of the FP32 path on the same workload (0: skip)")
+    ap.add_argument("--fp8-steps", type=int, default=3, help="steps of the FP8X3 and FP8 paths on the same workload "
+                                                             "(0: skip)")
     ap.add_argument("--bins", type=int, default=-1,
                     help="bins per axis of the Sec. III-D bin-scheme comparison leg (-1: the workload's truncation "
                          "when Mu = Mp; 0: skip)")
@@ -142,7 +200,7 @@ def main():
     pairs = wl.pairs
     log(f"[bench] workload {wl.name}: n={wl.n} Mu={wl.Mu} Mp={wl.Mp} pairs/step={pairs:.3e}")
     t = [torch.as_tensor(v, device=dev) for v in wl.arrays()]
-    need = max([pp.workspace_size(wl.W, wl.H, wl.n, wl.Mu, wl.Mp, precision=p) for p in ("fp32", "fp64")]
+    need = max([pp.workspace_size(wl.W, wl.H, wl.n, wl.Mu, wl.Mp, precision=p) for p in ("fp32", "fp64", "fp8x3")]
                + [pp.workspace_size(wl.W, wl.H, wl.n, wl.Mu, wl.Mp, precision=args.precision, basis=args.basis)])
     ws = torch.empty(need, dtype=torch.uint8, device=dev)
     log(f"[bench] workspace {need / 2**20:.1f} MiB")
@@ -187,17 +245,22 @@ def main():
     if args.precision in ("fp64", "fp32"):
         T = "double" if args.precision == "fp64" else "float"
         kernel_name = {"fwd": f"k_fwd_mat<{T}>", "bwd": f"k_bwd_mat<{T}>"}[dom]
+    if args.precision in ("fp8x3", "fp8"):
+        X = "x3" if args.precision == "fp8x3" else "plain"
+        kernel_name = {"fwd": f"k_fwd_fp8<{X}> (coefficient contraction)",
+                       "bwd": f"k_bwd_fp8<{X}> (gradient contraction, gx and gy launches)"}[dom]
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": measured_traffic(wl.name, args.precision, dom),
                 "kernel": kernel_name, "avg_launch_ms": round(avg_ms, 3), "launches_per_step": stages[dom][1] // args.steps,
                 "algorithmic_flops_per_launch": alg_flops,
                 "executed_mfma_tflops": round(achieved * MFMA_MULT[args.precision], 2),
-                "executed_mfma_frac": round(achieved * MFMA_MULT[args.precision] / peak, 4)}
+                "executed_mfma_frac": round(achieved * MFMA_MULT[args.precision] / peak, 4),
+                "mfma_counters": measured_mfma(wl.name, args.precision)}
 
     out = {"metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None,
-           "dtype": {"bf16x3": "bf16", "bf16": "bf16", "fp32": "f32", "fp64": "f64"}[args.precision],
+           "dtype": DTYPE[args.precision],
            "data": "synthetic",
            "config": {"workload": wl.name + ("_jittered" if args.jitter else ""), "n_blocks": wl.n, "Mu": wl.Mu,
                       "Mp": wl.Mp, "W": wl.W, "H": wl.H, "precision": args.precision, "basis": args.basis,
@@ -223,12 +286,30 @@ def main():
                              "steps": args.fp32_steps,
                              "stages_ms_per_step": {k: round(v[0] / args.fp32_steps, 3) for k, v in st32.items()}}
         if ref is not None:
-            E32, a32, gx32, gy32 = (v.cpu().numpy() for v in r32)
-            E64, a64, gx64, gy64 = (v.cpu().numpy() for v in ref)
-            out["fp32_plain"]["rel_err_vs_fp64_gpu"] = {
-                "E": abs(float(E32) - float(E64)) / abs(float(E64)), "a": rel(a32, a64),
-                "g": rel(np.concatenate([gx32, gy32]), np.concatenate([gx64, gy64]))}
+            out["fp32_plain"]["rel_err_vs_fp64_gpu"] = errors_vs(ref, r32)
         out["speedup_vs_fp32"] = value / v32
+
+    fp8_runs = {}
+    if args.fp8_steps > 0 and args.precision not in ("fp8x3", "fp8"):
+        # The FP8 operand types (e4m3 on the scaled f8f6f4 MFMA) on the same workload: time, stages,
+        # the gradient contraction's share of the fp8 matrix peak, and the error against FP64.
+        out["fp8"] = {}
+        for p8 in ("fp8x3", "fp8"):
+            dt8, st8, r8 = timed_steps(pp, torch, t, wl, p8, args.fp8_steps, 1, ws)
+            v8 = pairs * args.fp8_steps / dt8
+            fp8_runs[p8] = r8
+            bwd_ms = st8["bwd"][0] / st8["bwd"][1]
+            rec = {"value": v8, "unit": "pairs/s", "ms_per_step": dt8 / args.fp8_steps * 1e3, "steps": args.fp8_steps,
+                   "stages_ms_per_step": {k: round(v[0] / args.fp8_steps, 3) for k, v in st8.items()},
+                   "bwd_launch_ms": round(bwd_ms, 3),
+                   "bwd_frac_of_fp8_peak": round(2.0 * pairs / (bwd_ms * 1e-3) / 1e12 / PEAK_TFLOPS[p8], 4),
+                   "speedup_vs_" + args.precision: v8 / value}
+            if ref is not None:
+                rec["rel_err_vs_fp64_gpu"] = errors_vs(ref, r8)
+            out["fp8"][p8] = rec
+            log(f"[bench] {p8}: {dt8 / args.fp8_steps * 1e3:.1f} ms/step, {v8:.4e} pairs/s; stages "
+                + ", ".join(f"{k}={v[0] / v[1]:.2f}ms x{v[1] // args.fp8_steps}" for k, v in st8.items())
+                + (f"; vs fp64 {rec['rel_err_vs_fp64_gpu']}" if ref is not None else ""))
 
     if args.eval_precision != "none":
         # The evaluation rows: psi and xi at every block centre (two contractions: psi and xi_x share
@@ -296,6 +377,8 @@ def main():
         gdir = np.concatenate([g_dir[0].cpu().numpy(), g_dir[1].cpu().numpy()])
         bins = {"m": m_bins, "M": Mb, "density_ms": td, "coeffs_ms": tcf, "field_ms": tf, "interp_ms": ti,
                 "total_ms": td + tcf + tf + ti,
+                "transforms": "dense FP64 GEMMs against cos/sin tables (O(m^3) per transform), not the FFT of "
+                              "Sec. III-D; the cost is that of this comparison path",
                 "transform_gemm_tflops_fp64": round(gemm_flops / ((tcf + tf) * 1e-3) / 1e12, 2),
                 "compared_with": dir_name,
                 "coeffs_rel_diff": rel(abn, adn),
@@ -310,33 +393,48 @@ def main():
             f"psi {bins['psi_rel_diff_at_bin_centres']:.3e}, xi {bins['xi_rel_diff_at_bin_centres']:.3e}, "
             f"block gradient {bins['block_gradient_rel_diff']:.3e}")
 
-    if not args.no_accuracy:
-        import oracle
-        acc = {}
-        rng = np.random.default_rng(12345)
-        us = np.concatenate([[1, 0, 1, 2, 0], rng.integers(0, wl.Mu, 59)])
-        ps = np.concatenate([[0, 1, 1, 0, 2], rng.integers(0, wl.Mp, 59)])
-        t0 = time.perf_counter()
-        ao, _ = oracle.coeffs_sampled(wl.W, wl.H, *wl.arrays(), us, ps)
-        acc["oracle_sample"] = f"{len(us)} coefficients a_up over all {wl.n} blocks, FP64 oracle"
-        a_np = a.cpu().numpy()
-        acc["a_sampled_vs_oracle"] = rel(a_np[us, ps], ao)
-        log(f"[bench] oracle coefficient sample in {time.perf_counter() - t0:.1f} s")
-        if ref is not None:
-            E64, a64, gx64, gy64 = (v.cpu().numpy() for v in ref)
-            acc["fp64_a_sampled_vs_oracle"] = rel(a64[us, ps], ao)
-            acc["E_vs_fp64_gpu"] = abs(float(E.cpu()) - float(E64)) / abs(float(E64))
-            acc["a_vs_fp64_gpu"] = rel(a_np, a64)
-            g = np.concatenate([gx.cpu().numpy(), gy.cpu().numpy()])
-            g64 = np.concatenate([gx64, gy64])
-            acc["g_vs_fp64_gpu"] = rel(g, g64)
-            acc["g_max_block_vs_fp64_gpu"] = float(np.max(np.hypot(gx.cpu().numpy() - gx64, gy.cpu().numpy() - gy64))
-                                                   / np.max(np.hypot(gx64, gy64)))
-        out["rel_err"] = acc
-        log(f"[bench] rel err {acc}")
+    # Accuracy against the FP64 path of the GPU (every element; per 64 x 64 coefficient tile and per
+    # 256-block gradient tile as well, so that no tile hides behind the large low frequencies).
+    if not args.no_accuracy and ref is not None:
+        acc = errors_vs(ref, (E, a, gx, gy))
+        out["rel_err"] = {"vs_fp64_gpu": acc}
+        log(f"[bench] rel err vs fp64 GPU {acc}")
 
     if not args.no_cpu_baseline:
+        # The CPU-baseline leg: the FP64 oracle on the host, timed on a bounded sample of the workload,
+        # and (unless --no-accuracy) the oracle's direct sums of sampled coefficients, three in every
+        # 256 x 256 tile, against which the GPU's coefficients are stated one by one (each scaled by
+        # f_up sum_i |S'_iu T'_ip|, the magnitude that bounds the rounding of its sum).
         import oracle
+        if not args.no_accuracy:
+            rng = np.random.default_rng(12345)
+            us, ps = [], []
+            for u0 in range(0, wl.Mu, 256):
+                for p0 in range(0, wl.Mp, 256):
+                    for _ in range(3):
+                        u, p = int(rng.integers(u0, min(u0 + 256, wl.Mu))), int(rng.integers(p0, min(p0 + 256, wl.Mp)))
+                        if u or p:
+                            us.append(u)
+                            ps.append(p)
+            us, ps = np.array(us), np.array(ps)
+            t0 = time.perf_counter()
+            ao, _, Rabs = oracle.coeffs_sampled_full(wl.W, wl.H, *wl.arrays(), us, ps)
+            fac = oracle.coef_factors(wl.W, wl.H, wl.Mu, wl.Mp)[us, ps]
+            log(f"[bench] oracle coefficient samples in {time.perf_counter() - t0:.1f} s")
+            den = np.abs(fac) * Rabs
+            runs = {args.precision: (E, a, gx, gy)}
+            if ref is not None:
+                runs["fp64"] = ref
+            runs.update(fp8_runs)
+            vs = {}
+            for name, r in runs.items():
+                an = r[1].cpu().numpy()[us, ps]
+                e = np.abs(an - ao) / np.where(den > 0, den, 1.0)
+                vs[name] = {"relative_norm": rel(an, ao), "scaled_max": float(e.max()), "scaled_median": float(np.median(e))}
+            out.setdefault("rel_err", {})["sampled_coeffs_vs_oracle"] = {
+                "sample": f"{len(us)} coefficients, three in every 256 x 256 tile, each a direct FP64 oracle sum over "
+                          f"all {wl.n} blocks; scaled error |a - a*| / (f_up sum_i |S'_iu T'_ip|)", **vs}
+            log(f"[bench] sampled coefficients vs oracle {vs}")
         rng = np.random.default_rng(777)
         idx = np.sort(rng.choice(wl.n, args.cpu_sample, replace=False))
         xs, ys, wsz, hs = (v[idx] for v in wl.arrays())
@@ -346,11 +444,12 @@ def main():
         tc = time.perf_counter() - t0
         cp = args.cpu_sample * wl.Mu * wl.Mp
         out["cpu_baseline"] = {"value": cp / tc, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
+                               "cpu_model": cpu_model(),
                                "sample": f"energy + gradient of {args.cpu_sample} blocks drawn (seeded) from the "
                                          f"{wl.n}-block workload at the full {wl.Mu}x{wl.Mp} truncation, FP64 "
                                          f"direct summation; {tc:.1f} s",
                                "seconds": tc}
-        log(f"[bench] oracle: {tc:.1f} s for {cp:.3e} pairs on {oracle.num_threads()} threads")
+        log(f"[bench] oracle: {tc:.1f} s for {cp:.3e} pairs on {oracle.num_threads()} threads ({cpu_model()})")
         # one core, beside the paper's single-threaded setting: a smaller sample of the same work
         threads = oracle.num_threads()
         k1 = max(1, args.cpu_sample // 30)
