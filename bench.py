@@ -83,18 +83,21 @@ def cpu_model():
     return "unknown"
 
 
-# The sources that build the bf16 contraction kernels and their launches (the kernels whose HBM
-# traffic profiles/traffic_* records).
-TRAFFIC_SOURCES = ("api.hip", "common.h", "basis_gen.h", "kernels_bf16.hip", "kernels_common.hip")
+# The sources that build each precision's contraction kernels and their launches: a committed counter
+# summary (profiles/traffic_*, profiles/mfma_*) is used only while these files are unchanged.
+COMMON_SOURCES = ("api.hip", "common.h", "basis_gen.h", "kernels_common.hip")
+KERNEL_SOURCES = {"bf16x3": ("kernels_bf16.hip",), "bf16": ("kernels_bf16.hip",),
+                  "fp8x3": ("kernels_bf16.hip", "kernels_fp8.hip"), "fp8": ("kernels_bf16.hip", "kernels_fp8.hip"),
+                  "fp64": ("kernels_f64.hip",), "fp32": ("kernels_f64.hip",)}
 
 
-def kernel_source_hash():
-    """sha256 of the sources of the measured kernels; traffic figures are reported only for the
+def kernel_source_hash(precision="bf16x3"):
+    """sha256 of the sources of one precision's kernels; counter figures are reported only for the
     kernels they were taken on."""
     import hashlib
     d = os.path.join(ROOT, "paper_2307_12041_amd", "csrc")
     hs = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
+    for f in COMMON_SOURCES + KERNEL_SOURCES[precision]:
         hs.update(open(os.path.join(d, f), "rb").read())
     return hs.hexdigest()
 
@@ -106,7 +109,7 @@ def measured_traffic(workload, precision, stage):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("kernel_source_sha256") != kernel_source_hash():
+    if rec.get("kernel_source_sha256") != kernel_source_hash(precision):
         return None
     st = rec.get("stages", {}).get(stage)
     return None if st is None else st.get("hbm_bytes_per_launch")
@@ -119,7 +122,7 @@ def measured_mfma(workload, precision):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("kernel_source_sha256") != kernel_source_hash():
+    if rec.get("kernel_source_sha256") != kernel_source_hash(precision):
         return None
     return rec.get("kernels")
 
@@ -275,7 +278,8 @@ def main():
         log(f"[bench] fp64 plain: {dt64 / args.fp64_steps * 1e3:.1f} ms/step, {v64:.4e} pairs/s")
         out["fp64_plain"] = {"value": v64, "unit": "pairs/s", "ms_per_step": dt64 / args.fp64_steps * 1e3,
                              "steps": args.fp64_steps,
-                             "stages_ms_per_step": {k: round(v[0] / args.fp64_steps, 3) for k, v in st64.items()}}
+                             "stages_ms_per_step": {k: round(v[0] / args.fp64_steps, 3) for k, v in st64.items()},
+                             "mfma_counters": measured_mfma(wl.name, "fp64")}
         out["speedup_vs_fp64_plain"] = value / v64
 
     if args.fp32_steps > 0 and args.precision != "fp32":
@@ -303,7 +307,9 @@ def main():
                    "stages_ms_per_step": {k: round(v[0] / args.fp8_steps, 3) for k, v in st8.items()},
                    "bwd_launch_ms": round(bwd_ms, 3),
                    "bwd_frac_of_fp8_peak": round(2.0 * pairs / (bwd_ms * 1e-3) / 1e12 / PEAK_TFLOPS[p8], 4),
-                   "speedup_vs_" + args.precision: v8 / value}
+                   "speedup_vs_" + args.precision: v8 / value,
+                   "mfma_counters": measured_mfma(wl.name, p8), "traffic": {
+                       st: measured_traffic(wl.name, p8, st) for st in ("fwd", "bwd")}}
             if ref is not None:
                 rec["rel_err_vs_fp64_gpu"] = errors_vs(ref, r8)
             out["fp8"][p8] = rec
