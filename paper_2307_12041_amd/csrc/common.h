@@ -100,6 +100,17 @@ inline int seed_runs(int M) { return (M + 255) / 256 * 8; }
 // records of the chunk after next without a bounds test.
 __host__ __device__ inline int64_t phase_rows(int64_t n) { return (n + 31) / 32 * 32 + 64; }
 
+// The (output tile, block split) of a forward workgroup on a grid of (tiles, splits).  Workgroups
+// go to the 8 XCDs round-robin by linear id; taking ids in XCD-major order gives each XCD a
+// contiguous run of splits, so the workgroups that read one split's per-block records (every tile
+// of it) share that XCD's L2 instead of fetching the records once per XCD.
+__device__ inline void fwd_tile_split(int &tile, int64_t &split) {
+    const unsigned g = gridDim.x * gridDim.y, l = blockIdx.y * gridDim.x + blockIdx.x;
+    const unsigned id = (g % 8u == 0u) ? (l % 8u) * (g / 8u) + l / 8u : l;
+    tile = (int)(id % gridDim.x);
+    split = (int64_t)(id / gridDim.x);
+}
+
 // One backward contraction of the bf16 path (gx or gy).
 struct BwdAxisBf16 {
     const PhaseRec *ta;          // K-axis records (basis generated along K)

@@ -217,7 +217,7 @@ __device__ __forceinline__ void gen32(const GenRec &R, int u0, float (&v)[32]) {
     start_run(R, ca, sb);
     v[0] = ca.f * sb.f;
 #pragma unroll
-    for (int j = 1; j < 32; ++j) v[j] = ca.next() * sb.next();
+    for (int j = 1; j < 32; ++j) v[j] = ca.next1() * sb.next();
     if (u0 == 0) v[0] = R.size;
 }
 
@@ -369,9 +369,12 @@ __global__ __launch_bounds__(512) void k_fwd_bf16(int64_t n, int Mu, int Mp, con
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int group = wave >> 2, gt = tid & 255;
     const int64_t rows = phase_rows(n);
-    const int tu0 = (int)(blockIdx.x / tiles_p) * FT, tp0 = (int)(blockIdx.x % tiles_p) * FT;
+    int tile;
+    int64_t split;
+    fwd_tile_split(tile, split);
+    const int tu0 = (tile / tiles_p) * FT, tp0 = (tile % tiles_p) * FT;
     const int wu = 128 * (wave >> 2), wp = 64 * (wave & 3);
-    const int64_t c_begin = (int64_t)blockIdx.y * chunks_per_split;
+    const int64_t c_begin = split * chunks_per_split;
     const int64_t c_end = min(chunks, c_begin + chunks_per_split);
 
     f32x16 acc[4][2];
@@ -426,7 +429,7 @@ __global__ __launch_bounds__(512) void k_fwd_bf16(int64_t n, int Mu, int Mp, con
         lds_barrier();
     }
 
-    float *out = part + (size_t)blockIdx.y * (size_t)Mu * (size_t)Mp;
+    float *out = part + (size_t)split * (size_t)Mu * (size_t)Mp;
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -471,9 +474,9 @@ struct RunStages {
             start_run(R, C, S);
             v[0] = C.f * S.f;
             if (u0 == 0) v[0] = R.size;
-            v[1] = C.next() * S.next();
+            v[1] = C.next1() * S.next();
         } else if constexpr (st <= 30) {
-            v[st + 1] = C.next() * S.next();
+            v[st + 1] = C.next1() * S.next();
         }
         // split of pair q: hi at stage 2q + 1, lo at 2q + 2
         if constexpr (st >= 1 && st <= 32) {
@@ -606,9 +609,12 @@ __global__ __launch_bounds__(256) void k_fwd1_bf16(int64_t n, int Mu, int Mp, co
     __shared__ __attribute__((aligned(16))) char smem[2 * FBUF];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t rows = phase_rows(n);
-    const int tu0 = (int)(blockIdx.x / tiles_p) * FT, tp0 = (int)(blockIdx.x % tiles_p) * FT;
+    int tile;
+    int64_t split;
+    fwd_tile_split(tile, split);
+    const int tu0 = (tile / tiles_p) * FT, tp0 = (tile % tiles_p) * FT;
     const int wu = 128 * (wave >> 1), wp = 128 * (wave & 1);
-    const int64_t c_begin = (int64_t)blockIdx.y * chunks_per_split;
+    const int64_t c_begin = split * chunks_per_split;
     const int64_t c_end = min(chunks, c_begin + chunks_per_split);
 
     f32x16 acc[4][4];
@@ -665,7 +671,7 @@ __global__ __launch_bounds__(256) void k_fwd1_bf16(int64_t n, int Mu, int Mp, co
     }
     if (c < c_end) fwd1_chunk<0>(smem, ox, oy, acc, gxB, gyB, o0, ux, uy, kk, rr);
 
-    float *out = part + (size_t)blockIdx.y * (size_t)Mu * (size_t)Mp;
+    float *out = part + (size_t)split * (size_t)Mu * (size_t)Mp;
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -797,13 +803,13 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
         if constexpr (KA == RUN_COS) {
             v[0] = ca.f;
 #pragma unroll
-            for (int e = 1; e < 8; ++e) v[e] = ca.next();
-            ca.next();
+            for (int e = 1; e < 8; ++e) v[e] = ca.next1();
+            ca.next1();
         } else {
             v[0] = ca.f * sb.f;
 #pragma unroll
-            for (int e = 1; e < 8; ++e) v[e] = ca.next() * sb.next();
-            ca.next(); sb.next();
+            for (int e = 1; e < 8; ++e) v[e] = ca.next1() * sb.next();
+            ca.next1(); sb.next();
             v[0] = kcur == 0 ? size0 : v[0];
         }
         kcur += 8;
@@ -983,13 +989,13 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
 
 // A-operand generator of one 32-block subtile: recurrence state and the 32-frequency phasors (see
 // k_bwd_bf16), with the values and split halves of the step being generated.  The generator's
-// work is cut into pieces of at most three VALU instructions (a value and the first FMA of each
-// recurrence; the second FMAs; one half of a hi/lo split; half of a phasor jump), so that the
-// pieces can be dealt over the MFMA slots evenly.
+// work is cut into pieces of at most three VALU instructions (a value and the first FMA of the
+// beta recurrence; the FMAs that advance both recurrences; one half of a hi/lo split; half of a
+// phasor jump), so that the pieces can be dealt over the MFMA slots evenly.
 template <int KA>
 struct AGen {
     Cheb ca, sb;
-    float tc, ts;                 // first FMAs of the two recurrences in flight
+    float ts;                     // first FMA of the beta recurrence in flight
     float pac, pas, pbc, pbs, jac, jas, jbc, jbs, sac, sas, sbc, sbs, size0;
     float tj0, tj1;               // phasor jump in flight
     float v[8];
@@ -1031,17 +1037,15 @@ struct AGen {
     __device__ __forceinline__ void value1() {
         if constexpr (KA == RUN_COS) {
             v[E] = ca.f;
-            tc = fmaf(ca.cl, ca.f, -ca.fm);
         } else {
             v[E] = ca.f * sb.f;
             if constexpr (E == 0 && FIRST0) v[0] = size0;
-            tc = fmaf(ca.cl, ca.f, -ca.fm);
             ts = fmaf(sb.cl, sb.f, -sb.fm);
         }
     }
     // The second FMAs: the recurrences advance by one frequency.
     __device__ __forceinline__ void value2() {
-        const float nc = fmaf(ca.ch, ca.f, tc);
+        const float nc = fmaf(ca.ch, ca.f, -ca.fm);   // the centre factor: one FMA (Cheb::next1)
         ca.fm = ca.f;
         ca.f = nc;
         if constexpr (KA != RUN_COS) {

@@ -190,9 +190,9 @@ struct Gen8 {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             if constexpr (KA == RUN_COS) {
-                v[e] = (P == 0 && e == 0) ? ca.f : ca.next();
+                v[e] = (P == 0 && e == 0) ? ca.f : ca.next1();
             } else {
-                v[e] = (P == 0 && e == 0) ? ca.f * sb.f : ca.next() * sb.next();
+                v[e] = (P == 0 && e == 0) ? ca.f * sb.f : ca.next1() * sb.next();
             }
         }
         split4(v[0], v[1], v[2], v[3], hi[2 * P], lo[2 * P]);
@@ -400,8 +400,8 @@ namespace {
 // thread generates four runs of 32 frequencies of chunk c + 1 (block k = tid % 64, X and Y runs
 // tid / 64 and tid / 64 + 4 of the tile) into the other.
 // LDS buffer: X hi, X lo, Y hi, Y lo, each [64 blocks][256 frequencies] e4m3, 16-byte segments
-// XOR-swizzled by 2 (row % 8) + (row / 8) % 2, then the E8M0 codes of the u = 0 row and the p = 0
-// column (the chunk's largest size).  Operands are read with ds_read_b64_tr_b8: for read t of an
+// XOR-swizzled by M(row) (g8_swz), then the E8M0 codes of the u = 0 row and the p = 0 column (the
+// chunk's largest size).  Operands are read with ds_read_b64_tr_b8: for read t of an
 // operand, source lane s of a 16-lane group reads 8 frequencies (16 g + 8 (s % 2) + ..) of block
 // row 32 h + 8 t + s / 2, so that result lane i of group g holds frequency 16 g + i of blocks
 // 32 h + 8 t .. + 7 (A and B read alike, hence the same K order).
@@ -410,7 +410,19 @@ constexpr int G8_ARR = 64 * 256;
 constexpr int G8_CODES = 4 * G8_ARR;
 constexpr int G8_BUF = 4 * G8_ARR + 256;
 
-__device__ __forceinline__ int g8_swz(int row) { return 2 * (row & 7) + ((row >> 3) & 1); }
+// Rows are 256 bytes, one period of the 64 banks, so a 16-byte segment's banks are fixed by its
+// index; the LDS serves 128 bytes per pass for these accesses, where the index mod 8 counts.  A
+// b128 store pass (8 lanes) writes one segment of 8 aligned rows, and a 16-lane group of a
+// transpose read takes one segment of 8 aligned rows, the 32-lane half that segment and the next
+// (an even index and its successor).  M(row) = r ^ 8 (r % 2) ^ (row / 8) % 2, r = row % 8, is
+// distinct mod 8 over 8 aligned rows and never equals another row's M ^ 1 (so the two segments of a
+// read half fill 16 bank groups); its last term makes all 16 rows of an aligned group distinct, for
+// stores served 16 lanes (256 bytes) at a time.  (The previous M, 2 r + (row / 8) % 2, took only
+// four values mod 8: two-way conflicts, 85 % of the forward's LDS cycles by the bank-conflict counter.)
+__device__ __forceinline__ int g8_swz(int row) {
+    const int r = row & 7;
+    return r ^ ((r & 1) << 3) ^ ((row >> 3) & 1);
+}
 
 // One run's start values and the block's recurrence coefficients and size.
 struct Rec8 {
@@ -446,7 +458,7 @@ __device__ __forceinline__ void gen_run8(const Rec8 &R, bool first, int e0, char
     float v[32];
     v[0] = first ? ldexpf(R.size, -e0) : C.f * S.f;
 #pragma unroll
-    for (int e = 1; e < 32; ++e) v[e] = C.next() * S.next();
+    for (int e = 1; e < 32; ++e) v[e] = C.next1() * S.next();
     unsigned hi[8], lo[8];
 #pragma unroll
     for (int g = 0; g < 8; ++g) {
@@ -466,8 +478,9 @@ __device__ __forceinline__ void gen_run8(const Rec8 &R, bool first, int e0, char
 __device__ __forceinline__ i32x8 read_op8(const char *arr, int f_base, int lane) {
     typedef __attribute__((address_space(3))) i32x2 lds_i32x2;
     const int s = lane & 15, g = (lane >> 4) & 1, h = lane >> 5;
-    const int seg = ((f_base >> 4) + g) ^ (2 * (s >> 1));
-    const int base = (32 * h + (s >> 1)) * 256 + 8 * (s & 1);
+    const int r = s >> 1;   // row 32 h + 8 t + r: g8_swz of it is r ^ 8 (r % 2) ^ (t % 2)
+    const int seg = ((f_base >> 4) + g) ^ r ^ ((r & 1) << 3);
+    const int base = (32 * h + r) * 256 + 8 * (s & 1);
     i32x8 o;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -488,9 +501,12 @@ __global__ __launch_bounds__(256) void k_fwd_fp8(int64_t n, int Mu, int Mp, cons
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t rows = phase_rows(n);
-    const int tu0 = (int)(blockIdx.x / tiles_p) * 256, tp0 = (int)(blockIdx.x % tiles_p) * 256;
+    int tile;
+    int64_t split;
+    fwd_tile_split(tile, split);
+    const int tu0 = (tile / tiles_p) * 256, tp0 = (tile % tiles_p) * 256;
     const int wu = 128 * (wave >> 1), wp = 128 * (wave & 1);
-    const int64_t c_begin = (int64_t)blockIdx.y * chunks_per_split;
+    const int64_t c_begin = split * chunks_per_split;
     const int64_t c_end = min(chunks, c_begin + chunks_per_split);
 
     f32x16 acc[4][4];
@@ -577,7 +593,7 @@ __global__ __launch_bounds__(256) void k_fwd_fp8(int64_t n, int Mu, int Mp, cons
         lds_barrier();
     }
 
-    float *out = part + (size_t)blockIdx.y * (size_t)Mu * (size_t)Mp;
+    float *out = part + (size_t)split * (size_t)Mu * (size_t)Mp;
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll

@@ -45,24 +45,30 @@ def test_argument_errors_leave_device_outputs_untouched():
     for prec in ("fp64", "bf16x3"):
         P = pp.PPProblem(W, H, n, Mu, Mp, pp.PRECISIONS[prec], 0)
         need = pp.workspace_size(W, H, n, Mu, Mp, precision=prec)
-        ws = torch.empty(need, dtype=torch.uint8, device=DEV)
+        need_fp8 = pp.workspace_size(W, H, n, Mu, Mp, precision="fp8")
+        ws = torch.empty(max(need, need_fp8), dtype=torch.uint8, device=DEV)
         a, E, gx, gy, N = sentinel(Mu, Mp), sentinel(1), sentinel(n), sentinel(n), sentinel(n)
         psi, ex, ey = sentinel(n), sentinel(n), sentinel(n)
         bad = [("short workspace", P, need - 1, WS), ("W = 0", pp.PPProblem(0.0, H, n, Mu, Mp, P.precision, 0), need, ARG),
                ("H NaN", pp.PPProblem(W, float("nan"), n, Mu, Mp, P.precision, 0), need, ARG),
                ("Mu = 0", pp.PPProblem(W, H, n, 0, Mp, P.precision, 0), need, ARG),
                ("n < 0", pp.PPProblem(W, H, -1, Mu, Mp, P.precision, 0), need, ARG),
-               ("FP8", pp.PPProblem(W, H, n, Mu, Mp, 4, 0), need, UNSUP),
+               ("FP8 evaluation rows", pp.PPProblem(W, H, n, Mu, Mp, 4, 0), need, [None, None, None, UNSUP, UNSUP]),
+               ("FP8 with the workspace of another precision", pp.PPProblem(W, H, n, Mu, Mp, 4, 0), need_fp8 - 1,
+                [WS, WS, WS, UNSUP, UNSUP]),
                ("unknown precision", pp.PPProblem(W, H, n, Mu, Mp, 9, 0), need, ARG)]
         if prec == "fp64":
             bad.append(("store mode in FP64", pp.PPProblem(W, H, n, Mu, Mp, 0, 1), need, UNSUP))
         for what, Q, nb, code in bad:
-            r = [lib.pp_coeffs(ctypes.byref(Q), *blocks, vp(a), vp(ws), nb, st),
-                 lib.pp_energy(ctypes.byref(Q), *blocks, vp(E), vp(a), vp(ws), nb, st),
-                 lib.pp_field(ctypes.byref(Q), *blocks, vp(a), None, vp(gx), vp(gy), vp(ws), nb, st),
-                 lib.pp_point_field(ctypes.byref(Q), vp(x), vp(y), vp(a), vp(psi), vp(ex), vp(ey), vp(ws), nb, st),
-                 lib.pp_block_potential(ctypes.byref(Q), *blocks, vp(a), vp(N), vp(ws), nb, st)]
-            assert r == [code] * 5, (prec, what, r)
+            codes = code if isinstance(code, list) else [code] * 5
+            calls = [lambda: lib.pp_coeffs(ctypes.byref(Q), *blocks, vp(a), vp(ws), nb, st),
+                     lambda: lib.pp_energy(ctypes.byref(Q), *blocks, vp(E), vp(a), vp(ws), nb, st),
+                     lambda: lib.pp_field(ctypes.byref(Q), *blocks, vp(a), None, vp(gx), vp(gy), vp(ws), nb, st),
+                     lambda: lib.pp_point_field(ctypes.byref(Q), vp(x), vp(y), vp(a), vp(psi), vp(ex), vp(ey), vp(ws),
+                                                nb, st),
+                     lambda: lib.pp_block_potential(ctypes.byref(Q), *blocks, vp(a), vp(N), vp(ws), nb, st)]
+            r = [f() if c is not None else None for f, c in zip(calls, codes)]
+            assert r == codes, (prec, what, r)
             assert untouched(a, E, gx, gy, N, psi, ex, ey), (prec, what)
         # a missing block array, and a misaligned output
         r1 = lib.pp_energy(ctypes.byref(P), None, *blocks[1:], vp(E), vp(a), vp(ws), need, st)
