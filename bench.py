@@ -86,7 +86,7 @@ def cpu_model():
 # The sources that build each precision's contraction kernels and their launches: a committed counter
 # summary (profiles/traffic_*, profiles/mfma_*) is used only while these files are unchanged.
 COMMON_SOURCES = ("api.hip", "common.h", "basis_gen.h", "kernels_common.hip")
-KERNEL_SOURCES = {"bf16x3": ("kernels_bf16.hip",), "bf16": ("kernels_bf16.hip",),
+KERNEL_SOURCES = {"bf16x3": ("kernels_bf16.hip",), "bf16": ("kernels_bf16.hip",), "bf16mix": ("kernels_bf16.hip",),
                   "fp8x3": ("kernels_bf16.hip", "kernels_fp8.hip"), "fp8": ("kernels_bf16.hip", "kernels_fp8.hip"),
                   "fp64": ("kernels_f64.hip",), "fp32": ("kernels_f64.hip",)}
 
@@ -170,6 +170,9 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--fp32-steps", type=int, default=2, help="steps of the FP32 path on the same workload (0: skip)")
+    ap.add_argument("--mix-steps", type=int, default=3,
+                    help="steps of the mixed bf16 split (three products on the low-frequency tiles only) on the "
+                         "same workload (0: skip)")
     ap.add_argument("--fp8-steps", type=int, default=3, help="steps of the FP8X3 and FP8 paths on the same workload "
                                                              "(0: skip)")
     ap.add_argument("--bins", type=int, default=-1,
@@ -203,7 +206,7 @@ def main():
     pairs = wl.pairs
     log(f"[bench] workload {wl.name}: n={wl.n} Mu={wl.Mu} Mp={wl.Mp} pairs/step={pairs:.3e}")
     t = [torch.as_tensor(v, device=dev) for v in wl.arrays()]
-    need = max([pp.workspace_size(wl.W, wl.H, wl.n, wl.Mu, wl.Mp, precision=p) for p in ("fp32", "fp64", "fp8x3")]
+    need = max([pp.workspace_size(wl.W, wl.H, wl.n, wl.Mu, wl.Mp, precision=p) for p in ("fp32", "fp64", "fp8x3", "bf16mix")]
                + [pp.workspace_size(wl.W, wl.H, wl.n, wl.Mu, wl.Mp, precision=args.precision, basis=args.basis)])
     ws = torch.empty(need, dtype=torch.uint8, device=dev)
     log(f"[bench] workspace {need / 2**20:.1f} MiB")
@@ -292,6 +295,20 @@ def main():
         if ref is not None:
             out["fp32_plain"]["rel_err_vs_fp64_gpu"] = errors_vs(ref, r32)
         out["speedup_vs_fp32"] = value / v32
+
+    if args.mix_steps > 0 and args.precision == "bf16x3" and args.basis == "recompute":
+        # The mixed split on the same workload: three products on the low-frequency tiles, one elsewhere.
+        dtm, stm, rm = timed_steps(pp, torch, t, wl, "bf16mix", args.mix_steps, 1, ws)
+        vm = pairs * args.mix_steps / dtm
+        rec = {"value": vm, "unit": "pairs/s", "ms_per_step": dtm / args.mix_steps * 1e3, "steps": args.mix_steps,
+               "stages_ms_per_step": {k: round(v[0] / args.mix_steps, 3) for k, v in stm.items()},
+               "speedup_vs_bf16x3": vm / value, "mfma_counters": measured_mfma(wl.name, "bf16mix")}
+        if ref is not None:
+            rec["rel_err_vs_fp64_gpu"] = errors_vs(ref, rm)
+        out["bf16mix"] = rec
+        log(f"[bench] bf16mix: {dtm / args.mix_steps * 1e3:.1f} ms/step, {vm:.4e} pairs/s; stages "
+            + ", ".join(f"{k}={v[0] / v[1]:.2f}ms x{v[1] // args.mix_steps}" for k, v in stm.items())
+            + (f"; vs fp64 {rec['rel_err_vs_fp64_gpu']}" if ref is not None else ""))
 
     fp8_runs = {}
     if args.fp8_steps > 0 and args.precision not in ("fp8x3", "fp8"):

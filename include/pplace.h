@@ -74,8 +74,20 @@ typedef enum pp_precision {
                        (u = 0 row, p = 0 column) scaled by the largest size of each 64-block chunk, the
                        gradient's coefficient operand scaled per column and 64-value chunk; the k = 0 term
                        of the gradient contraction added exactly in FP32.  Relative error ~3e-2. */
-    PP_FP8X3 = 5    /* e4m3 hi/lo split of the same operands: hi*hi + lo*hi + hi*lo; relative error ~1e-3
+    PP_FP8X3 = 5,   /* e4m3 hi/lo split of the same operands: hi*hi + lo*hi + hi*lo; relative error ~1e-3
                        (3 mantissa bits per part).  FP8 and FP8X3 serve pp_coeffs, pp_energy,
+                       pp_energy_static and pp_field in recompute mode; pp_point_field,
+                       pp_block_potential and the stored basis give PP_ERR_UNSUPPORTED. */
+    PP_BF16MIX = 6  /* mixed split: PP_BF16X3 (three products) on the low-frequency tiles, PP_BF16 (hi only,
+                       one product) elsewhere.  Per axis the first ceil(M / 1024) tiles of 256
+                       frequencies (at least one: the first quarter of the frequencies) are split: the
+                       coefficient contraction uses three products on the tiles with u and p both in
+                       that range, the gradient contraction of gx (gy) on the N tiles of u (p) in it,
+                       with the whole K axis.  The coefficients fall off like 1 / (u^2 + p^2)
+                       (Sec. III-A), so the errors of the one-product tiles are small against the
+                       largest terms of the energy and the gradient, which keep the accuracy of
+                       PP_BF16X3 on placement-like inputs; each coefficient of those tiles on its own
+                       is only as accurate as PP_BF16 makes it (~3e-3).  Serves pp_coeffs, pp_energy,
                        pp_energy_static and pp_field in recompute mode; pp_point_field,
                        pp_block_potential and the stored basis give PP_ERR_UNSUPPORTED. */
 } pp_precision;

@@ -24,7 +24,7 @@ __all__ = ["PRECISIONS", "BASIS_MODES", "PPError", "library_path", "load", "work
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libpplace.so")
 
-PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "fp8": 4, "fp8x3": 5}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "fp8": 4, "fp8x3": 5, "bf16mix": 6}
 BASIS_MODES = {"recompute": 0, "store": 1}
 
 PP_OK = 0

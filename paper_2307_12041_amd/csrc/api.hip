@@ -29,9 +29,16 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 bool supported_precision(int prec) {
     return prec == PP_FP64 || prec == PP_FP32 || prec == PP_BF16 || prec == PP_BF16X3 || prec == PP_FP8 ||
-           prec == PP_FP8X3;
+           prec == PP_FP8X3 || prec == PP_BF16MIX;
 }
-bool is_bf16(int prec) { return prec == PP_BF16 || prec == PP_BF16X3; }
+bool is_bf16(int prec) { return prec == PP_BF16 || prec == PP_BF16X3 || prec == PP_BF16MIX; }
+
+// Mixed split: the low-frequency tiles that take three products, per axis: ceil(M / 1024) tiles of
+// 256 frequencies (at least one, at most all), i.e. the first quarter of the frequencies.
+int mix_tiles(int M) {
+    const int r = (M + 1023) / 1024, t = (M + 255) / 256;
+    return r < 1 ? 1 : (r > t ? t : r);
+}
 bool is_fp8(int prec) { return prec == PP_FP8 || prec == PP_FP8X3; }
 // Operand types whose basis is generated from per-block phase records and run seeds.
 bool is_gen(int prec) { return is_bf16(prec) || is_fp8(prec); }
@@ -44,10 +51,11 @@ int validate_problem(const pp_problem *P) {
     if (P->n < 0 || P->n > kMaxBlocks) return PP_ERR_ARG;
     if (P->Mu < 1 || P->Mp < 1 || P->Mu > kMaxFreq || P->Mp > kMaxFreq) return PP_ERR_ARG;
     if ((int64_t)P->Mu * (int64_t)P->Mp > kMaxPairs) return PP_ERR_ARG;
-    if (P->precision < PP_FP64 || P->precision > PP_FP8X3) return PP_ERR_ARG;
+    if (P->precision < PP_FP64 || P->precision > PP_BF16MIX) return PP_ERR_ARG;
     if (P->basis_mode != PP_BASIS_RECOMPUTE && P->basis_mode != PP_BASIS_STORE) return PP_ERR_ARG;
     if (!supported_precision(P->precision)) return PP_ERR_UNSUPPORTED;
-    if (P->basis_mode == PP_BASIS_STORE && !is_bf16(P->precision)) return PP_ERR_UNSUPPORTED;
+    if (P->basis_mode == PP_BASIS_STORE && (!is_bf16(P->precision) || P->precision == PP_BF16MIX))
+        return PP_ERR_UNSUPPORTED;
     if (!grids_fit(*P)) return PP_ERR_ARG;
     return PP_OK;
 }
@@ -76,9 +84,16 @@ FwdPlan fwd_plan(const pp_problem &P) {
     pl.tiles_p = (P.Mp + pl.tp - 1) / pl.tp;
     pl.chunks = (P.n + pl.kb - 1) / pl.kb;
     const int64_t tiles = (int64_t)pl.tiles_u * pl.tiles_p;
-    // Enough workgroups to fill 256 CUs several times over, never more splits than chunks.
+    // Enough workgroups to fill 256 CUs several times over, never more splits than chunks.  The mixed
+    // split runs its few three-product tiles in a launch of their own, which needs as many
+    // workgroups: at least 512 there.
     const int64_t target = 2048;
     int64_t splits = (target + tiles - 1) / tiles;
+    if (P.precision == PP_BF16MIX) {
+        const int64_t corner = (int64_t)mix_tiles(P.Mu) * mix_tiles(P.Mp);
+        const int64_t need = (512 + corner - 1) / corner;
+        if (splits < need) splits = need;
+    }
     if (splits > pl.chunks) splits = pl.chunks;
     if (splits > 4096) splits = 4096;
     if (splits < 1) splits = 1;
@@ -196,7 +211,8 @@ bool grids_fit(const pp_problem &P) {
     const BwdPlan b = bwd_plan(P);
     const bool bf = is_gen(P.precision);
     const uint64_t tiles = (uint64_t)f.tiles_u * (uint64_t)f.tiles_p;
-    bool ok = dim_ok(tiles, P.precision == PP_BF16 ? 512 : 256) && (uint64_t)f.splits <= 0xffffffffull;
+    bool ok = dim_ok(tiles, (P.precision == PP_BF16 || P.precision == PP_BF16MIX) ? 512 : 256) &&
+              (uint64_t)f.splits <= 0xffffffffull;
     ok = ok && dim_ok((uint64_t)reduce_scale_blocks(P.Mu, P.Mp), 256);   // split-K reduction
     ok = ok && dim_ok(cdiv(MM, 256), 256);                                 // row-form operands (FP64 / FP32)
     ok = ok && dim_ok(cdiv(n, 256), 256);                                  // final per-block sums
@@ -267,6 +283,10 @@ int run_forward(const pp_problem &P, const double *x, const double *y, const dou
         } else if (is_fp8(P.precision)) {
             TimedLaunch t(T("fwd"), s);
             err = launch_fwd_fp8(f, x3, P.n, P.Mu, P.Mp, tx, ty, sx, sy, (float *)part, s);
+        } else if (P.precision == PP_BF16MIX) {
+            TimedLaunch t(T("fwd"), s);
+            err = launch_fwd_bf16_mix(f, mix_tiles(P.Mu), mix_tiles(P.Mp), P.n, P.Mu, P.Mp, tx, ty, sx, sy,
+                                      (float *)part, s);
         } else {
             TimedLaunch t(T("fwd"), s);
             err = launch_fwd_bf16(f, x3, P.n, P.Mu, P.Mp, tx, ty, sx, sy, (float *)part, s);
@@ -438,8 +458,25 @@ int pp_field(const pp_problem *P, const double *x, const double *y, const double
             axy.tab_h = st.xh; axy.tab_l = st.xl; axy.tab_ld = st.ldx;
             axy.tiles_b = tb; axy.tiles_n = (P->Mp + 255) / 256;
         }
-        { TimedLaunch t("bwd", s); if (launch_bwd_bf16(ROW_FIELD, x3, P->n, axx, s) != hipSuccess) return PP_ERR_DEVICE; }
-        { TimedLaunch t("bwd", s); if (launch_bwd_bf16(ROW_FIELD, x3, P->n, axy, s) != hipSuccess) return PP_ERR_DEVICE; }
+        if (P->precision == PP_BF16MIX) {
+            // the low-frequency N tiles with three products, the others with one (the K axis whole in
+            // both); each launch writes the partial row sums of its own N tiles
+            const int rx = mix_tiles(P->Mu), ry = mix_tiles(P->Mp);
+            for (int axis = 0; axis < 2; ++axis) {
+                TimedLaunch t("bwd", s);
+                BwdAxisBf16 lo = axis == 0 ? axx : axy, hi = lo;
+                const int r = axis == 0 ? rx : ry, tn = axis == 0 ? b.tiles_nx : b.tiles_ny;
+                lo.nt0 = 0; lo.nt_end = r;
+                if (launch_bwd_bf16(ROW_FIELD, true, P->n, lo, s) != hipSuccess) return PP_ERR_DEVICE;
+                if (r < tn) {
+                    hi.nt0 = r; hi.nt_end = tn;
+                    if (launch_bwd_bf16(ROW_FIELD, false, P->n, hi, s) != hipSuccess) return PP_ERR_DEVICE;
+                }
+            }
+        } else {
+            { TimedLaunch t("bwd", s); if (launch_bwd_bf16(ROW_FIELD, x3, P->n, axx, s) != hipSuccess) return PP_ERR_DEVICE; }
+            { TimedLaunch t("bwd", s); if (launch_bwd_bf16(ROW_FIELD, x3, P->n, axy, s) != hipSuccess) return PP_ERR_DEVICE; }
+        }
         { TimedLaunch t("final", s); if (launch_bwd_final(gpx, b.tiles_nx, gpy, b.tiles_ny, P->n, dE, gx, gy, s) != hipSuccess) return PP_ERR_DEVICE; }
         return PP_OK;
     }
@@ -459,7 +496,8 @@ int pp_point_field(const pp_problem *P, const double *px, const double *py, cons
                    double *xix, double *xiy, void *ws, size_t ws_bytes, void *stream) {
     int st = validate_problem(P);
     if (st != PP_OK) return st;
-    if (P->basis_mode != PP_BASIS_RECOMPUTE || is_fp8(P->precision)) return PP_ERR_UNSUPPORTED;
+    if (P->basis_mode != PP_BASIS_RECOMPUTE || is_fp8(P->precision) || P->precision == PP_BF16MIX)
+        return PP_ERR_UNSUPPORTED;
     if (P->n > 0 && (!px || !py || !aligned8(px) || !aligned8(py))) return PP_ERR_ARG;
     if (!a || !aligned8(a)) return PP_ERR_ARG;
     if ((psi && !aligned8(psi)) || (xix && !aligned8(xix)) || (xiy && !aligned8(xiy))) return PP_ERR_ARG;
@@ -535,7 +573,8 @@ int pp_block_potential(const pp_problem *P, const double *x, const double *y, co
                        const double *a, double *N, void *ws, size_t ws_bytes, void *stream) {
     int st = validate_problem(P);
     if (st != PP_OK) return st;
-    if (P->basis_mode != PP_BASIS_RECOMPUTE || is_fp8(P->precision)) return PP_ERR_UNSUPPORTED;
+    if (P->basis_mode != PP_BASIS_RECOMPUTE || is_fp8(P->precision) || P->precision == PP_BF16MIX)
+        return PP_ERR_UNSUPPORTED;
     if ((st = validate_blocks(P, x, y, w, h)) != PP_OK) return st;
     if (!a || !aligned8(a)) return PP_ERR_ARG;
     if (P->n > 0 && (!N || !aligned8(N))) return PP_ERR_ARG;

@@ -126,6 +126,9 @@ struct BwdAxisBf16 {
     // epilogue axis (for the w sin kind).
     double *gpart2;
     float pil;
+    // Recompute mode: the launch covers N tiles nt0 .. nt_end - 1 (nt_end = 0: all N tiles), so that
+    // the mixed split can contract some N tiles with three products and the rest with one.
+    int nt0, nt_end;
 };
 
 // One gradient contraction of the fp8 paths (gx or gy): as BwdAxisBf16 without store mode; B is the
@@ -178,6 +181,10 @@ hipError_t launch_phase_tables(int64_t n, const double *x, const double *y, cons
 hipError_t launch_seed_table(int64_t n, int runs, const PhaseRec *tab, RunSeed *seeds, hipStream_t s);
 hipError_t launch_fwd_bf16(const FwdPlan &pl, bool x3, int64_t n, int Mu, int Mp, const PhaseRec *tx,
                            const PhaseRec *ty, const RunSeed *sx, const RunSeed *sy, float *part, hipStream_t s);
+// Mixed split: the rx x ry low-frequency tiles with k_fwd1_bf16 (three products), the others with
+// the one-product kernel; same partials and plan as launch_fwd_bf16.
+hipError_t launch_fwd_bf16_mix(const FwdPlan &pl, int rx, int ry, int64_t n, int Mu, int Mp, const PhaseRec *tx,
+                               const PhaseRec *ty, const RunSeed *sx, const RunSeed *sy, float *part, hipStream_t s);
 hipError_t launch_prep_bwd_bf16(RowForm f, const double *a, int Mu, int Mp, double W, double H, int trans, int Np,
                                 int Kh, unsigned short *B, hipStream_t s);
 size_t bwd_bf16_operand_elems(int Np, int Kh);   // bf16 elements of one tiled backward operand

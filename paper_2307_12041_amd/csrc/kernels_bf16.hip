@@ -360,11 +360,14 @@ __device__ __forceinline__ void fwd_mma(const char *buf, const OpBase &ox, const
     }
 }
 
+// skip_u x skip_p: the tiles of that low-frequency corner are left to another launch (the mixed split
+// contracts them with three products); 0 x 0 skips nothing.
 template <bool X3>
 __global__ __launch_bounds__(512) void k_fwd_bf16(int64_t n, int Mu, int Mp, const PhaseRec *__restrict__ tx,
                                                   const PhaseRec *__restrict__ ty, const RunSeed *__restrict__ sx,
                                                   const RunSeed *__restrict__ sy, float *__restrict__ part,
-                                                  int tiles_p, int64_t chunks, int64_t chunks_per_split) {
+                                                  int tiles_p, int64_t chunks, int64_t chunks_per_split, int skip_u,
+                                                  int skip_p) {
     __shared__ __attribute__((aligned(16))) char smem[2 * FBUF];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int group = wave >> 2, gt = tid & 255;
@@ -372,6 +375,7 @@ __global__ __launch_bounds__(512) void k_fwd_bf16(int64_t n, int Mu, int Mp, con
     int tile;
     int64_t split;
     fwd_tile_split(tile, split);
+    if (tile / tiles_p < skip_u && tile % tiles_p < skip_p) return;   // the whole workgroup, before any barrier
     const int tu0 = (tile / tiles_p) * FT, tp0 = (tile % tiles_p) * FT;
     const int wu = 128 * (wave >> 2), wp = 64 * (wave & 3);
     const int64_t c_begin = split * chunks_per_split;
@@ -742,7 +746,7 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
         if (btile >= ax.tiles_b) return;
     } else {
         btile = blockIdx.x;
-        ntile = blockIdx.y;
+        ntile = blockIdx.y + ax.nt0;
     }
     const int64_t i0 = (int64_t)btile * 256 + 32 * wave;
     const int n0 = ntile * BTN;
@@ -1181,7 +1185,7 @@ __global__ __launch_bounds__(256) void k_bwd1_bf16(int64_t n, BwdAxisBf16 ax) {
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int h = lane >> 5, j = lane & 31;
-    const int btile = blockIdx.x, ntile = blockIdx.y;
+    const int btile = blockIdx.x, ntile = blockIdx.y + ax.nt0;
     const int64_t i0 = (int64_t)btile * 256 + 64 * wave;
     const int n0 = ntile * BTN;
     const int Q = ax.Kh / 32;
@@ -1481,7 +1485,22 @@ hipError_t launch_fwd_bf16(const FwdPlan &pl, bool x3, int64_t n, int Mu, int Mp
                            pl.chunks_per_split);
     else
         hipLaunchKernelGGL(k_fwd_bf16<false>, grid, dim3(512), 0, s, n, Mu, Mp, tx, ty, sx, sy, part, pl.tiles_p,
-                           pl.chunks, pl.chunks_per_split);
+                           pl.chunks, pl.chunks_per_split, 0, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_fwd_bf16_mix(const FwdPlan &pl, int rx, int ry, int64_t n, int Mu, int Mp, const PhaseRec *tx,
+                               const PhaseRec *ty, const RunSeed *sx, const RunSeed *sy, float *part, hipStream_t s) {
+    if (pl.tu != FT || pl.tp != FT || pl.kb != FKB) return hipErrorInvalidValue;
+    if (rx < 1 || ry < 1 || rx > pl.tiles_u || ry > pl.tiles_p) return hipErrorInvalidValue;
+    // the rx x ry low-frequency tiles with three products (a grid over that corner alone: tiles_p = ry
+    // maps its tile index to the same (u, p) tile), then every other tile with one; both write the
+    // same split-K partials, so the reduction is unchanged
+    hipLaunchKernelGGL(k_fwd1_bf16, dim3(rx * ry, pl.splits), dim3(256), 0, s, n, Mu, Mp, tx, ty, sx, sy, part, ry,
+                       pl.chunks, pl.chunks_per_split);
+    if (rx < pl.tiles_u || ry < pl.tiles_p)
+        hipLaunchKernelGGL(k_fwd_bf16<false>, dim3(pl.tiles_u * pl.tiles_p, pl.splits), dim3(512), 0, s, n, Mu, Mp, tx,
+                           ty, sx, sy, part, pl.tiles_p, pl.chunks, pl.chunks_per_split, rx, ry);
     return hipGetLastError();
 }
 
@@ -1498,7 +1517,10 @@ size_t bwd_bf16_operand_elems(int Np, int Kh) { return (size_t)(Np / BTN) * (siz
 namespace {
 template <int KA, int E1, int E2>
 hipError_t launch_rowform_bf16(bool x3, int64_t n, const BwdAxisBf16 &ax, hipStream_t s) {
-    dim3 grid((unsigned)((n + 255) / 256), (unsigned)((ax.Nb + BTN - 1) / BTN));
+    const int tiles_n = (ax.Nb + BTN - 1) / BTN;
+    const int nt_end = ax.nt_end > 0 ? ax.nt_end : tiles_n;
+    if (ax.nt0 < 0 || nt_end > tiles_n || ax.nt0 >= nt_end) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((n + 255) / 256), (unsigned)(nt_end - ax.nt0));
     if (x3) hipLaunchKernelGGL((k_bwd1_bf16<KA, E1, E2>), grid, dim3(256), 0, s, n, ax);
     else hipLaunchKernelGGL((k_bwd_bf16<false, false, KA, E1, E2>), grid, dim3(512), 0, s, n, ax);
     return hipGetLastError();

@@ -144,14 +144,15 @@ def test_evaluation_entry_points_validate_before_launch(lib):
 
 
 def test_unsupported_modes_reported(lib):
-    for prec in (4, 5):                  # the fp8 types run in recompute mode only
+    for prec in (4, 5, 6):               # the fp8 types and the mixed split run in recompute mode only
         assert ws_size(lib, P(precision=prec))[0] == 0
         assert ws_size(lib, P(precision=prec, basis_mode=1))[0] == -3
     fake = ctypes.c_void_p(1 << 20)
-    q = P(precision=5)
-    st, need = ws_size(lib, q)
-    assert lib.pp_point_field(ctypes.byref(q), fake, fake, fake, fake, fake, fake, fake, need, None) == -3
-    assert lib.pp_block_potential(ctypes.byref(q), fake, fake, fake, fake, fake, fake, fake, need, None) == -3
+    for prec in (5, 6):                  # ... and serve neither evaluation row
+        q = P(precision=prec)
+        st, need = ws_size(lib, q)
+        assert lib.pp_point_field(ctypes.byref(q), fake, fake, fake, fake, fake, fake, fake, need, None) == -3
+        assert lib.pp_block_potential(ctypes.byref(q), fake, fake, fake, fake, fake, fake, fake, need, None) == -3
     for prec in (0, 1):                  # stored tables exist for the bf16 operand types only
         st, _ = ws_size(lib, P(precision=prec, basis_mode=1))
         assert st == -3
@@ -250,7 +251,7 @@ def _documented_status(W, H, n, Mu, Mp, prec, basis):
     Mu * Mp <= 2^30, and for the stored basis ceil(n / 256) * ceil(max(Mu, Mp) / 256) < 2^21)."""
     ok = lambda v: math.isfinite(v) and v > 0.0
     if (not ok(W) or not ok(H) or n < 0 or n > 2 ** 31 - 512 or not 1 <= Mu <= 65536 or not 1 <= Mp <= 65536
-            or Mu * Mp > 2 ** 30 or not 0 <= prec <= 5 or basis not in (0, 1)):
+            or Mu * Mp > 2 ** 30 or not 0 <= prec <= 6 or basis not in (0, 1)):
         return -1
     if basis == 1 and prec not in (2, 3):
         return -3
