@@ -296,9 +296,11 @@ def main():
             out["fp32_plain"]["rel_err_vs_fp64_gpu"] = errors_vs(ref, r32)
         out["speedup_vs_fp32"] = value / v32
 
+    mix_run = None
     if args.mix_steps > 0 and args.precision == "bf16x3" and args.basis == "recompute":
         # The mixed split on the same workload: three products on the low-frequency tiles, one elsewhere.
         dtm, stm, rm = timed_steps(pp, torch, t, wl, "bf16mix", args.mix_steps, 1, ws)
+        mix_run = rm
         vm = pairs * args.mix_steps / dtm
         rec = {"value": vm, "unit": "pairs/s", "ms_per_step": dtm / args.mix_steps * 1e3, "steps": args.mix_steps,
                "stages_ms_per_step": {k: round(v[0] / args.mix_steps, 3) for k, v in stm.items()},
@@ -449,6 +451,8 @@ def main():
             if ref is not None:
                 runs["fp64"] = ref
             runs.update(fp8_runs)
+            if mix_run is not None:
+                runs["bf16mix"] = mix_run
             vs = {}
             for name, r in runs.items():
                 an = r[1].cpu().numpy()[us, ps]

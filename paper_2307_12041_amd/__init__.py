@@ -22,7 +22,8 @@ __all__ = ["PRECISIONS", "BASIS_MODES", "PPError", "library_path", "load", "work
            "timing_query", "bin_workspace_size", "bin_density", "bin_coeffs", "bin_field"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libpplace.so")
+# PP_LIBRARY names another build of the same library (the host-sanitizer test uses it).
+_LIB_PATH = os.environ.get("PP_LIBRARY") or os.path.join(_HERE, "libpplace.so")
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "fp8": 4, "fp8x3": 5, "bf16mix": 6}
 BASIS_MODES = {"recompute": 0, "store": 1}
