@@ -1069,6 +1069,9 @@ struct AGen {
     __device__ __forceinline__ void half_lo() {
         ll[M] = split_lo(v[2 * M], v[2 * M + 1], hah[M], hbh[M]);
     }
+    // One-product contraction: the hi half alone (no lo split follows).
+    template <int M>
+    __device__ __forceinline__ void pack_hi() { hh[M] = pack_bf16(v[2 * M], v[2 * M + 1]); }
     __device__ __forceinline__ bf16x8 hi() const { return __builtin_bit_cast(bf16x8, u32x4{hh[0], hh[1], hh[2], hh[3]}); }
     __device__ __forceinline__ bf16x8 lo() const { return __builtin_bit_cast(bf16x8, u32x4{ll[0], ll[1], ll[2], ll[3]}); }
 };
@@ -1168,9 +1171,55 @@ __device__ __forceinline__ void bwd1_slot(Bwd1Ctx<KA> &c) {
     __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int KA, int... I>
+// One-product chunk (plain bf16, and the one-product N tiles of the mixed split): 4 steps of 16 slots,
+// slot t of a step holding MFMA (column tile t / 2, subtile t % 2) and the whole generator work of
+// value u = t of the following step (its value and both FMAs of the recurrences, and the hi half of
+// the pair it completes); the phasor jump takes slots 0-7 of step 0, the reseeds follow the last
+// value of each subtile in step 2.  Next step's hi B is read at slots 8-15, at least 8 slots ahead
+// of its first use and after the current step's last use of the same register; the barrier moves
+// to slot 7 of step 3 and the copies of the chunk after next (hi half only) to its slots 8-15.
+template <int KA, int I>
+__device__ __forceinline__ void bwd1_slot_plain(Bwd1Ctx<KA> &c) {
+    constexpr int s = I / 16, t = I % 16;
+    constexpr int b = t / 2, a = t % 2;
+    c.acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(c.ah[a], c.bh[b], c.acc[a][b], 0, 0, 0);
+    if constexpr (s == 3 && t == 7) {
+        wait_copies();
+        lds_barrier();
+    }
+    if constexpr (t >= 8) {
+        constexpr int bb = t - 8;
+        if constexpr (s < 3) c.bh[bb] = bwd1_readb(c.cur, 0, bb, s + 1, c.h, c.j);
+        else c.bh[bb] = bwd1_readb(c.nxt, 0, bb, 0, c.h, c.j);
+    }
+    if constexpr (s == 3 && t >= 8) {
+        typedef __attribute__((address_space(3))) void lds_void;
+        constexpr int sl = t - 8;
+        __builtin_amdgcn_global_load_lds((const void *)(c.cpy_src + sl * 4096 + c.lane_off),
+                                         (lds_void *)(c.cpy_dst + sl * 4096 + c.wave_off), 16, 0, 0);
+    }
+    {
+        constexpr int u = t, ga = u & 1, e = u >> 1;
+        c.g[ga].template value1<e, false>();
+        c.g[ga].value2();
+        if constexpr ((u & 3) >= 2) c.g[ga].template pack_hi<(u >> 2)>();
+        if constexpr (s == 0 && u < 8) {
+            c.g[u >> 2].template jump<(u & 3)>();
+        }
+        if constexpr (s == 2 && u == 14) c.g[0].reseed();
+        if constexpr (s == 2 && u == 15) c.g[1].reseed();
+    }
+    if constexpr (t == 15) {
+#pragma unroll
+        for (int aa = 0; aa < 2; ++aa) c.ah[aa] = c.g[aa].hi();
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+template <bool X3, int KA, int... I>
 __device__ __forceinline__ void bwd1_slots(Bwd1Ctx<KA> &c, std::integer_sequence<int, I...>) {
-    (bwd1_slot<KA, I>(c), ...);
+    if constexpr (X3) (bwd1_slot<KA, I>(c), ...);
+    else (bwd1_slot_plain<KA, I>(c), ...);
 }
 
 template <int KA, bool FIRST0, int... T>
@@ -1179,7 +1228,8 @@ __device__ __forceinline__ void bwd1_gen_all(Bwd1Ctx<KA> &c, std::integer_sequen
 }
 
 
-template <int KA, int E1, int E2>
+// X3: three products per pair (hi*hi, lo*hi, hi*lo); otherwise one (hi*hi).
+template <bool X3, int KA, int E1, int E2>
 __global__ __launch_bounds__(256) void k_bwd1_bf16(int64_t n, BwdAxisBf16 ax) {
     __shared__ __attribute__((aligned(16))) char smem[2 * BBUF];
     const int tid = threadIdx.x, lane = tid & 63;
@@ -1234,7 +1284,7 @@ __global__ __launch_bounds__(256) void k_bwd1_bf16(int64_t n, BwdAxisBf16 ax) {
         c.nxt = smem + ((q & 1) ^ 1) * BBUF;
         c.cpy_dst = smem + (q & 1) * BBUF;
         c.cpy_src = gb + (size_t)min(q + 2, Q - 1) * tile_bytes;
-        bwd1_slots(c, std::make_integer_sequence<int, 192>{});
+        bwd1_slots<X3>(c, std::make_integer_sequence<int, X3 ? 192 : 64>{});
     }
     wait_copies();   // the copies issued in the last chunks must land before the buffers are reused
     __syncthreads();
@@ -1521,8 +1571,8 @@ hipError_t launch_rowform_bf16(bool x3, int64_t n, const BwdAxisBf16 &ax, hipStr
     const int nt_end = ax.nt_end > 0 ? ax.nt_end : tiles_n;
     if (ax.nt0 < 0 || nt_end > tiles_n || ax.nt0 >= nt_end) return hipErrorInvalidValue;
     dim3 grid((unsigned)((n + 255) / 256), (unsigned)(nt_end - ax.nt0));
-    if (x3) hipLaunchKernelGGL((k_bwd1_bf16<KA, E1, E2>), grid, dim3(256), 0, s, n, ax);
-    else hipLaunchKernelGGL((k_bwd_bf16<false, false, KA, E1, E2>), grid, dim3(512), 0, s, n, ax);
+    if (x3) hipLaunchKernelGGL((k_bwd1_bf16<true, KA, E1, E2>), grid, dim3(256), 0, s, n, ax);
+    else hipLaunchKernelGGL((k_bwd1_bf16<false, KA, E1, E2>), grid, dim3(256), 0, s, n, ax);
     return hipGetLastError();
 }
 }  // namespace
