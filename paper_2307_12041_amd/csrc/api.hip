@@ -211,8 +211,7 @@ bool grids_fit(const pp_problem &P) {
     const BwdPlan b = bwd_plan(P);
     const bool bf = is_gen(P.precision);
     const uint64_t tiles = (uint64_t)f.tiles_u * (uint64_t)f.tiles_p;
-    bool ok = dim_ok(tiles, (P.precision == PP_BF16 || P.precision == PP_BF16MIX) ? 512 : 256) &&
-              (uint64_t)f.splits <= 0xffffffffull;
+    bool ok = dim_ok(tiles, 256) && (uint64_t)f.splits <= 0xffffffffull;
     ok = ok && dim_ok((uint64_t)reduce_scale_blocks(P.Mu, P.Mp), 256);   // split-K reduction
     ok = ok && dim_ok(cdiv(MM, 256), 256);                                 // row-form operands (FP64 / FP32)
     ok = ok && dim_ok(cdiv(n, 256), 256);                                  // final per-block sums

@@ -142,11 +142,9 @@ __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(
 
 // ================================================================================================
 // Forward: At[u][p] = sum_i S_iu T_ip over a range of blocks.
-// Kernels: k_fwd1_bf16 (x3, one wave per SIMD, further below) and k_fwd_bf16 (plain bf16, here).
-// k_fwd_bf16: 512 threads = 8 waves in two ping-pong groups.  Wave w owns the 128 x 64 output sub-tile
-// (u-half w / 4, p-quarter w % 4); waves w and w + 4 share a SIMD.  Per chunk of 32 blocks the
-// group of waves 0-3 generates the X tile, the group of waves 4-7 the Y tile; while one group
-// contracts chunk c from one LDS buffer the other generates chunk c + 1 into the other buffer.
+// Kernels: k_fwd1_bf16<X3> (one wave per SIMD, three products or one, further below) and the
+// store-mode k_fwd_bf16_st (512 threads = 8 waves, wave w owning the 128 x 64 output sub-tile (u-half
+// w / 4, p-quarter w % 4), contracting tiles staged from the stored tables with fwd_mma).
 // LDS tile layout: [block][frequency] bf16, 512-byte rows with XOR-swizzled 16-byte segments;
 // MFMA operands are read with the transpose read.
 // ================================================================================================
@@ -360,91 +358,6 @@ __device__ __forceinline__ void fwd_mma(const char *buf, const OpBase &ox, const
     }
 }
 
-// skip_u x skip_p: the tiles of that low-frequency corner are left to another launch (the mixed split
-// contracts them with three products); 0 x 0 skips nothing.
-template <bool X3>
-__global__ __launch_bounds__(512) void k_fwd_bf16(int64_t n, int Mu, int Mp, const PhaseRec *__restrict__ tx,
-                                                  const PhaseRec *__restrict__ ty, const RunSeed *__restrict__ sx,
-                                                  const RunSeed *__restrict__ sy, float *__restrict__ part,
-                                                  int tiles_p, int64_t chunks, int64_t chunks_per_split, int skip_u,
-                                                  int skip_p) {
-    __shared__ __attribute__((aligned(16))) char smem[2 * FBUF];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int group = wave >> 2, gt = tid & 255;
-    const int64_t rows = phase_rows(n);
-    int tile;
-    int64_t split;
-    fwd_tile_split(tile, split);
-    if (tile / tiles_p < skip_u && tile % tiles_p < skip_p) return;   // the whole workgroup, before any barrier
-    const int tu0 = (tile / tiles_p) * FT, tp0 = (tile % tiles_p) * FT;
-    const int wu = 128 * (wave >> 2), wp = 64 * (wave & 3);
-    const int64_t c_begin = split * chunks_per_split;
-    const int64_t c_end = min(chunks, c_begin + chunks_per_split);
-
-    f32x16 acc[4][2];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
-    OpBase ox, oy;
-    ox.init(wu, lane);
-    oy.init(wp, lane);
-
-    // Group 0 generates the X tile (u), group 1 the Y tile (p).
-    const PhaseRec *tab = group == 0 ? tx : ty;
-    const RunSeed *seeds = group == 0 ? sx : sy;
-    const int f0 = group == 0 ? tu0 : tp0;
-    const int aoff = group == 0 ? 0 : 2 * FARR;
-    const int kk = gt & 31, run = f0 / 32 + (gt >> 5);
-    auto load_rec = [&](int64_t chunk) { return load_gen_at(tab, seeds, rows, run, n, chunk * FKB + kk); };
-    GenRec rec;
-    if (c_begin < c_end) {
-        rec = load_rec(c_begin);
-        fwd_gen<X3>(rec, f0, smem + aoff, smem + aoff + FARR, gt);
-        if (group == 1 && c_begin + 1 < c_end) rec = load_rec(c_begin + 1);
-    }
-    __syncthreads();
-    for (int64_t c = c_begin; c < c_end; ++c) {
-        const int bsel = (int)((c - c_begin) & 1);
-        char *cur = smem + bsel * FBUF, *nxt = smem + (bsel ^ 1) * FBUF;
-        const bool more = c + 1 < c_end;
-        // Two phases per chunk, separated by a barrier so that the waves of a SIMD stay in
-        // opposite roles: while one contracts, the other generates.  (Without the middle barrier
-        // the contracting wave, which only issues its MFMAs, runs ahead into its own generation
-        // phase while the other still generates; the two generators then share the VALU and the
-        // second contraction runs alone.)
-        if (group == 0) {
-            // fetch the next chunk's records before the MFMAs; they are used in phase 2
-            if (more) rec = load_rec(c + 1);
-            fwd_mma<X3>(cur, ox, oy, acc);
-        } else {
-            if (more) fwd_gen<X3>(rec, f0, nxt + aoff, nxt + aoff + FARR, gt);
-        }
-        lds_barrier();
-        if (group == 0) {
-            if (more) fwd_gen<X3>(rec, f0, nxt + aoff, nxt + aoff + FARR, gt);
-        } else {
-            // fetch the records of the chunk after next before the MFMAs
-            if (c + 2 < c_end) rec = load_rec(c + 2);
-            fwd_mma<X3>(cur, ox, oy, acc);
-        }
-        lds_barrier();
-    }
-
-    float *out = part + (size_t)split * (size_t)Mu * (size_t)Mp;
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int u = tu0 + wu + 32 * a + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const int p = tp0 + wp + 32 * b + (lane & 31);
-                if (u < Mu && p < Mp) out[(size_t)u * Mp + p] = acc[a][b][r];
-            }
-}
 
 // ------------------------------------------------------------------------------------------------
 // Forward, one wave per SIMD: 256 threads = 4 waves; wave w owns the 128 x 128 output sub-tile
@@ -470,8 +383,9 @@ struct RunStages {
     float v[32];
     unsigned h[16], l[16], hah[16], hbh[16];
 
-    // Stage ST of the run starting at frequency u0, block row k, run r, stored into arr_h / arr_l.
-    template <int ST>
+    // Stage ST of the run starting at frequency u0, block row k, run r, stored into arr_h / arr_l
+    // (X3 false: the hi halves alone, stored into arr_h).
+    template <int ST, bool X3 = true>
     __device__ __forceinline__ void stage(int u0, char *arr_h, char *arr_l, int k, int r) {
         constexpr int st = ST;
         if constexpr (st == 0) {
@@ -487,17 +401,20 @@ struct RunStages {
             constexpr int q = (st - 1) >> 1;
             if constexpr (((st - 1) & 1) == 0) {
                 h[q] = pack_bf16(v[2 * q], v[2 * q + 1]);
-                asm("" : "+v"(h[q]));   // keeps the shift below on h (else it re-converts v[2q] alone)
-                hah[q] = h[q] << 16;
-                hbh[q] = h[q] & 0xffff0000u;
-            } else {
+                if constexpr (X3) {
+                    asm("" : "+v"(h[q]));   // keeps the shift below on h (else it re-converts v[2q] alone)
+                    hah[q] = h[q] << 16;
+                    hbh[q] = h[q] & 0xffff0000u;
+                }
+            } else if constexpr (X3) {
                 l[q] = split_lo(v[2 * q], v[2 * q + 1], hah[q], hbh[q]);
             }
         }
         if constexpr (st >= 8 && (st & 7) == 0) {
             constexpr int m = (st - 8) >> 3;
             *(u32x4 *)(arr_h + fswz(k, 4 * r + m)) = u32x4{h[4 * m], h[4 * m + 1], h[4 * m + 2], h[4 * m + 3]};
-            *(u32x4 *)(arr_l + fswz(k, 4 * r + m)) = u32x4{l[4 * m], l[4 * m + 1], l[4 * m + 2], l[4 * m + 3]};
+            if constexpr (X3)
+                *(u32x4 *)(arr_l + fswz(k, 4 * r + m)) = u32x4{l[4 * m], l[4 * m + 1], l[4 * m + 2], l[4 * m + 3]};
         }
     }
     static constexpr int kStages = 33;
@@ -606,16 +523,75 @@ __device__ __forceinline__ void fwd1_chunk(char *smem, const OpBase &ox, const O
     fwd1_slots<B>(c, std::make_integer_sequence<int, 96>{});
 }
 
+// One-product chunk (plain bf16, and the one-product tiles of the mixed split): 2 K steps of 16
+// MFMA slots (hi*hi over the 16 accumulator tiles, a-major).  Step-1 operands are read at slots 4-11;
+// the 33 stages (hi halves only) of the X run and of the Y run spread together over slots 0-27,
+// so that every slot holds independent recurrence chains of both runs (one run's stages depend on
+// each other, and a slot holding two of them would wait for the VALU latency in between); the
+// barrier follows slot 27; the next chunk's first five step-0 operands are read in slots 28-31 and
+// the other three in slots 0-2 of their own chunk, each before its first use.
+constexpr int kPlainRunSlots = 28;
+constexpr int plain_stage_slot(int st) { return st * kPlainRunSlots / RunStages::kStages; }
+static_assert(plain_stage_slot(RunStages::kStages - 1) < kPlainRunSlots, "plain stage plan");
+
+template <int I, int N, int... S>
+__device__ __forceinline__ void fwd1p_stages(Fwd1Ctx &c, std::integer_sequence<int, S...>) {
+    ((plain_stage_slot(S) == I ? (c.gx.template stage<S, false>(c.ux, c.smem + F1_XH(N), nullptr, c.k, c.r),
+                                  c.gy.template stage<S, false>(c.uy, c.smem + F1_YH(N), nullptr, c.k, c.r))
+                               : void()), ...);
+}
+
+template <int I, int B>
+__device__ __forceinline__ void fwd1p_slot(Fwd1Ctx &c) {
+    constexpr int N = 1 - B;
+    if constexpr (I < 16) fwd1_mfma<I>(c.o0, c.acc);
+    else fwd1_mfma<I - 16>(c.o1, c.acc);
+    if constexpr (I >= 4 && I < 12) fwd1_read<1, I - 4, B>(c.smem, c.ox, c.oy, c.o1);
+    if constexpr (I < kPlainRunSlots) fwd1p_stages<I, N>(c, std::make_integer_sequence<int, RunStages::kStages>{});
+    if constexpr (I == kPlainRunSlots - 1) lds_barrier();
+    if constexpr (I >= 28 && I <= 30) fwd1_read<0, I - 28, N>(c.smem, c.ox, c.oy, c.o0);
+    if constexpr (I == 31) {
+        fwd1_read<0, 3, N>(c.smem, c.ox, c.oy, c.o0);
+        fwd1_read<0, 4, N>(c.smem, c.ox, c.oy, c.o0);
+    }
+    if constexpr (I <= 2) fwd1_read<0, 5 + I, B>(c.smem, c.ox, c.oy, c.o0);
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int B, int... I>
+__device__ __forceinline__ void fwd1p_slots(Fwd1Ctx &c, std::integer_sequence<int, I...>) {
+    (fwd1p_slot<I, B>(c), ...);
+}
+
+template <bool X3, int B>
+__device__ __forceinline__ void fwd1_chunk_any(char *smem, const OpBase &ox, const OpBase &oy, f32x16 (&acc)[4][4],
+                                               RunStages &gx, RunStages &gy, FwdOps1 &o0, int ux, int uy, int k,
+                                               int r) {
+    if constexpr (X3) {
+        fwd1_chunk<B>(smem, ox, oy, acc, gx, gy, o0, ux, uy, k, r);
+    } else {
+        FwdOps1 o1;
+        Fwd1Ctx c{smem, ox, oy, acc, gx, gy, o0, o1, ux, uy, k, r};
+        fwd1p_slots<B>(c, std::make_integer_sequence<int, 32>{});
+    }
+}
+
+// X3: three products per pair (hi*hi, lo*hi, hi*lo); otherwise one (hi*hi).  skip_u x skip_p: the
+// tiles of that low-frequency corner are left to another launch (the mixed split contracts them
+// with three products); 0 x 0 skips nothing.
+template <bool X3>
 __global__ __launch_bounds__(256) void k_fwd1_bf16(int64_t n, int Mu, int Mp, const PhaseRec *__restrict__ tx,
                                                    const PhaseRec *__restrict__ ty, const RunSeed *__restrict__ sx,
                                                    const RunSeed *__restrict__ sy, float *__restrict__ part,
-                                                   int tiles_p, int64_t chunks, int64_t chunks_per_split) {
+                                                   int tiles_p, int64_t chunks, int64_t chunks_per_split, int skip_u,
+                                                   int skip_p) {
     __shared__ __attribute__((aligned(16))) char smem[2 * FBUF];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t rows = phase_rows(n);
     int tile;
     int64_t split;
     fwd_tile_split(tile, split);
+    if (tile / tiles_p < skip_u && tile % tiles_p < skip_p) return;   // the whole workgroup, before any barrier
     const int tu0 = (tile / tiles_p) * FT, tp0 = (tile % tiles_p) * FT;
     const int wu = 128 * (wave >> 1), wp = 128 * (wave & 1);
     const int64_t c_begin = split * chunks_per_split;
@@ -644,8 +620,8 @@ __global__ __launch_bounds__(256) void k_fwd1_bf16(int64_t n, int Mu, int Mp, co
     auto recx = [&](int64_t ch) { return load_gen(tx, sx, rows, runx, ch * FKB + kk); };
     auto recy = [&](int64_t ch) { return load_gen(ty, sy, rows, runy, ch * FKB + kk); };
     if (c_begin < c_end) {
-        fwd_gen<true>(recx(c_begin), tu0, smem + F1_XH(0), smem + F1_XL(0), tid);
-        fwd_gen<true>(recy(c_begin), tp0, smem + F1_YH(0), smem + F1_YL(0), tid);
+        fwd_gen<X3>(recx(c_begin), tu0, smem + F1_XH(0), smem + F1_XL(0), tid);
+        fwd_gen<X3>(recy(c_begin), tp0, smem + F1_YH(0), smem + F1_YL(0), tid);
     }
     // Two record sets alternate: the chunk at even offset from c_begin generates from set B and
     // fetches the records of the chunk after next into set A, the chunk at odd offset the reverse.
@@ -668,12 +644,12 @@ __global__ __launch_bounds__(256) void k_fwd1_bf16(int64_t n, int Mu, int Mp, co
     for (; c + 1 < c_end; c += 2) {
         gxA.R = recx(c + 2);
         gyA.R = recy(c + 2);
-        fwd1_chunk<0>(smem, ox, oy, acc, gxB, gyB, o0, ux, uy, kk, rr);
+        fwd1_chunk_any<X3, 0>(smem, ox, oy, acc, gxB, gyB, o0, ux, uy, kk, rr);
         gxB.R = recx(c + 3);
         gyB.R = recy(c + 3);
-        fwd1_chunk<1>(smem, ox, oy, acc, gxA, gyA, o0, ux, uy, kk, rr);
+        fwd1_chunk_any<X3, 1>(smem, ox, oy, acc, gxA, gyA, o0, ux, uy, kk, rr);
     }
-    if (c < c_end) fwd1_chunk<0>(smem, ox, oy, acc, gxB, gyB, o0, ux, uy, kk, rr);
+    if (c < c_end) fwd1_chunk_any<X3, 0>(smem, ox, oy, acc, gxB, gyB, o0, ux, uy, kk, rr);
 
     float *out = part + (size_t)split * (size_t)Mu * (size_t)Mp;
 #pragma unroll
@@ -1531,10 +1507,10 @@ hipError_t launch_fwd_bf16(const FwdPlan &pl, bool x3, int64_t n, int Mu, int Mp
     if (pl.tu != FT || pl.tp != FT || pl.kb != FKB) return hipErrorInvalidValue;
     dim3 grid(pl.tiles_u * pl.tiles_p, pl.splits);
     if (x3)
-        hipLaunchKernelGGL(k_fwd1_bf16, grid, dim3(256), 0, s, n, Mu, Mp, tx, ty, sx, sy, part, pl.tiles_p, pl.chunks,
-                           pl.chunks_per_split);
+        hipLaunchKernelGGL(k_fwd1_bf16<true>, grid, dim3(256), 0, s, n, Mu, Mp, tx, ty, sx, sy, part, pl.tiles_p,
+                           pl.chunks, pl.chunks_per_split, 0, 0);
     else
-        hipLaunchKernelGGL(k_fwd_bf16<false>, grid, dim3(512), 0, s, n, Mu, Mp, tx, ty, sx, sy, part, pl.tiles_p,
+        hipLaunchKernelGGL(k_fwd1_bf16<false>, grid, dim3(256), 0, s, n, Mu, Mp, tx, ty, sx, sy, part, pl.tiles_p,
                            pl.chunks, pl.chunks_per_split, 0, 0);
     return hipGetLastError();
 }
@@ -1546,10 +1522,10 @@ hipError_t launch_fwd_bf16_mix(const FwdPlan &pl, int rx, int ry, int64_t n, int
     // the rx x ry low-frequency tiles with three products (a grid over that corner alone: tiles_p = ry
     // maps its tile index to the same (u, p) tile), then every other tile with one; both write the
     // same split-K partials, so the reduction is unchanged
-    hipLaunchKernelGGL(k_fwd1_bf16, dim3(rx * ry, pl.splits), dim3(256), 0, s, n, Mu, Mp, tx, ty, sx, sy, part, ry,
-                       pl.chunks, pl.chunks_per_split);
+    hipLaunchKernelGGL(k_fwd1_bf16<true>, dim3(rx * ry, pl.splits), dim3(256), 0, s, n, Mu, Mp, tx, ty, sx, sy, part,
+                       ry, pl.chunks, pl.chunks_per_split, 0, 0);
     if (rx < pl.tiles_u || ry < pl.tiles_p)
-        hipLaunchKernelGGL(k_fwd_bf16<false>, dim3(pl.tiles_u * pl.tiles_p, pl.splits), dim3(512), 0, s, n, Mu, Mp, tx,
+        hipLaunchKernelGGL(k_fwd1_bf16<false>, dim3(pl.tiles_u * pl.tiles_p, pl.splits), dim3(256), 0, s, n, Mu, Mp, tx,
                            ty, sx, sy, part, pl.tiles_p, pl.chunks, pl.chunks_per_split, rx, ry);
     return hipGetLastError();
 }
