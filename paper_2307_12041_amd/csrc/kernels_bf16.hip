@@ -215,7 +215,7 @@ __device__ __forceinline__ void gen32(const GenRec &R, int u0, float (&v)[32]) {
     start_run(R, ca, sb);
     v[0] = ca.f * sb.f;
 #pragma unroll
-    for (int j = 1; j < 32; ++j) v[j] = ca.next1() * sb.next();
+    for (int j = 1; j < 32; ++j) v[j] = ca.next1() * sb.next1();
     if (u0 == 0) v[0] = R.size;
 }
 
@@ -392,9 +392,9 @@ struct RunStages {
             start_run(R, C, S);
             v[0] = C.f * S.f;
             if (u0 == 0) v[0] = R.size;
-            v[1] = C.next1() * S.next();
+            v[1] = C.next1() * S.next1();
         } else if constexpr (st <= 30) {
-            v[st + 1] = C.next1() * S.next();
+            v[st + 1] = C.next1() * S.next1();
         }
         // split of pair q: hi at stage 2q + 1, lo at 2q + 2
         if constexpr (st >= 1 && st <= 32) {
@@ -788,8 +788,8 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
         } else {
             v[0] = ca.f * sb.f;
 #pragma unroll
-            for (int e = 1; e < 8; ++e) v[e] = ca.next1() * sb.next();
-            ca.next1(); sb.next();
+            for (int e = 1; e < 8; ++e) v[e] = ca.next1() * sb.next1();
+            ca.next1(); sb.next1();
             v[0] = kcur == 0 ? size0 : v[0];
         }
         kcur += 8;
@@ -969,13 +969,12 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
 
 // A-operand generator of one 32-block subtile: recurrence state and the 32-frequency phasors (see
 // k_bwd_bf16), with the values and split halves of the step being generated.  The generator's
-// work is cut into pieces of at most three VALU instructions (a value and the first FMA of the
-// beta recurrence; the FMAs that advance both recurrences; one half of a hi/lo split; half of a
-// phasor jump), so that the pieces can be dealt over the MFMA slots evenly.
+// work is cut into pieces of at most three VALU instructions (a value; the FMAs that advance both
+// recurrences; one half of a hi/lo split; half of a phasor jump), so that the pieces can be dealt
+// over the MFMA slots evenly.
 template <int KA>
 struct AGen {
     Cheb ca, sb;
-    float ts;                     // first FMA of the beta recurrence in flight
     float pac, pas, pbc, pbs, jac, jas, jbc, jbs, sac, sas, sbc, sbs, size0;
     float tj0, tj1;               // phasor jump in flight
     float v[8];
@@ -1020,7 +1019,6 @@ struct AGen {
         } else {
             v[E] = ca.f * sb.f;
             if constexpr (E == 0 && FIRST0) v[0] = size0;
-            ts = fmaf(sb.cl, sb.f, -sb.fm);
         }
     }
     // The second FMAs: the recurrences advance by one frequency.
@@ -1029,7 +1027,7 @@ struct AGen {
         ca.fm = ca.f;
         ca.f = nc;
         if constexpr (KA != RUN_COS) {
-            const float ns = fmaf(sb.ch, sb.f, ts);
+            const float ns = fmaf(sb.ch, sb.f, -sb.fm);
             sb.fm = sb.f;
             sb.f = ns;
         }

@@ -192,7 +192,7 @@ struct Gen8 {
             if constexpr (KA == RUN_COS) {
                 v[e] = (P == 0 && e == 0) ? ca.f : ca.next1();
             } else {
-                v[e] = (P == 0 && e == 0) ? ca.f * sb.f : ca.next1() * sb.next();
+                v[e] = (P == 0 && e == 0) ? ca.f * sb.f : ca.next1() * sb.next1();
             }
         }
         split4(v[0], v[1], v[2], v[3], hi[2 * P], lo[2 * P]);
@@ -458,7 +458,7 @@ __device__ __forceinline__ void gen_run8(const Rec8 &R, bool first, int e0, char
     float v[32];
     v[0] = first ? ldexpf(R.size, -e0) : C.f * S.f;
 #pragma unroll
-    for (int e = 1; e < 32; ++e) v[e] = C.next1() * S.next();
+    for (int e = 1; e < 32; ++e) v[e] = C.next1() * S.next1();
     unsigned hi[8], lo[8];
 #pragma unroll
     for (int g = 0; g < 8; ++g) {
