@@ -239,15 +239,13 @@ def main():
     alg_flops = 2.0 * pairs                  # one contraction: 2 flops per (block, u, p)
     achieved = alg_flops / (avg_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
-    if args.precision == "bf16x3" and args.basis == "recompute":
-        kernel_name = {"fwd": "k_fwd1_bf16 (coefficient contraction)",
-                       "bwd": "k_bwd1_bf16 (gradient contraction, gx and gy launches)"}[dom]
-    elif args.precision == "bf16x3":
-        kernel_name = {"fwd": "k_fwd_bf16_st<x3> (coefficient contraction)",
-                       "bwd": "k_bwd_bf16<x3, store> (gradient contraction, gx and gy launches)"}[dom]
+    X = "x3" if args.precision == "bf16x3" else "plain"
+    if args.basis == "recompute":
+        kernel_name = {"fwd": f"k_fwd1_bf16<{X}> (coefficient contraction)",
+                       "bwd": f"k_bwd1_bf16<{X}> (gradient contraction, gx and gy launches)"}[dom]
     else:
-        kernel_name = {"fwd": "k_fwd_bf16<plain> (coefficient contraction)",
-                       "bwd": "k_bwd_bf16<plain> (gradient contraction, gx and gy launches)"}[dom]
+        kernel_name = {"fwd": f"k_fwd_bf16_st<{X}> (coefficient contraction)",
+                       "bwd": f"k_bwd_bf16_st<{X}> (gradient contraction, gx and gy launches)"}[dom]
     if args.precision in ("fp64", "fp32"):
         T = "double" if args.precision == "fp64" else "float"
         kernel_name = {"fwd": f"k_fwd_mat<{T}>", "bwd": f"k_bwd_mat<{T}>"}[dom]

@@ -666,12 +666,11 @@ __global__ __launch_bounds__(256) void k_fwd1_bf16(int64_t n, int Mu, int Mp, co
 
 // ================================================================================================
 // Backward: G[i][nn] = sum_k A_ik B[k][nn], g_i = sum_nn E_i,nn G[i][nn].
-// Kernels: k_bwd1_bf16 (x3 with the basis regenerated, one wave per SIMD, further below) and
-// k_bwd_bf16 (plain bf16, and the store mode of both bf16 types, here).
-// k_bwd_bf16: 512 threads = 8 waves; wave w owns blocks i0 + 32 w .. + 31 and all 256 columns of the N tile.
-// A (sine differences along the K axis) is generated in registers directly in MFMA operand
-// layout: lane half h = lane / 32 walks frequencies h * Kh + 8 t (t = 0, 1, ...), so each lane's
-// recurrence runs over contiguous frequencies.  B is staged per chunk of 32 + 32 frequencies
+// Kernels: k_bwd1_bf16 (the basis regenerated, one wave per SIMD, three products or one, further
+// below) and k_bwd_bf16_st (the store mode of both bf16 types, A read from the stored table, here).
+// A (sine differences along the K axis) is held in MFMA operand layout: lane half h = lane / 32
+// walks frequencies h * Kh + 8 t (t = 0, 1, ...), so each lane's recurrence (or table row) runs over
+// contiguous frequencies.  B is staged per chunk of 32 + 32 frequencies
 // (4 K steps) in LDS by direct global->LDS copies: the global operand is pre-tiled in exactly the
 // LDS byte order, one contiguous 64 KB block (hi then lo) per (N tile, chunk), rows of 128 bytes
 // whose 16-byte segments are XOR-swizzled by (row / 2) % 8: any 16 consecutive rows then cover all
@@ -704,69 +703,25 @@ __device__ __forceinline__ float ep_value(float ca, float sa, float cb, float sb
     else return (float)nn * pil * sa;
 }
 
-// KA: kind of the K-axis basis (RUN_SINDIFF or RUN_COS); E1, E2: kinds of the first and (if E2 >= 0)
-// second epilogue (see RunKind).  The gradient is <SINDIFF, COSDIFF, -1>.
-template <bool X3, bool ST, int KA, int E1, int E2>
-__global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
+// Gradient contraction from the stored basis (store mode): G[i][nn] = sum_k S_ik B[k][nn] with S read
+// from its table, then the cosine-difference row dot.  512 threads = 8 waves, wave w owning blocks
+// i0 + 32 w .. + 31 and all 256 columns of the N tile (8 accumulator tiles).
+template <bool X3>
+__global__ __launch_bounds__(512) void k_bwd_bf16_st(int64_t n, BwdAxisBf16 ax) {
     __shared__ __attribute__((aligned(16))) char smem[2 * BBUF];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, j = lane & 31;
-    int btile, ntile;
-    if constexpr (ST) {
-        // One-dimensional grid, workgroups dealt round-robin over the 8 XCDs: the N tiles of one
-        // block tile go to the same XCD at about the same time, so they share its L2 copy of the
-        // block tile's table rows.
-        const int w = blockIdx.x, xcd = w & 7, slot = w >> 3;
-        btile = xcd + 8 * (slot / ax.tiles_n);
-        ntile = slot % ax.tiles_n;
-        if (btile >= ax.tiles_b) return;
-    } else {
-        btile = blockIdx.x;
-        ntile = blockIdx.y + ax.nt0;
-    }
+    // One-dimensional grid, workgroups dealt round-robin over the 8 XCDs: the N tiles of one block
+    // tile go to the same XCD at about the same time, so they share its L2 copy of the block tile's
+    // table rows.
+    const int w = blockIdx.x, xcd = w & 7, slot = w >> 3;
+    const int btile = xcd + 8 * (slot / ax.tiles_n);
+    const int ntile = slot % ax.tiles_n;
+    if (btile >= ax.tiles_b) return;
     const int64_t i0 = (int64_t)btile * 256 + 32 * wave;
     const int n0 = ntile * BTN;
     const int64_t ib = i0 + j;        // this lane's block for the A operand
-    const bool valid = ib < n;
     const int Q = ax.Kh / 32;         // chunks along K
-
-    // A-operand recurrence state (basis along the K axis).  Two fp32 phasors of the current
-    // frequency, e^{i pi kcur ta} and e^{i pi kcur tb}, are seeded once in FP64 and advanced by the
-    // 32-frequency phasors of the phase record at every reseed, so the K loop makes no memory
-    // access and no FP64 reduction for its seeds (drift after 64 jumps ~1e-6).
-    Cheb ca, sb;
-    int kcur = h * ax.Kh;             // next frequency this lane generates
-    float pac, pas, pbc, pbs;         // phasors at kcur
-    float jac, jas, jbc, jbs;         // 32-frequency jumps
-    float sac, sas, sbc, sbs;         // one-frequency steps (for the k - 1 terms)
-    float size0 = 0.0f;
-    if (!ST && valid) {
-        const PhaseRec RA = ax.ta[ib];
-        seed_phasor(kcur, RA.ta, pac, pas);
-        seed_phasor(kcur, RA.tb, pbc, pbs);
-        jac = RA.ca32; jas = RA.sa32; jbc = RA.cb32; jbs = RA.sb32;
-        sac = RA.ca; sas = RA.sa; sbc = RA.cb; sbs = RA.sb;
-        ca.ch = RA.c2ah; ca.cl = RA.c2al; sb.ch = RA.c2bh; sb.cl = RA.c2bl;
-        size0 = RA.size;
-    } else {
-        pac = pas = pbc = pbs = jac = jas = jbc = jbs = sac = sas = sbc = sbs = 0.0f;
-        ca.ch = ca.cl = sb.ch = sb.cl = 0.0f;
-    }
-    auto reseed = [&]() {
-        ca.f = pac;
-        ca.fm = pac * sac + pas * sas;                // cos((k - 1) alpha)
-        sb.f = 2.0f * pbs;                            // 2 sin(k beta)
-        sb.fm = 2.0f * (pbs * sbc - pbc * sbs);       // 2 sin((k - 1) beta)
-    };
-    auto jump = [&]() {
-        float t = pac * jac - pas * jas;
-        pas = pas * jac + pac * jas;
-        pac = t;
-        t = pbc * jbc - pbs * jbs;
-        pbs = pbs * jbc + pbc * jbs;
-        pbc = t;
-    };
-    reseed();
 
     f32x16 acc[8];
 #pragma unroll
@@ -776,32 +731,6 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
 
     const size_t tile_elems = (size_t)BBUF / 2;      // bf16 elements per chunk tile (hi + lo)
     const unsigned short *gb = ax.B + (size_t)ntile * Q * tile_elems;
-
-    // A operand of one K step (8 consecutive frequencies of this lane's block), split hi/lo.
-    auto gen_a = [&](bf16x8 &ah, bf16x8 &al) {
-        float v[8];
-        if constexpr (KA == RUN_COS) {
-            v[0] = ca.f;
-#pragma unroll
-            for (int e = 1; e < 8; ++e) v[e] = ca.next1();
-            ca.next1();
-        } else {
-            v[0] = ca.f * sb.f;
-#pragma unroll
-            for (int e = 1; e < 8; ++e) v[e] = ca.next1() * sb.next1();
-            ca.next1(); sb.next1();
-            v[0] = kcur == 0 ? size0 : v[0];
-        }
-        kcur += 8;
-        unsigned hh[4], ll[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            if (X3) split2(v[2 * m], v[2 * m + 1], hh[m], ll[m]);
-            else hh[m] = pack_bf16(v[2 * m], v[2 * m + 1]);
-        }
-        ah = __builtin_bit_cast(bf16x8, u32x4{hh[0], hh[1], hh[2], hh[3]});
-        if (X3) al = __builtin_bit_cast(bf16x8, u32x4{ll[0], ll[1], ll[2], ll[3]});
-    };
 
     // One K step: B operands (row 32 b + j, logical segment 4 h + s, physical segment XORed with
     // (j / 2) % 8) and the three MFMA passes over the 8 accumulators.
@@ -824,94 +753,49 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
         }
     };
 
-    if constexpr (ST) {
-        // A from the stored basis table: row ib, frequencies h Kh + 32 q + 8 s + 0..7 for step s of
-        // chunk q (rows past n are zero).  The next chunk's operands are requested before its B
-        // copies, a whole chunk ahead of their use.
-        const unsigned short *rh = ax.tab_h + (size_t)ib * (size_t)ax.tab_ld + h * ax.Kh;
-        const unsigned short *rl = ax.tab_l + (size_t)ib * (size_t)ax.tab_ld + h * ax.Kh;
-        bf16x8 cah[4], cal[4], nah[4], nal[4];
-        auto load_a = [&](int q, bf16x8 (&dh)[4], bf16x8 (&dl)[4]) {
+    // A from the stored basis table: row ib, frequencies h Kh + 32 q + 8 s + 0..7 for step s of chunk
+    // q (rows past n are zero).  The next chunk's operands are requested before its B copies, a whole
+    // chunk ahead of their use.
+    const unsigned short *rh = ax.tab_h + (size_t)ib * (size_t)ax.tab_ld + h * ax.Kh;
+    const unsigned short *rl = ax.tab_l + (size_t)ib * (size_t)ax.tab_ld + h * ax.Kh;
+    bf16x8 cah[4], cal[4], nah[4], nal[4];
+    auto load_a = [&](int q, bf16x8 (&dh)[4], bf16x8 (&dl)[4]) {
 #pragma unroll
-            for (int st = 0; st < 4; ++st) {
-                dh[st] = *(const bf16x8 *)(rh + 32 * q + 8 * st);
-                if (X3) dl[st] = *(const bf16x8 *)(rl + 32 * q + 8 * st);
-            }
-        };
-        load_a(0, cah, cal);
-        bwd_copy_b(gb, smem, tid);
-        wait_copies();
-        __syncthreads();
-        for (int q = 0; q < Q; ++q) {
-            char *cur = smem + (q & 1) * BBUF, *nxt = smem + ((q & 1) ^ 1) * BBUF;
-            if (q + 1 < Q) {
-                load_a(q + 1, nah, nal);
-                bwd_copy_b(gb + (size_t)(q + 1) * tile_elems, nxt, tid);
-            }
-#pragma unroll
-            for (int st = 0; st < 4; ++st) mma_step(cur, st, cah[st], cal[st]);
-            wait_copies();
-            __syncthreads();
-#pragma unroll
-            for (int st = 0; st < 4; ++st) {
-                cah[st] = nah[st];
-                if (X3) cal[st] = nal[st];
-            }
+        for (int st = 0; st < 4; ++st) {
+            dh[st] = *(const bf16x8 *)(rh + 32 * q + 8 * st);
+            if (X3) dl[st] = *(const bf16x8 *)(rl + 32 * q + 8 * st);
         }
-    } else {
-        // Two wave groups in opposite roles, two phases per chunk separated by barriers: while the
-        // waves of one group contract (A in registers, B from LDS), the waves of the other generate
-        // their A operands for the chunk they contract next, so on every SIMD one wave issues
-        // MFMAs while the other issues the generator's VALU work.  Group 0 (waves 0-3) contracts
-        // chunk q in phase 1 and generates chunk q + 1 in phase 2; group 1 generates chunk q in
-        // phase 1 and contracts it in phase 2.
-        const int group = wave >> 2;
-        bf16x8 Ah[4], Al[4];
-        auto gen_chunk = [&]() {
+    };
+    load_a(0, cah, cal);
+    bwd_copy_b(gb, smem, tid);
+    wait_copies();
+    __syncthreads();
+    for (int q = 0; q < Q; ++q) {
+        char *cur = smem + (q & 1) * BBUF, *nxt = smem + ((q & 1) ^ 1) * BBUF;
+        if (q + 1 < Q) {
+            load_a(q + 1, nah, nal);
+            bwd_copy_b(gb + (size_t)(q + 1) * tile_elems, nxt, tid);
+        }
 #pragma unroll
-            for (int st = 0; st < 4; ++st) gen_a(Ah[st], Al[st]);
-            // the next chunk starts 32 frequencies later: advance the phasors, reseed
-            jump();
-            reseed();
-        };
-        if (group == 0) gen_chunk();
-        bwd_copy_b(gb, smem, tid);
+        for (int st = 0; st < 4; ++st) mma_step(cur, st, cah[st], cal[st]);
         wait_copies();
         __syncthreads();
-        // The next chunk's B tile is copied from the start of the chunk; the middle barrier orders
-        // LDS only, so the copies stay in flight until the wait before the chunk's last barrier.
-        for (int q = 0; q < Q; ++q) {
-            char *cur = smem + (q & 1) * BBUF, *nxt = smem + ((q & 1) ^ 1) * BBUF;
-            if (q + 1 < Q) bwd_copy_b(gb + (size_t)(q + 1) * tile_elems, nxt, tid);
-            if (group == 0) {
 #pragma unroll
-                for (int st = 0; st < 4; ++st) mma_step(cur, st, Ah[st], Al[st]);
-            } else {
-                gen_chunk();
-            }
-            lds_barrier();
-            if (group == 0) {
-                if (q + 1 < Q) gen_chunk();
-            } else {
-#pragma unroll
-                for (int st = 0; st < 4; ++st) mma_step(cur, st, Ah[st], Al[st]);
-            }
-            wait_copies();
-            lds_barrier();
+        for (int st = 0; st < 4; ++st) {
+            cah[st] = nah[st];
+            if (X3) cal[st] = nal[st];
         }
     }
 
-    // Epilogue: lane holds G for rows 8 (r / 4) + 4 h + r % 4 and columns n0 + 32 b + j.
-    // E = -2 sin(nn alpha) sin(nn beta) of the epilogue axis, stepped by 32 columns.
-    // The E2 epilogue (if any) shares the phasors with E1.
-    constexpr bool DUAL = E2 >= 0;
-    // each lane sums its 8 columns of a row in FP32; the 32 lanes of the row add in FP64
-    double rs[16], rs2[16];
+    // Epilogue: lane holds G for rows 8 (r / 4) + 4 h + r % 4 and columns n0 + 32 b + j;
+    // E = -2 sin(nn alpha) sin(nn beta) of the epilogue axis, stepped by 32 columns.  Each lane sums
+    // its 8 columns of a row in FP32; the 32 lanes of the row add in FP64.
+    double rs[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int row = 8 * (r >> 2) + 4 * h + (r & 3);
         const int64_t ibe = i0 + row;
-        float sum = 0.0f, sum2 = 0.0f;
+        float sum = 0.0f;
         if (ibe < n) {
             const PhaseRec RE = ax.te[ibe];
             const int nn = n0 + j;
@@ -920,10 +804,7 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
             seed_phasor(nn, RE.tb, cb0, sb0);
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
-                sum = fmaf(ep_value<E1>(ca0, sa0, cb0, sb0, nn + 32 * b, RE.size, ax.pil), acc[b][r], sum);
-                if constexpr (DUAL)
-                    sum2 = fmaf(ep_value<(DUAL ? E2 : 0)>(ca0, sa0, cb0, sb0, nn + 32 * b, RE.size, ax.pil), acc[b][r],
-                                sum2);
+                sum = fmaf(ep_value<RUN_COSDIFF>(ca0, sa0, cb0, sb0, nn + 32 * b, RE.size, ax.pil), acc[b][r], sum);
                 const float ta = ca0 * RE.ca32 - sa0 * RE.sa32;
                 sa0 = sa0 * RE.ca32 + ca0 * RE.sa32;
                 ca0 = ta;
@@ -933,29 +814,24 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
             }
         }
         rs[r] = sum;
-        rs2[r] = sum2;
     }
-    auto reduce_store = [&](double (&x)[16], double *__restrict__ gp) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        double v = rs[r];
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        v += __shfl_xor(v, 8);
+        v += __shfl_xor(v, 16);
+        rs[r] = v;
+    }
+    if (j == 0) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            double v = x[r];
-            v += __shfl_xor(v, 1);
-            v += __shfl_xor(v, 2);
-            v += __shfl_xor(v, 4);
-            v += __shfl_xor(v, 8);
-            v += __shfl_xor(v, 16);
-            x[r] = v;
+            const int64_t ibe = i0 + 8 * (r >> 2) + 4 * h + (r & 3);
+            if (ibe < n) ax.gpart[(size_t)ntile * (size_t)n + (size_t)ibe] = rs[r];
         }
-        if (j == 0) {
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t ibe = i0 + 8 * (r >> 2) + 4 * h + (r & 3);
-                if (ibe < n) gp[(size_t)ntile * (size_t)n + (size_t)ibe] = x[r];
-            }
-        }
-    };
-    reduce_store(rs, ax.gpart);
-    if constexpr (DUAL) reduce_store(rs2, ax.gpart2);
+    }
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -967,8 +843,10 @@ __global__ __launch_bounds__(512) void k_bwd_bf16(int64_t n, BwdAxisBf16 ax) {
 // into the buffer just released.
 // ------------------------------------------------------------------------------------------------
 
-// A-operand generator of one 32-block subtile: recurrence state and the 32-frequency phasors (see
-// k_bwd_bf16), with the values and split halves of the step being generated.  The generator's
+// A-operand generator of one 32-block subtile: recurrence state and two fp32 phasors of the current
+// frequency, e^{i pi k ta} and e^{i pi k tb}, seeded once in FP64 and advanced by the record's
+// 32-frequency phasors at every reseed (no memory access and no FP64 reduction in the K loop; drift
+// after 64 jumps ~1e-6), with the values and split halves of the step being generated.  The generator's
 // work is cut into pieces of at most three VALU instructions (a value; the FMAs that advance both
 // recurrences; one half of a hi/lo split; half of a phasor jump), so that the pieces can be dealt
 // over the MFMA slots evenly.
@@ -1325,7 +1203,8 @@ __global__ __launch_bounds__(256) void k_bwd1_bf16(int64_t n, BwdAxisBf16 ax) {
 
 // Row-form operand preparation for the bf16 path: BT[nn][k] = a_up times the factor of the form
 // (gradient: 1 / scale of the K axis; potentials: 1 / (wt_u vt_p); point field: 1),
-// split into bf16 hi and lo, zero padded, and tiled exactly in the LDS byte order of k_bwd_bf16:
+// split into bf16 hi and lo, zero padded, and tiled exactly in the LDS byte order of the gradient
+// contractions (k_bwd1_bf16, k_bwd_bf16_st):
 // tile (n_tile, q) = [hi | lo][256 rows][8 segments of 8 values], the 16-byte segment of logical
 // index seg stored at seg ^ ((row / 2) % 8); logical segment seg = 4 half + s holds
 // k = half * Kh + 32 q + 8 s + e (e = 0..7).
@@ -1559,8 +1438,8 @@ hipError_t launch_bwd_bf16(RowForm f, bool x3, int64_t n, const BwdAxisBf16 &ax,
             ax.tab_ld < 2 * ax.Kh || (x3 && !ax.tab_l))
             return hipErrorInvalidValue;
         const unsigned g = (unsigned)((ax.tiles_b + 7) / 8 * 8 * ax.tiles_n);
-        if (x3) hipLaunchKernelGGL((k_bwd_bf16<true, true, RUN_SINDIFF, RUN_COSDIFF, -1>), dim3(g), dim3(512), 0, s, n, ax);
-        else hipLaunchKernelGGL((k_bwd_bf16<false, true, RUN_SINDIFF, RUN_COSDIFF, -1>), dim3(g), dim3(512), 0, s, n, ax);
+        if (x3) hipLaunchKernelGGL(k_bwd_bf16_st<true>, dim3(g), dim3(512), 0, s, n, ax);
+        else hipLaunchKernelGGL(k_bwd_bf16_st<false>, dim3(g), dim3(512), 0, s, n, ax);
         return hipGetLastError();
     }
     switch (f) {
