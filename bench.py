@@ -127,6 +127,51 @@ def measured_mfma(workload, precision):
     return rec.get("kernels")
 
 
+def library_gemm(torch, dev, wl, stages, args, max_operand_bytes=20 * 2**30):
+    """Context for the contraction rate, not part of the path: the vendor bf16 GEMM (torch.mm, which
+    calls hipBLASLt, fp32 accumulation) timed with HIP events on torch's stream, one product of
+    stored operands of the coefficient contraction's shape (Mu x n times n x Mp, the store-mode
+    forward's plain product without its table build) and one square 8192^3 product.  Random normal
+    operands; only the time is used.  Beside it, the time per product of this library's own
+    contractions in the timed run (the x3 split executes three per launch, generating its operands)."""
+    cases = {"contraction_shape": (wl.Mu, wl.n, wl.Mp), "square_8192": (8192, 8192, 8192)}
+    rec = {"gemm": "torch.mm bf16 -> hipBLASLt"}
+    for name, (m, k, nn) in cases.items():
+        if 2 * k * (m + nn) > max_operand_bytes:
+            rec[name] = {"shape": [m, k, nn], "skipped": "operands above the size cap"}
+            continue
+        A = torch.randn(m, k, device=dev, dtype=torch.bfloat16)
+        B = torch.randn(k, nn, device=dev, dtype=torch.bfloat16)
+        torch.mm(A, B)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.library_steps):
+            torch.mm(A, B)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.library_steps
+        tf = 2.0 * m * k * nn / (ms * 1e-3) / 1e12
+        rec[name] = {"shape": [m, k, nn], "ms": round(ms, 3), "tflops": round(tf, 1),
+                     "frac_of_bf16_peak": round(tf / PEAK_TFLOPS["bf16"], 4)}
+        del A, B
+        torch.cuda.empty_cache()
+    mult = MFMA_MULT[args.precision]
+    ours = {}
+    for st in ("fwd", "bwd"):
+        per = stages[st][0] / stages[st][1] / mult
+        ours[st] = {"ms_per_product": round(per, 3),
+                    "executed_tflops": round(2.0 * wl.pairs / (per * 1e-3) / 1e12, 1)}
+    rec["ours_" + args.precision] = ours
+    cs = rec["contraction_shape"]
+    if "ms" in cs:
+        log(f"[bench] library bf16 GEMM {cs['shape']}: {cs['ms']:.2f} ms ({cs['tflops']:.0f} TFLOP/s); square 8192^3: "
+            + (f"{rec['square_8192']['tflops']:.0f} TFLOP/s" if "ms" in rec["square_8192"] else "skipped")
+            + f"; ours per product: fwd {ours['fwd']['ms_per_product']:.2f} ms ({ours['fwd']['executed_tflops']:.0f}),"
+            f" bwd {ours['bwd']['ms_per_product']:.2f} ms ({ours['bwd']['executed_tflops']:.0f})")
+    return rec
+
+
 def timed_steps(pp, torch, t, wl, prec, steps, warmup, ws, positions=None, basis="recompute"):
     """Warm up, then time `steps` evaluations (energy + gradient).  With `positions` (a list of
     (x, y) device tensors) step k evaluates positions[k % len]."""
@@ -186,6 +231,9 @@ def main():
     ap.add_argument("--jitter", action="store_true",
                     help="each timed step evaluates new positions: the base positions plus N(0,1) jitter, prepared "
                          "on the device before the timed region (the repeated-evaluation workload)")
+    ap.add_argument("--library-steps", type=int, default=3,
+                    help="timed calls of the vendor bf16 GEMM (torch.mm, hipBLASLt) on stored operands of the "
+                         "coefficient contraction's shape and on a square 8192^3 product, for context (0: skip)")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="run one device copy of this many GiB first (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -333,6 +381,9 @@ def main():
             log(f"[bench] {p8}: {dt8 / args.fp8_steps * 1e3:.1f} ms/step, {v8:.4e} pairs/s; stages "
                 + ", ".join(f"{k}={v[0] / v[1]:.2f}ms x{v[1] // args.fp8_steps}" for k, v in st8.items())
                 + (f"; vs fp64 {rec['rel_err_vs_fp64_gpu']}" if ref is not None else ""))
+
+    if args.library_steps > 0 and args.precision in ("bf16x3", "bf16"):
+        out["library_gemm"] = library_gemm(torch, dev, wl, stages, args)
 
     if args.eval_precision != "none":
         # The evaluation rows: psi and xi at every block centre (two contractions: psi and xi_x share
