@@ -384,8 +384,9 @@ struct RunStages {
     unsigned h[16], l[16], hah[16], hbh[16];
 
     // Stage ST of the run starting at frequency u0, block row k, run r, stored into arr_h / arr_l
-    // (X3 false: the hi halves alone, stored into arr_h).
-    template <int ST, bool X3 = true>
+    // (X3 false: the hi halves alone, stored into arr_h; STORE false: the segment a stage 8, 16, 24
+    // or 32 completes is left to a store_seg call in a later slot).
+    template <int ST, bool X3 = true, bool STORE = true>
     __device__ __forceinline__ void stage(int u0, char *arr_h, char *arr_l, int k, int r) {
         constexpr int st = ST;
         if constexpr (st == 0) {
@@ -410,12 +411,15 @@ struct RunStages {
                 l[q] = split_lo(v[2 * q], v[2 * q + 1], hah[q], hbh[q]);
             }
         }
-        if constexpr (st >= 8 && (st & 7) == 0) {
-            constexpr int m = (st - 8) >> 3;
-            *(u32x4 *)(arr_h + fswz(k, 4 * r + m)) = u32x4{h[4 * m], h[4 * m + 1], h[4 * m + 2], h[4 * m + 3]};
-            if constexpr (X3)
-                *(u32x4 *)(arr_l + fswz(k, 4 * r + m)) = u32x4{l[4 * m], l[4 * m + 1], l[4 * m + 2], l[4 * m + 3]};
-        }
+        if constexpr (STORE && st >= 8 && (st & 7) == 0)
+            this->template store_seg<((st - 8) >> 3), X3>(arr_h, arr_l, k, r);
+    }
+    // Segment M (values 8M .. 8M + 7, complete after stage 8M + 8) into arr_h (and arr_l).
+    template <int M, bool X3 = true>
+    __device__ __forceinline__ void store_seg(char *arr_h, char *arr_l, int k, int r) {
+        *(u32x4 *)(arr_h + fswz(k, 4 * r + M)) = u32x4{h[4 * M], h[4 * M + 1], h[4 * M + 2], h[4 * M + 3]};
+        if constexpr (X3)
+            *(u32x4 *)(arr_l + fswz(k, 4 * r + M)) = u32x4{l[4 * M], l[4 * M + 1], l[4 * M + 2], l[4 * M + 3]};
     }
     static constexpr int kStages = 33;
 };
@@ -430,6 +434,16 @@ constexpr int run_stage_at(int slot) {
     return -1;
 }
 static_assert((RunStages::kStages - 1) * kRunSlots / RunStages::kStages < kRunSlots, "stage plan");
+// The stores of a run's segments 0-2 (and of segment 3 of the X run) go to the stage-free slot after
+// the stage that completes them, which keeps the two 16-byte stores off the slots that already
+// issue a stage; the Y run's last segment is stored with its stage, before the chunk's barrier.
+constexpr int run_store_at(int slot) {
+    for (int m = 0; m < 4; ++m)
+        if ((8 * m + 8) * kRunSlots / RunStages::kStages + 1 == slot) return m;
+    return -1;
+}
+static_assert(run_stage_at(run_store_at(10) == 0 ? 10 : 0) < 0 && run_stage_at(20) < 0 && run_stage_at(30) < 0 &&
+                  run_stage_at(40) < 0 && run_store_at(40) == 3, "store plan");
 
 // LDS layout of the one-wave forward: the hi and lo arrays of both buffers interleaved,
 // [Xh0 Xh1 Xl0 Xl1 | Yh0 Yh1 Yl0 Yl1], 16 KB each, so that with one lane base for the X arrays
@@ -472,15 +486,46 @@ struct Fwd1Ctx {
     int ux, uy, k, r;
 };
 
-// Step-0 operands: the first five (those of the first four MFMAs) are read in slots 84-88 of the
-// previous chunk, the others in slots 0-10 of their own chunk, each at least four slots before its
-// first use.
+// Operand reads are placed in the slots that hold no generator stage (a stage issues about six
+// VALU instructions, which one wave issues beside a 32-cycle MFMA at little cost; a stage slot with
+// two LDS reads on top stretches the MFMA slot).  Step-0 operands 0-13 of the next chunk are read in
+// slots 82-95, after the chunk's barrier, and operands 14 and 15 of the chunk itself in its
+// stage-free slots 5 and 10; the step-1 operands in the stage-free slots 15-76, two per slot in the
+// first three.  Every read lands at least six slots before its operand's first use.
 template <int OP>
-constexpr int fwd1_read0_slot() { return OP < 5 ? 84 + OP : OP - 5; }
+constexpr int fwd1_read0_slot() { return OP < 14 ? 82 + OP : 5 * (OP - 13); }
+template <int OP>
+constexpr int fwd1_read1_slot() {
+    constexpr int slot[16] = {15, 15, 20, 20, 25, 25, 30, 35, 40, 46, 51, 56, 61, 66, 71, 76};
+    return slot[OP];
+}
+// First use of operand OP in a K step (MFMA order of fwd1_mfma: ah[a] at 4a, bh[b] at b, bl[b] at
+// 16 + b, al[a] at 32 + 4a).
+constexpr int fwd1_first_use(int op) {
+    return op == 0 ? 0 : op < 5 ? op - 1 : op < 8 ? 4 * (op - 4) : op < 12 ? 16 + op - 8 : 32 + 4 * (op - 12);
+}
+constexpr bool fwd1_reads_ok() {
+    for (int op = 0; op < 16; ++op) {
+        const int s1 = op == 0 ? 15 : op == 1 ? 15 : op == 2 ? 20 : op == 3 ? 20 : op == 4 ? 25 : op == 5 ? 25
+                     : op == 6 ? 30 : op == 7 ? 35 : op == 8 ? 40 : op == 9 ? 46 : op == 10 ? 51 : op == 11 ? 56
+                     : op == 12 ? 61 : op == 13 ? 66 : op == 14 ? 71 : 76;
+        if (s1 < kRunSlots ? run_stage_at(s1) >= 0 : run_stage_at(s1 - kRunSlots) >= 0) return false;
+        if (s1 + 6 > 48 + fwd1_first_use(op)) return false;
+        const int s0 = op < 14 ? 82 + op - 96 : 5 * (op - 13);
+        if (s0 >= 0 && run_stage_at(s0) >= 0) return false;
+        if (s0 + 6 > fwd1_first_use(op)) return false;
+    }
+    return true;
+}
+static_assert(fwd1_reads_ok(), "read plan");
 
 template <int I, int B, int... OP>
 __device__ __forceinline__ void fwd1_reads0_at(Fwd1Ctx &c, std::integer_sequence<int, OP...>) {
     ((I == fwd1_read0_slot<OP>() ? fwd1_read<0, OP, B>(c.smem, c.ox, c.oy, c.o0) : void()), ...);
+}
+template <int I, int B, int... OP>
+__device__ __forceinline__ void fwd1_reads1_at(Fwd1Ctx &c, std::integer_sequence<int, OP...>) {
+    ((I == fwd1_read1_slot<OP>() ? fwd1_read<1, OP, B>(c.smem, c.ox, c.oy, c.o1) : void()), ...);
 }
 
 // Slot I of a chunk that contracts buffer B and generates into buffer 1 - B.
@@ -489,17 +534,22 @@ __device__ __forceinline__ void fwd1_slot(Fwd1Ctx &c) {
     constexpr int N = 1 - B;
     if constexpr (I < 48) fwd1_mfma<I>(c.o0, c.acc);
     else fwd1_mfma<I - 48>(c.o1, c.acc);
-    if constexpr (I >= 12 && I < 44 && (I & 1) == 0) fwd1_read<1, (I - 12) / 2, B>(c.smem, c.ox, c.oy, c.o1);
+    fwd1_reads1_at<I, B>(c, std::make_integer_sequence<int, 16>{});
     constexpr int XS = I < kRunSlots ? run_stage_at(I) : -1;
     constexpr int YS = I >= kRunSlots && I < 2 * kRunSlots ? run_stage_at(I - kRunSlots) : -1;
-    if constexpr (XS >= 0) c.gx.template stage<XS>(c.ux, c.smem + F1_XH(N), c.smem + F1_XL(N), c.k, c.r);
-    if constexpr (YS >= 0) c.gy.template stage<YS>(c.uy, c.smem + F1_YH(N), c.smem + F1_YL(N), c.k, c.r);
+    if constexpr (XS >= 0) c.gx.template stage<XS, true, false>(c.ux, c.smem + F1_XH(N), c.smem + F1_XL(N), c.k, c.r);
+    if constexpr (YS >= 0)
+        c.gy.template stage<YS, true, YS == 32>(c.uy, c.smem + F1_YH(N), c.smem + F1_YL(N), c.k, c.r);
+    constexpr int XM = I < kRunSlots ? run_store_at(I) : -1;
+    constexpr int YM = I >= kRunSlots && I < 2 * kRunSlots ? run_store_at(I - kRunSlots) : -1;
+    if constexpr (XM >= 0) c.gx.template store_seg<XM>(c.smem + F1_XH(N), c.smem + F1_XL(N), c.k, c.r);
+    if constexpr (YM >= 0 && YM < 3) c.gy.template store_seg<YM>(c.smem + F1_YH(N), c.smem + F1_YL(N), c.k, c.r);
     // The generator's last store is in slot 81 at the latest: after the barrier the next chunk's
     // tiles are complete (its first step-0 operands are read in the following slots, well before the
     // next chunk's first MFMA) and this chunk's buffer is free for the next chunk's generator.
     static_assert(2 * kRunSlots - 1 <= 81, "slot plan");
     if constexpr (I == 81) lds_barrier();
-    if constexpr (I >= 84 && I <= 88) fwd1_reads0_at<I, N>(c, std::make_integer_sequence<int, 5>{});
+    if constexpr (I >= 82) fwd1_reads0_at<I, N>(c, std::make_integer_sequence<int, 14>{});
     if constexpr (I <= 10) fwd1_reads0_at<I, B>(c, std::make_integer_sequence<int, 16>{});
     __builtin_amdgcn_sched_barrier(0);
 }
@@ -576,6 +626,14 @@ __device__ __forceinline__ void fwd1_chunk_any(char *smem, const OpBase &ox, con
     }
 }
 
+// Step-0 operands of the first chunk that the loop expects already read: 0-13 for the three-product
+// schedule, 0-4 for the one-product one.
+template <bool X3, int... OP>
+__device__ __forceinline__ void fwd1_prologue_reads(const char *smem, const OpBase &ox, const OpBase &oy, FwdOps1 &o0,
+                                                    std::integer_sequence<int, OP...>) {
+    ((X3 || OP < 5 ? fwd1_read<0, OP, 0>(smem, ox, oy, o0) : void()), ...);
+}
+
 // X3: three products per pair (hi*hi, lo*hi, hi*lo); otherwise one (hi*hi).  skip_u x skip_p: the
 // tiles of that low-frequency corner are left to another launch (the mixed split contracts them
 // with three products); 0 x 0 skips nothing.
@@ -632,11 +690,7 @@ __global__ __launch_bounds__(256) void k_fwd1_bf16(int64_t n, int Mu, int Mp, co
     gyB.R = recy(c_begin + 1);
     lds_barrier();
     FwdOps1 o0;
-    fwd1_read<0, 0, 0>(smem, ox, oy, o0);
-    fwd1_read<0, 1, 0>(smem, ox, oy, o0);
-    fwd1_read<0, 2, 0>(smem, ox, oy, o0);
-    fwd1_read<0, 3, 0>(smem, ox, oy, o0);
-    fwd1_read<0, 4, 0>(smem, ox, oy, o0);
+    fwd1_prologue_reads<X3>(smem, ox, oy, o0, std::make_integer_sequence<int, 14>{});
     // Nothing the prologue loaded may still be in flight at the loop head (the compiler would then
     // wait for every load and LDS read at the first use in each iteration).
     asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
