@@ -172,6 +172,28 @@ def library_gemm(torch, dev, wl, stages, args, max_operand_bytes=20 * 2**30):
     return rec
 
 
+def mfma_sustained(torch, pp, dev, iters, reps=3):
+    """The bf16 matrix rate the chip sustains with every CU loaded: the library's calibration kernel
+    (one workgroup of four waves per CU, each wave 16 MFMAs per iteration on normally distributed
+    operands, nothing else in its loop), timed with HIP events on torch's stream.  Under such a load
+    the power limit sets the clock, so this is the practical ceiling of an MFMA-bound kernel on data
+    like the contractions' operands."""
+    wg = torch.cuda.get_device_properties(dev).multi_processor_count
+    out = torch.empty(wg * 256, dtype=torch.float32, device=dev)
+    pp.mfma_calibrate(out, workgroups=wg, iters=iters)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        pp.mfma_calibrate(out, workgroups=wg, iters=iters)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    tf = wg * 4 * 16 * iters * 32768.0 / (ms * 1e-3) / 1e12
+    return {"kernel": "k_mfma_calibrate (pp_mfma_calibrate)", "workgroups": wg, "iters": iters, "ms": round(ms, 3),
+            "tflops": round(tf, 1), "frac_of_bf16_peak": round(tf / PEAK_TFLOPS["bf16"], 4)}
+
+
 def timed_steps(pp, torch, t, wl, prec, steps, warmup, ws, positions=None, basis="recompute"):
     """Warm up, then time `steps` evaluations (energy + gradient).  With `positions` (a list of
     (x, y) device tensors) step k evaluates positions[k % len]."""
@@ -234,6 +256,10 @@ def main():
     ap.add_argument("--library-steps", type=int, default=3,
                     help="timed calls of the vendor bf16 GEMM (torch.mm, hipBLASLt) on stored operands of the "
                          "coefficient contraction's shape and on a square 8192^3 product, for context (0: skip)")
+    ap.add_argument("--mfma-calibration-iters", type=int, default=40000,
+                    help="iterations of the matrix-core calibration kernel (one workgroup per CU, 16 bf16 MFMAs "
+                         "per wave and iteration on normally distributed operands), timed for the sustained bf16 "
+                         "matrix rate under load (0: skip)")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="run one device copy of this many GiB first (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -384,6 +410,13 @@ def main():
 
     if args.library_steps > 0 and args.precision in ("bf16x3", "bf16"):
         out["library_gemm"] = library_gemm(torch, dev, wl, stages, args)
+    if args.mfma_calibration_iters > 0 and args.precision in ("bf16x3", "bf16"):
+        cal = mfma_sustained(torch, pp, dev, args.mfma_calibration_iters)
+        out["mfma_sustained"] = cal
+        roofline["executed_frac_of_sustained"] = round(roofline["executed_mfma_tflops"] / cal["tflops"], 4)
+        log(f"[bench] sustained bf16 MFMA rate (calibration kernel, every CU loaded): {cal['tflops']:.0f} TFLOP/s "
+            f"({cal['frac_of_bf16_peak']:.3f} of the datasheet peak); the dominant kernel executes "
+            f"{roofline['executed_frac_of_sustained']:.3f} of it")
 
     if args.eval_precision != "none":
         # The evaluation rows: psi and xi at every block centre (two contractions: psi and xi_x share

@@ -267,6 +267,19 @@ const char *pp_strerror(int status);
 int pp_timing_enable(int on);
 int pp_timing_query(const char *name, double *total_ms, int *count);
 
+/* Matrix-core calibration (a measurement hook; it computes nothing of the method).
+ * pp_mfma_calibrate(workgroups, iters, out, stream) enqueues one kernel of `workgroups` workgroups of
+ * 256 threads (four waves).  Every wave issues 16 * iters v_mfma_f32_32x32x16_bf16 instructions into
+ * 16 accumulator tiles and nothing else in its loop, on bf16 operands drawn from a standard normal
+ * distribution (a counter-based hash of workgroup, thread and register), and each thread writes the
+ * sum of its accumulators to out[workgroup * 256 + thread].  One call executes
+ * workgroups * 4 * 16 * iters * 32768 flops; timed with events on `stream` it gives the bf16 rate the
+ * matrix cores sustain on such data with every CU loaded (use a multiple of the CU count), which the
+ * power limit, through the clock, holds well below the datasheet peak.
+ * out: caller-owned device buffer of workgroups * 256 floats.  Returns PP_ERR_ARG for workgroups < 1
+ * or > 65535, iters < 1 or out NULL, PP_ERR_DEVICE if the launch fails, else PP_OK. */
+int pp_mfma_calibrate(int workgroups, int iters, float *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,7 +19,7 @@ import torch
 
 __all__ = ["PRECISIONS", "BASIS_MODES", "PPError", "library_path", "load", "workspace_size", "coeffs",
            "energy", "energy_static", "field", "point_field", "block_potential", "PPEnergy", "energy_autograd", "timing_enable",
-           "timing_query", "bin_workspace_size", "bin_density", "bin_coeffs", "bin_field"]
+           "timing_query", "mfma_calibrate", "bin_workspace_size", "bin_density", "bin_coeffs", "bin_field"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 # PP_LIBRARY names another build of the same library (the host-sanitizer test uses it).
@@ -31,7 +31,8 @@ BASIS_MODES = {"recompute": 0, "store": 1}
 PP_OK = 0
 EXPORTS = ("pp_workspace_size", "pp_coeffs", "pp_energy", "pp_energy_static", "pp_field", "pp_point_field",
            "pp_block_potential",
-           "pp_strerror", "pp_timing_enable", "pp_timing_query", "pp_bin_workspace_size", "pp_bin_density",
+           "pp_strerror", "pp_timing_enable", "pp_timing_query", "pp_mfma_calibrate", "pp_bin_workspace_size",
+           "pp_bin_density",
            "pp_bin_coeffs", "pp_bin_field", "pp_bin_interp")
 
 
@@ -82,6 +83,8 @@ def load():
     lib.pp_timing_enable.restype = ctypes.c_int
     lib.pp_timing_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
     lib.pp_timing_query.restype = ctypes.c_int
+    lib.pp_mfma_calibrate.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp]
+    lib.pp_mfma_calibrate.restype = ctypes.c_int
     B = ctypes.POINTER(PPBinProblem)
     lib.pp_bin_workspace_size.argtypes = [B, ctypes.POINTER(sz)]
     lib.pp_bin_density.argtypes = [B, vp, vp, vp, vp, vp, vp, sz, vp]
@@ -387,6 +390,20 @@ def timing_query(stage: str):
     if st != PP_OK:
         raise PPError(st, "pp_timing_query")
     return float(ms.value), int(cnt.value)
+
+
+def mfma_calibrate(out, *, workgroups, iters):
+    """Enqueue the matrix-core calibration kernel on torch's current stream of out's device (out: a
+    contiguous float32 CUDA tensor of at least workgroups * 256 elements); time it with events on that
+    stream.  The launch executes workgroups * 4 * 16 * iters * 32768 bf16 flops."""
+    if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()):
+        raise TypeError("out must be a contiguous float32 CUDA tensor")
+    if out.numel() < workgroups * 256:
+        raise ValueError("out holds fewer than workgroups * 256 floats")
+    with torch.cuda.device(out.device):
+        st = load().pp_mfma_calibrate(int(workgroups), int(iters), _vp(out), _stream(out.device))
+    if st != PP_OK:
+        raise PPError(st, "pp_mfma_calibrate")
 
 
 class PPEnergy(torch.autograd.Function):

@@ -45,6 +45,15 @@ def test_strerror(lib):
         assert isinstance(s, bytes) and len(s) > 3
 
 
+def test_mfma_calibrate_rejects_bad_arguments_before_launch(lib):
+    """The calibration hook validates on the host: no launch (none could run here) for a workgroup
+    count outside 1..65535, an iteration count below 1 or a NULL output."""
+    buf = ctypes.c_void_p(0x1000)   # never dereferenced: every call below must fail validation
+    for wg, it, out in ((0, 10, buf), (65536, 10, buf), (-3, 10, buf), (256, 0, buf), (256, -1, buf),
+                        (256, 10, None)):
+        assert lib.pp_mfma_calibrate(wg, it, out, None) == -1
+
+
 def P(**kw):
     d = dict(W=100.0, H=50.0, n=1000, Mu=64, Mp=48, precision=0, basis_mode=0)
     d.update(kw)
