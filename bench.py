@@ -91,14 +91,24 @@ KERNEL_SOURCES = {"bf16x3": ("kernels_bf16.hip",), "bf16": ("kernels_bf16.hip",)
                   "fp64": ("kernels_f64.hip",), "fp32": ("kernels_f64.hip",)}
 
 
+def code_tokens(src):
+    """The code of a C++ source without its comments and with whitespace runs collapsed (string and
+    character literals kept), so that a change of comments or layout alone keeps the hash below."""
+    import re
+    pat = re.compile(r'//[^\n]*|/\*.*?\*/|"(?:\\.|[^"\\])*"|\'(?:\\.|[^\'\\])*\'', re.S)
+    code = pat.sub(lambda m: m.group(0) if m.group(0)[0] in "\"'" else " ", src)
+    return " ".join(code.split())
+
+
 def kernel_source_hash(precision="bf16x3"):
-    """sha256 of the sources of one precision's kernels; counter figures are reported only for the
-    kernels they were taken on."""
+    """sha256 of the code (comments and layout aside) of one precision's kernel sources; counter
+    figures are reported only for the kernels they were taken on."""
     import hashlib
     d = os.path.join(ROOT, "paper_2307_12041_amd", "csrc")
     hs = hashlib.sha256()
     for f in COMMON_SOURCES + KERNEL_SOURCES[precision]:
-        hs.update(open(os.path.join(d, f), "rb").read())
+        hs.update(code_tokens(open(os.path.join(d, f)).read()).encode())
+        hs.update(b"\0")
     return hs.hexdigest()
 
 

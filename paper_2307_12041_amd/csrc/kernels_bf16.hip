@@ -560,10 +560,10 @@ __device__ __forceinline__ void fwd1_slots(Fwd1Ctx &c, std::integer_sequence<int
 }
 
 // One chunk: contract buffer B into acc while generating the next chunk's X and Y runs into
-// buffer 1 - B.  96 slots of one MFMA each; the step-0 operands are read in slots 84-88 of the
-// previous chunk and 0-10 of this one, the step-1 operands one every two slots from slot 12; the
-// X run's stages spread over slots 0-40, the Y run's over slots 41-81; the chunk's one barrier
-// follows slot 81.
+// buffer 1 - B.  96 slots of one MFMA each; the X run's stages spread over slots 0-40, the Y run's
+// over slots 41-81, each run segment stored in the stage-free slot after the stage completing it;
+// the operand reads in the other stage-free slots (fwd1_read0_slot, fwd1_read1_slot); the chunk's
+// one barrier follows slot 81.
 template <int B>
 __device__ __forceinline__ void fwd1_chunk(char *smem, const OpBase &ox, const OpBase &oy, f32x16 (&acc)[4][4],
                                            RunStages &gx, RunStages &gy, FwdOps1 &o0, int ux, int uy, int k,
