@@ -50,8 +50,6 @@ def _load():
     d, i64, i32 = ctypes.c_double, ctypes.c_int64, ctypes.c_int
     lib.oracle_coeffs.argtypes = [d, d, i64, _dp, _dp, _dp, _dp, i32, i32, _dp, _dp]
     lib.oracle_energy.argtypes = [d, d, i64, _dp, _dp, _dp, _dp, i32, i32, _dp, _dp, _dp]
-    lib.oracle_energy_from.argtypes = [_dp, _dp, i32, i32]
-    lib.oracle_energy_from.restype = d
     lib.oracle_grad.argtypes = [d, d, i64, _dp, _dp, _dp, _dp, i32, i32, _dp, _dp, _dp]
     lib.oracle_grad_sampled.argtypes = [d, d, _dp, _dp, _dp, _dp, i32, i32, _dp, i64, _lp, _dp, _dp]
     lib.oracle_coeffs_sampled.argtypes = [d, d, i64, _dp, _dp, _dp, _dp, i32, _ip, _ip, _dp, _dp]
@@ -120,12 +118,6 @@ def energy(W, H, x, y, w, h, Mu, Mp):
     _check(lib.oracle_energy(W, H, n, *[p for _, p in xs], Mu, Mp, ctypes.byref(E),
                              a.ctypes.data_as(_dp), I.ctypes.data_as(_dp)), "energy")
     return float(E.value), a, I
-
-
-def energy_from(a, I) -> float:
-    a, pa = _f64(a)
-    I, pI = _f64(I)
-    return float(_load().oracle_energy_from(pa, pI, a.shape[0], a.shape[1]))
 
 
 def grad(W, H, x, y, w, h, a):

@@ -277,21 +277,6 @@ struct FwdOps {
     bf16x8 ah[4], al[4], bh[2], bl[2];
 };
 
-template <bool X3>
-__device__ __forceinline__ void fwd_load(const char *buf, const OpBase &ox, const OpBase &oy, int ks, FwdOps &o) {
-    const char *xh = buf, *xl = buf + FARR, *yh = buf + 2 * FARR, *yl = buf + 3 * FARR;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        o.ah[a] = load_opT(xh, ox, a, ks);
-        if (X3) o.al[a] = load_opT(xl, ox, a, ks);
-    }
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-        o.bh[b] = load_opT(yh, oy, b, ks);
-        if (X3) o.bl[b] = load_opT(yl, oy, b, ks);
-    }
-}
-
 // Three passes over the 8 accumulators, so consecutive MFMAs never share an accumulator.
 template <bool X3>
 __device__ __forceinline__ void fwd_mfma(const FwdOps &o, f32x16 (&acc)[4][2]) {
