@@ -374,6 +374,16 @@ struct RunStages {
     template <int ST, bool X3 = true, bool STORE = true>
     __device__ __forceinline__ void stage(int u0, char *arr_h, char *arr_l, int k, int r) {
         constexpr int st = ST;
+        // split of pair q: hi at stage 2q + 1, lo at 2q + 2
+        constexpr bool HI = st >= 1 && st <= 32 && ((st - 1) & 1) == 0, LO = st >= 1 && st <= 32 && !HI;
+        constexpr int q = (st - 1) >> 1;
+        if constexpr (X3 && HI) {
+            // The pack goes first, ahead of the recurrence step: its result may be read only two wait
+            // states later, and with the step in between the shift and mask below need no s_nop.
+            h[q] = pack_bf16(v[2 * q], v[2 * q + 1]);
+            asm("" : "+v"(h[q]));   // keeps the shift below on h (else it re-converts v[2q] alone)
+            __builtin_amdgcn_sched_barrier(0);
+        }
         if constexpr (st == 0) {
             start_run(R, C, S);
             v[0] = C.f * S.f;
@@ -382,19 +392,14 @@ struct RunStages {
         } else if constexpr (st <= 30) {
             v[st + 1] = C.next1() * S.next1();
         }
-        // split of pair q: hi at stage 2q + 1, lo at 2q + 2
-        if constexpr (st >= 1 && st <= 32) {
-            constexpr int q = (st - 1) >> 1;
-            if constexpr (((st - 1) & 1) == 0) {
-                h[q] = pack_bf16(v[2 * q], v[2 * q + 1]);
-                if constexpr (X3) {
-                    asm("" : "+v"(h[q]));   // keeps the shift below on h (else it re-converts v[2q] alone)
-                    hah[q] = h[q] << 16;
-                    hbh[q] = h[q] & 0xffff0000u;
-                }
-            } else if constexpr (X3) {
-                l[q] = split_lo(v[2 * q], v[2 * q + 1], hah[q], hbh[q]);
-            }
+        if constexpr (X3 && HI) {
+            __builtin_amdgcn_sched_barrier(0);
+            hah[q] = h[q] << 16;
+            hbh[q] = h[q] & 0xffff0000u;
+        } else if constexpr (HI) {
+            h[q] = pack_bf16(v[2 * q], v[2 * q + 1]);
+        } else if constexpr (X3 && LO) {
+            l[q] = split_lo(v[2 * q], v[2 * q + 1], hah[q], hbh[q]);
         }
         if constexpr (STORE && st >= 8 && (st & 7) == 0)
             this->template store_seg<((st - 8) >> 3), X3>(arr_h, arr_l, k, r);
