@@ -360,8 +360,9 @@ struct FwdOps1 {
 // One run of 32 basis values generated in stages spread over the MFMA slots of the chunk, so that
 // its VALU work interleaves with the matrix work.  Stage map: 0 starts both recurrences from the
 // run's seeds and gives the first two values; 1-30 one value each; the hi/lo split of value pair q
-// in two halves at stages 2q + 1 and 2q + 2; the four 16-byte segments (hi and lo) stored at stages
-// 8, 16, 24, 32.
+// in two halves at stages 2q + 1 and 2q + 2; the four 16-byte segments (hi and lo) complete at stages
+// 8, 16, 24, 32 and are stored there (one-product schedule) or by store_seg in a later slot
+// (three-product schedule).
 struct RunStages {
     GenRec R;
     Cheb C, S;
