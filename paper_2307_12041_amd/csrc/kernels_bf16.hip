@@ -976,16 +976,69 @@ struct AGen {
 template <int KA>
 struct Bwd1Ctx {
     const char *cur, *nxt;
-    char *cpy_dst;                 // buffer receiving the chunk after next
+    char *cpy_dst;                 // released buffer receiving the chunk after next (after the barrier)
     const char *cpy_src;           // its global tile (past the last chunk: the last chunk again)
+    char *cpy_dst2;                // buffer receiving the next chunk (the rest of its copies)
+    const char *cpy_src2;          // its global tile (past the last chunk: the last chunk again)
     AGen<KA> (&g)[2];
     bf16x8 (&ah)[2], (&al)[2];     // A operands of the current step
     bf16x8 (&bh)[8], (&bl)[8];     // B operands
     f32x16 (&acc)[2][8];
     int h, j;
     unsigned lane_off;             // this lane's byte offset within a copy slice
-    int wave_off;                  // this wave's byte offset within a copy slice (uniform)
+    int wave_off;                  // 1024 times the wave's index (uniform)
 };
+
+// Copy slice SL (0 .. NSL - 1) of this wave's quarter of the first 4 NSL KB of an operand tile
+// (NSL = 16: hi and lo, the whole tile; 8: the hi half): tile bytes NSL wave_off + 1024 SL + 16 lane
+// go to the same offset of the LDS buffer (NEXT: the next chunk's tile and buffer, else the chunk
+// after next's).  Four consecutive slices share one address pair and differ in the instruction's
+// immediate offset, which applies to the global and the LDS address alike, so each group of four
+// needs one M0 value and one address computation.
+template <int SL, int NSL, bool NEXT, int KA>
+__device__ __forceinline__ void bwd1_copy_slice(const Bwd1Ctx<KA> &c) {
+    typedef __attribute__((address_space(3))) void lds_void;
+    static_assert(NSL % 4 == 0 && SL >= 0 && SL < NSL, "copy slices");
+    constexpr int grp = (SL >> 2) * 4096, imm = (SL & 3) * 1024;
+    const int part = NSL * c.wave_off + grp;
+    const char *src = NEXT ? c.cpy_src2 : c.cpy_src;
+    char *dst = NEXT ? c.cpy_dst2 : c.cpy_dst;
+    __builtin_amdgcn_global_load_lds((const void *)(src + part + c.lane_off), (lds_void *)(dst + part), 16, imm, 0);
+}
+
+// A wait for every outstanding LDS operation written with the compiler's own instruction, so that its
+// bookkeeping sees the reads complete (the empty asm statements keep memory operations on their side).
+__device__ __forceinline__ void counted_lds_wait() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vmcnt and expcnt at their maxima (no wait)
+    asm volatile("" ::: "memory");
+}
+
+// Copy plan of a chunk whose barrier follows slot BAR.  The four waves' direct copies share the CU's
+// memory pipeline, and issued in consecutive slots they slow the waves down (bunched into six slots
+// they cost the three-product kernel 1.5 % more than one per slot after the barrier, and one per
+// four to eight slots cost 1.5 % less); they are therefore spread out.  A buffer is free from the
+// barrier of the chunk that read it, and the tile for chunk q + 2 must have landed by the barrier of
+// chunk q + 1: slices 0 and 1 go in slots BAR + 1 and BAR + 1 + D of chunk q (into the buffer that
+// chunk q released), slices 2 .. NSL - 1 in slots 0, D, 2 D, ... of chunk q + 1 (into its next
+// buffer), well before that chunk's barrier.
+template <int BAR, int D>
+constexpr int bwd1_copy_after(int slot) { return slot == BAR + 1 ? 0 : slot == BAR + 1 + D ? 1 : -1; }
+template <int NSL, int D>
+constexpr int bwd1_copy_next(int slot) { return slot % D == 0 && slot / D + 2 < NSL ? slot / D + 2 : -1; }
+// The three-product chunk places them by its LDS waits instead: the compiler counts the copies among
+// the LDS operations, and with one outstanding it makes the next wait for an LDS read a wait for all
+// of them (slots 32, 48, 80, 96, 128 and 144 of the chunk, the first uses of the lo and hi B reads),
+// which the copy may then hold up.  Slices 2 .. 15 go right after such a wait and at least 15 slots
+// before the next one; slices 0 and 1 go after an explicit wait for the next chunk's hi B reads, at
+// slots 188 and 190, so that the next chunk's first MFMAs need no wait at all.
+constexpr int kBwd1CopyNext[14] = {1, 5, 9, 13, 49, 53, 57, 61, 97, 101, 105, 109, 145, 149};
+constexpr int bwd1x3_copy_next(int slot) {
+    for (int k = 0; k < 14; ++k)
+        if (kBwd1CopyNext[k] == slot) return k + 2;
+    return -1;
+}
+constexpr int bwd1x3_copy_after(int slot) { return slot == 188 ? 0 : slot == 190 ? 1 : -1; }
 
 // B operand of column tile b, K step s of a chunk buffer: row 32 b + j, logical segment 4 h + s,
 // physical segment XORed with (j / 2) % 8.
@@ -1033,6 +1086,9 @@ __device__ __forceinline__ void bwd1_slot(Bwd1Ctx<KA> &c) {
         const bf16x8 B = pass == 2 ? c.bl[b] : c.bh[b];
         c.acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, c.acc[a][b], 0, 0, 0);
     }
+    // The MFMA goes first in its slot: after the chunk's barrier the slot's B read would otherwise be
+    // issued ahead of it, and the wait for the MFMA's own operand then covers that fresh read too.
+    __builtin_amdgcn_sched_barrier(0);
     // lo B of this step in the first half of the lo*hi pass, hi B of the next step in the first half
     // of the hi*lo pass: each read lands at least 8 slots before its first use, so that even a full
     // LDS wait (the compiler's while direct copies are in flight) finds them complete.
@@ -1047,14 +1103,13 @@ __device__ __forceinline__ void bwd1_slot(Bwd1Ctx<KA> &c) {
         if constexpr (s < 3) c.bh[bb] = bwd1_readb(c.cur, 0, bb, s + 1, c.h, c.j);
         else c.bh[bb] = bwd1_readb(c.nxt, 0, bb, 0, c.h, c.j);
     }
-    if constexpr (s == 3 && t >= 32) {
-        // copy slice (t - 32) of the chunk after next into the released buffer (unconditionally, so
-        // that the chunk stays one basic block: past the end the last chunk is copied again into
-        // a buffer that is not read any more)
-        typedef __attribute__((address_space(3))) void lds_void;
-        constexpr int sl = t - 32;
-        __builtin_amdgcn_global_load_lds((const void *)(c.cpy_src + sl * 4096 + c.lane_off),
-                                         (lds_void *)(c.cpy_dst + sl * 4096 + c.wave_off), 16, 0, 0);
+    {
+        // copies (unconditional, so that the chunk stays one basic block: past the end the last
+        // chunk is copied again into a buffer that is not read any more)
+        constexpr int ca = bwd1x3_copy_after(I), cn = bwd1x3_copy_next(I);
+        if constexpr (I == 188) counted_lds_wait();
+        if constexpr (ca >= 0) bwd1_copy_slice<ca, 16, false>(c);
+        if constexpr (cn >= 0) bwd1_copy_slice<cn, 16, true>(c);
     }
     bwd1_gen<KA, s, false, t>(c);
     if constexpr (t == 6) {
@@ -1074,7 +1129,7 @@ __device__ __forceinline__ void bwd1_slot(Bwd1Ctx<KA> &c) {
 // the pair it completes); the phasor jump takes slots 0-7 of step 0, the reseeds follow the last
 // value of each subtile in step 2.  Next step's hi B is read at slots 8-15, at least 8 slots ahead
 // of its first use and after the current step's last use of the same register; the barrier moves
-// to slot 7 of step 3 and the copies of the chunk after next (hi half only) to its slots 8-15.
+// to slot 7 of step 3; the copies (hi halves only) follow bwd1_copy_after and bwd1_copy_next.
 template <int KA, int I>
 __device__ __forceinline__ void bwd1_slot_plain(Bwd1Ctx<KA> &c) {
     constexpr int s = I / 16, t = I % 16;
@@ -1089,11 +1144,11 @@ __device__ __forceinline__ void bwd1_slot_plain(Bwd1Ctx<KA> &c) {
         if constexpr (s < 3) c.bh[bb] = bwd1_readb(c.cur, 0, bb, s + 1, c.h, c.j);
         else c.bh[bb] = bwd1_readb(c.nxt, 0, bb, 0, c.h, c.j);
     }
-    if constexpr (s == 3 && t >= 8) {
-        typedef __attribute__((address_space(3))) void lds_void;
-        constexpr int sl = t - 8;
-        __builtin_amdgcn_global_load_lds((const void *)(c.cpy_src + sl * 4096 + c.lane_off),
-                                         (lds_void *)(c.cpy_dst + sl * 4096 + c.wave_off), 16, 0, 0);
+    {
+        constexpr int ca = bwd1_copy_after<55, 4>(I), cn = bwd1_copy_next<8, 4>(I);
+        static_assert(55 + 1 + 4 < 64 && 4 * 5 < 55 - 24, "copy plan");
+        if constexpr (ca >= 0) bwd1_copy_slice<ca, 8, false>(c);
+        if constexpr (cn >= 0) bwd1_copy_slice<cn, 8, true>(c);
     }
     {
         constexpr int u = t, ga = u & 1, e = u >> 1;
@@ -1153,15 +1208,20 @@ __global__ __launch_bounds__(256) void k_bwd1_bf16(int64_t n, BwdAxisBf16 ax) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
 
-    // Prologue: copies of chunks 0 and 1, A of step 0 of chunk 0, hi B of step 0.
+    // Prologue: copies of chunk 0 and of the first two slices of chunk 1 (the rest of chunk 1 is
+    // copied in chunk 0's slots), A of step 0 of chunk 0, hi B of step 0.
     typedef __attribute__((address_space(3))) void lds_void;
-    for (int q = 0; q < 2 && q < Q; ++q)
 #pragma unroll
-        for (int sl = 0; sl < BBUF / 4096; ++sl)
-            __builtin_amdgcn_global_load_lds((const void *)(gb + (size_t)q * tile_bytes + sl * 4096 + tid * 16),
-                                             (lds_void *)(smem + q * BBUF + sl * 4096 + wave * 1024), 16, 0, 0);
+    for (int sl = 0; sl < BBUF / 4096; ++sl)
+        __builtin_amdgcn_global_load_lds((const void *)(gb + sl * 4096 + tid * 16),
+                                         (lds_void *)(smem + sl * 4096 + wave * 1024), 16, 0, 0);
     bf16x8 ah[2], al[2], bh[8], bl[8];
-    Bwd1Ctx<KA> c{smem, smem + BBUF, smem, gb, g, ah, al, bh, bl, acc, h, j, (unsigned)tid * 16u, wave * 1024};
+    Bwd1Ctx<KA> c{smem, smem + BBUF, smem + BBUF, gb + (Q > 1 ? tile_bytes : 0), smem + BBUF, gb,
+                  g, ah, al, bh, bl, acc, h, j, (unsigned)lane * 16u, wave * 1024};
+    if (Q > 1) {
+        bwd1_copy_slice<0, X3 ? 16 : 8, false>(c);
+        bwd1_copy_slice<1, X3 ? 16 : 8, false>(c);
+    }
     if (h == 0) bwd1_gen_all<KA, true>(c, std::make_integer_sequence<int, 48>{});
     else bwd1_gen_all<KA, false>(c, std::make_integer_sequence<int, 48>{});
     // the lo halves of pair 3 (in the loop: slots 2 and 5 of the next step)
@@ -1175,12 +1235,15 @@ __global__ __launch_bounds__(256) void k_bwd1_bf16(int64_t n, BwdAxisBf16 ax) {
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < 8; ++b) bh[b] = bwd1_readb(smem, 0, b, 0, h, j);
+    counted_lds_wait();   // known complete, these reads need no wait at the top of the loop
 
     for (int q = 0; q < Q; ++q) {
         c.cur = smem + (q & 1) * BBUF;
         c.nxt = smem + ((q & 1) ^ 1) * BBUF;
         c.cpy_dst = smem + (q & 1) * BBUF;
         c.cpy_src = gb + (size_t)min(q + 2, Q - 1) * tile_bytes;
+        c.cpy_dst2 = smem + ((q & 1) ^ 1) * BBUF;
+        c.cpy_src2 = gb + (size_t)min(q + 1, Q - 1) * tile_bytes;
         bwd1_slots<X3>(c, std::make_integer_sequence<int, X3 ? 192 : 64>{});
     }
     wait_copies();   // the copies issued in the last chunks must land before the buffers are reused
