@@ -56,6 +56,10 @@ def check(wl, prec, grad_sample=None):
     (3001, 300, 150, 500.0, 300.0, 3),
     (5000, 257, 513, 300.0, 900.0, 4),
     (700, 40, 600, 64.0, 800.0, 5),
+    # 2 and 2, 3 and 4 chunks of 64 frequencies along the gradient contractions' K axes (gx over p,
+    # gy over u): the prologue's copies of the first chunks and the re-copies past the last one
+    (900, 100, 128, 400.0, 500.0, 6),
+    (800, 256, 190, 300.0, 700.0, 7),
 ])
 def test_bf16_parity_shapes(prec, n, Mu, Mp, W, H, seed):
     check(make_random(n, W, H, Mu, Mp, seed=seed), prec)
