@@ -361,8 +361,8 @@ struct FwdOps1 {
 // its VALU work interleaves with the matrix work.  Stage map: 0 starts both recurrences from the
 // run's seeds and gives the first two values; 1-30 one value each; the hi/lo split of value pair q
 // in two halves at stages 2q + 1 and 2q + 2; the four 16-byte segments (hi and lo) complete at stages
-// 8, 16, 24, 32 and are stored there (one-product schedule) or by store_seg in a later slot
-// (three-product schedule).
+// 8, 16, 24, 32 and are stored there (one-product schedule) or half by half by store_half in later
+// slots (three-product schedule).
 struct RunStages {
     GenRec R;
     Cheb C, S;
@@ -412,6 +412,12 @@ struct RunStages {
         if constexpr (X3)
             *(u32x4 *)(arr_l + fswz(k, 4 * r + M)) = u32x4{l[4 * M], l[4 * M + 1], l[4 * M + 2], l[4 * M + 3]};
     }
+    // The hi (HL = 0) or lo (HL = 1) half of segment M into arr.
+    template <int M, int HL>
+    __device__ __forceinline__ void store_half(char *arr, int k, int r) {
+        const unsigned *w = HL ? l : h;
+        *(u32x4 *)(arr + fswz(k, 4 * r + M)) = u32x4{w[4 * M], w[4 * M + 1], w[4 * M + 2], w[4 * M + 3]};
+    }
     static constexpr int kStages = 33;
 };
 
@@ -425,16 +431,23 @@ constexpr int run_stage_at(int slot) {
     return -1;
 }
 static_assert((RunStages::kStages - 1) * kRunSlots / RunStages::kStages < kRunSlots, "stage plan");
-// The stores of a run's segments 0-2 (and of segment 3 of the X run) go to the stage-free slot after
-// the stage that completes them, which keeps the two 16-byte stores off the slots that already
-// issue a stage; the Y run's last segment is stored with its stage, before the chunk's barrier.
-constexpr int run_store_at(int slot) {
-    for (int m = 0; m < 4; ++m)
-        if ((8 * m + 8) * kRunSlots / RunStages::kStages + 1 == slot) return m;
-    return -1;
+// Slots of the 16-byte stores of the three-product chunk, [run (X, Y)][segment][hi, lo]: one store in
+// each stage-free slot from the one after the stage completing the segment on (the X run's slots
+// 10-40 and 46, the Y run's 51-76), the Y run's last segment both in slot 81, before the barrier.
+constexpr int kFwdStoreSlot[2][4][2] = {{{10, 15}, {20, 25}, {30, 35}, {40, 46}},
+                                        {{51, 56}, {61, 66}, {71, 76}, {81, 81}}};
+constexpr bool fwd1_stores_ok() {
+    for (int run = 0; run < 2; ++run)
+        for (int m = 0; m < 4; ++m)
+            for (int hl = 0; hl < 2; ++hl) {
+                const int sl = kFwdStoreSlot[run][m][hl], done = run * kRunSlots + (8 * m + 8) * kRunSlots / RunStages::kStages;
+                const int off = sl - run * kRunSlots;
+                if (sl <= done || sl > 81 || (off >= 0 && off < kRunSlots && run_stage_at(off) >= 0)) return false;
+                if (run == 0 && sl >= kRunSlots && run_stage_at(sl - kRunSlots) >= 0) return false;
+            }
+    return true;
 }
-static_assert(run_stage_at(run_store_at(10) == 0 ? 10 : 0) < 0 && run_stage_at(20) < 0 && run_stage_at(30) < 0 &&
-                  run_stage_at(40) < 0 && run_store_at(40) == 3, "store plan");
+static_assert(fwd1_stores_ok(), "store plan");
 
 // LDS layout of the one-wave forward: the hi and lo arrays of both buffers interleaved,
 // [Xh0 Xh1 Xl0 Xl1 | Yh0 Yh1 Yl0 Yl1], 16 KB each, so that with one lane base for the X arrays
@@ -481,15 +494,14 @@ struct Fwd1Ctx {
 // VALU instructions, which one wave issues beside a 32-cycle MFMA at little cost; a stage slot with
 // two LDS reads on top stretches the MFMA slot).  Step-0 operands 0-13 of the next chunk are read in
 // slots 82-95, after the chunk's barrier, and operands 14 and 15 of the chunk itself in its
-// stage-free slots 5 and 10; the step-1 operands in the stage-free slots 15-76, two per slot in the
-// first three.  Every read lands at least six slots before its operand's first use.
+// stage-free slots 30 and 35; the step-1 operands in the stage-free slots 5-76, beside at most one
+// store, two per slot where the deadlines crowd.  Every read lands at least six slots before its
+// operand's first use.
+constexpr int kFwdRead1Slot[16] = {5, 5, 10, 15, 20, 25, 40, 46, 46, 51, 51, 56, 61, 66, 71, 76};
 template <int OP>
-constexpr int fwd1_read0_slot() { return OP < 14 ? 82 + OP : 5 * (OP - 13); }
+constexpr int fwd1_read0_slot() { return OP < 14 ? 82 + OP : OP == 14 ? 30 : 35; }
 template <int OP>
-constexpr int fwd1_read1_slot() {
-    constexpr int slot[16] = {15, 15, 20, 20, 25, 25, 30, 35, 40, 46, 51, 56, 61, 66, 71, 76};
-    return slot[OP];
-}
+constexpr int fwd1_read1_slot() { return kFwdRead1Slot[OP]; }
 // First use of operand OP in a K step (MFMA order of fwd1_mfma: ah[a] at 4a, bh[b] at b, bl[b] at
 // 16 + b, al[a] at 32 + 4a).
 constexpr int fwd1_first_use(int op) {
@@ -497,12 +509,10 @@ constexpr int fwd1_first_use(int op) {
 }
 constexpr bool fwd1_reads_ok() {
     for (int op = 0; op < 16; ++op) {
-        const int s1 = op == 0 ? 15 : op == 1 ? 15 : op == 2 ? 20 : op == 3 ? 20 : op == 4 ? 25 : op == 5 ? 25
-                     : op == 6 ? 30 : op == 7 ? 35 : op == 8 ? 40 : op == 9 ? 46 : op == 10 ? 51 : op == 11 ? 56
-                     : op == 12 ? 61 : op == 13 ? 66 : op == 14 ? 71 : 76;
+        const int s1 = kFwdRead1Slot[op];
         if (s1 < kRunSlots ? run_stage_at(s1) >= 0 : run_stage_at(s1 - kRunSlots) >= 0) return false;
         if (s1 + 6 > 48 + fwd1_first_use(op)) return false;
-        const int s0 = op < 14 ? 82 + op - 96 : 5 * (op - 13);
+        const int s0 = op < 14 ? 82 + op - 96 : op == 14 ? 30 : 35;
         if (s0 >= 0 && run_stage_at(s0) >= 0) return false;
         if (s0 + 6 > fwd1_first_use(op)) return false;
     }
@@ -519,6 +529,16 @@ __device__ __forceinline__ void fwd1_reads1_at(Fwd1Ctx &c, std::integer_sequence
     ((I == fwd1_read1_slot<OP>() ? fwd1_read<1, OP, B>(c.smem, c.ox, c.oy, c.o1) : void()), ...);
 }
 
+// The stores of slot I into buffer N (S = 8 run + 2 segment + half).
+template <int I, int N, int... S>
+__device__ __forceinline__ void fwd1_stores_at(Fwd1Ctx &c, std::integer_sequence<int, S...>) {
+    ((I == kFwdStoreSlot[S >> 3][(S >> 1) & 3][S & 1]
+          ? (S < 8 ? c.gx.template store_half<(S >> 1) & 3, S & 1>(c.smem + ((S & 1) ? F1_XL(N) : F1_XH(N)), c.k, c.r)
+                   : c.gy.template store_half<(S >> 1) & 3, S & 1>(c.smem + ((S & 1) ? F1_YL(N) : F1_YH(N)), c.k, c.r))
+          : void()),
+     ...);
+}
+
 // Slot I of a chunk that contracts buffer B and generates into buffer 1 - B.
 template <int I, int B>
 __device__ __forceinline__ void fwd1_slot(Fwd1Ctx &c) {
@@ -529,19 +549,15 @@ __device__ __forceinline__ void fwd1_slot(Fwd1Ctx &c) {
     constexpr int XS = I < kRunSlots ? run_stage_at(I) : -1;
     constexpr int YS = I >= kRunSlots && I < 2 * kRunSlots ? run_stage_at(I - kRunSlots) : -1;
     if constexpr (XS >= 0) c.gx.template stage<XS, true, false>(c.ux, c.smem + F1_XH(N), c.smem + F1_XL(N), c.k, c.r);
-    if constexpr (YS >= 0)
-        c.gy.template stage<YS, true, YS == 32>(c.uy, c.smem + F1_YH(N), c.smem + F1_YL(N), c.k, c.r);
-    constexpr int XM = I < kRunSlots ? run_store_at(I) : -1;
-    constexpr int YM = I >= kRunSlots && I < 2 * kRunSlots ? run_store_at(I - kRunSlots) : -1;
-    if constexpr (XM >= 0) c.gx.template store_seg<XM>(c.smem + F1_XH(N), c.smem + F1_XL(N), c.k, c.r);
-    if constexpr (YM >= 0 && YM < 3) c.gy.template store_seg<YM>(c.smem + F1_YH(N), c.smem + F1_YL(N), c.k, c.r);
+    if constexpr (YS >= 0) c.gy.template stage<YS, true, false>(c.uy, c.smem + F1_YH(N), c.smem + F1_YL(N), c.k, c.r);
+    fwd1_stores_at<I, N>(c, std::make_integer_sequence<int, 16>{});
     // The generator's last store is in slot 81 at the latest: after the barrier the next chunk's
     // tiles are complete (its first step-0 operands are read in the following slots, well before the
     // next chunk's first MFMA) and this chunk's buffer is free for the next chunk's generator.
     static_assert(2 * kRunSlots - 1 <= 81, "slot plan");
     if constexpr (I == 81) lds_barrier();
     if constexpr (I >= 82) fwd1_reads0_at<I, N>(c, std::make_integer_sequence<int, 14>{});
-    if constexpr (I <= 10) fwd1_reads0_at<I, B>(c, std::make_integer_sequence<int, 16>{});
+    if constexpr (I <= 35) fwd1_reads0_at<I, B>(c, std::make_integer_sequence<int, 16>{});
     __builtin_amdgcn_sched_barrier(0);
 }
 
@@ -552,9 +568,9 @@ __device__ __forceinline__ void fwd1_slots(Fwd1Ctx &c, std::integer_sequence<int
 
 // One chunk: contract buffer B into acc while generating the next chunk's X and Y runs into
 // buffer 1 - B.  96 slots of one MFMA each; the X run's stages spread over slots 0-40, the Y run's
-// over slots 41-81, each run segment stored in the stage-free slot after the stage completing it;
-// the operand reads in the other stage-free slots (fwd1_read0_slot, fwd1_read1_slot); the chunk's
-// one barrier follows slot 81.
+// over slots 41-81, the hi and lo halves of each run segment stored in stage-free slots after the
+// stage completing it (kFwdStoreSlot); the operand reads in the stage-free slots too
+// (fwd1_read0_slot, fwd1_read1_slot); the chunk's one barrier follows slot 81.
 template <int B>
 __device__ __forceinline__ void fwd1_chunk(char *smem, const OpBase &ox, const OpBase &oy, f32x16 (&acc)[4][4],
                                            RunStages &gx, RunStages &gy, FwdOps1 &o0, int ux, int uy, int k,
