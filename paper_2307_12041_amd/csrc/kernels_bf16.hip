@@ -397,6 +397,8 @@ struct RunStages {
             __builtin_amdgcn_sched_barrier(0);
             hah[q] = h[q] << 16;
             hbh[q] = h[q] & 0xffff0000u;
+            // opaque, so that register allocation does not recompute them in the next stage's slot
+            asm("" : "+v"(hah[q]), "+v"(hbh[q]));
         } else if constexpr (HI) {
             h[q] = pack_bf16(v[2 * q], v[2 * q + 1]);
         } else if constexpr (X3 && LO) {
@@ -545,6 +547,13 @@ __device__ __forceinline__ void fwd1_slot(Fwd1Ctx &c) {
     constexpr int N = 1 - B;
     if constexpr (I < 48) fwd1_mfma<I>(c.o0, c.acc);
     else fwd1_mfma<I - 48>(c.o1, c.acc);
+    // The records this chunk's runs start from were fetched a chunk ago, the next chunk's (eight
+    // loads) since: one wait for the older ones here, in the compiler's own instruction so that it
+    // needs no wait of its own at each record's first use.
+    if constexpr (I == 0) {
+        __builtin_amdgcn_s_waitcnt(0x0F78);   // vmcnt(8)
+        __builtin_amdgcn_sched_barrier(0);
+    }
     fwd1_reads1_at<I, B>(c, std::make_integer_sequence<int, 16>{});
     constexpr int XS = I < kRunSlots ? run_stage_at(I) : -1;
     constexpr int YS = I >= kRunSlots && I < 2 * kRunSlots ? run_stage_at(I - kRunSlots) : -1;
@@ -603,6 +612,10 @@ __device__ __forceinline__ void fwd1p_slot(Fwd1Ctx &c) {
     constexpr int N = 1 - B;
     if constexpr (I < 16) fwd1_mfma<I>(c.o0, c.acc);
     else fwd1_mfma<I - 16>(c.o1, c.acc);
+    if constexpr (I == 0) {   // the runs' records, as in the three-product chunk
+        __builtin_amdgcn_s_waitcnt(0x0F78);   // vmcnt(8)
+        __builtin_amdgcn_sched_barrier(0);
+    }
     if constexpr (I >= 4 && I < 12) fwd1_read<1, I - 4, B>(c.smem, c.ox, c.oy, c.o1);
     if constexpr (I < kPlainRunSlots) fwd1p_stages<I, N>(c, std::make_integer_sequence<int, RunStages::kStages>{});
     if constexpr (I == kPlainRunSlots - 1) lds_barrier();
@@ -699,8 +712,11 @@ __global__ __launch_bounds__(256) void k_fwd1_bf16(int64_t n, int Mu, int Mp, co
     FwdOps1 o0;
     fwd1_prologue_reads<X3>(smem, ox, oy, o0, std::make_integer_sequence<int, 14>{});
     // Nothing the prologue loaded may still be in flight at the loop head (the compiler would then
-    // wait for every load and LDS read at the first use in each iteration).
-    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+    // wait for every load and LDS read at the first use in each iteration); the wait is the
+    // compiler's own instruction, so that its bookkeeping knows.
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0x0070);   // vmcnt(0) lgkmcnt(0)
+    asm volatile("" ::: "memory");
     int64_t c = c_begin;
     for (; c + 1 < c_end; c += 2) {
         gxA.R = recx(c + 2);
