@@ -1009,9 +1009,11 @@ template <int KA>
 struct Bwd1Ctx {
     const char *cur, *nxt;
     char *cpy_dst;                 // released buffer receiving the chunk after next (after the barrier)
-    const char *cpy_src;           // its global tile (past the last chunk: the last chunk again)
+    unsigned cpy_off;              // its byte offset in the operand (past the last chunk: the last chunk again)
     char *cpy_dst2;                // buffer receiving the next chunk (the rest of its copies)
-    const char *cpy_src2;          // its global tile (past the last chunk: the last chunk again)
+    unsigned cpy_off2;             // its byte offset in the operand (past the last chunk: the last chunk again)
+    const char *gtile;             // the N tile's operand, Q chunks of 64 KB
+    int gbytes;                    // its size
     AGen<KA> (&g)[2];
     bf16x8 (&ah)[2], (&al)[2];     // A operands of the current step
     bf16x8 (&bh)[8], (&bl)[8];     // B operands
@@ -1024,18 +1026,25 @@ struct Bwd1Ctx {
 // Copy slice SL (0 .. NSL - 1) of this wave's quarter of the first 4 NSL KB of an operand tile
 // (NSL = 16: hi and lo, the whole tile; 8: the hi half): tile bytes NSL wave_off + 1024 SL + 16 lane
 // go to the same offset of the LDS buffer (NEXT: the next chunk's tile and buffer, else the chunk
-// after next's).  Four consecutive slices share one address pair and differ in the instruction's
-// immediate offset, which applies to the global and the LDS address alike, so each group of four
-// needs one M0 value and one address computation.
+// after next's).  The copy is a buffer load into LDS: the lane's offset in a register, the chunk's
+// in a scalar one, and four consecutive slices differ only in the immediate offset, which moves the
+// global and the LDS address alike (one M0 value per group of four).  Unlike the global form, which
+// the compiler also books as an LDS access and then answers with a full LDS wait at the next use of
+// any LDS read, the buffer form counts as a memory load only.
+template <int IMM>
+__device__ __forceinline__ void bwd1_copy16(const char *gtile, int gbytes, unsigned voff, unsigned soff, char *lds) {
+    typedef __attribute__((address_space(3))) void lds_void;
+    // raw buffer resource of the N tile's operand (uniform; the compiler keeps one in scalar registers)
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc((void *)gtile, (short)0, gbytes, 0x00020000);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (lds_void *)lds, 16, voff, soff, IMM, 0);
+}
 template <int SL, int NSL, bool NEXT, int KA>
 __device__ __forceinline__ void bwd1_copy_slice(const Bwd1Ctx<KA> &c) {
-    typedef __attribute__((address_space(3))) void lds_void;
     static_assert(NSL % 4 == 0 && SL >= 0 && SL < NSL, "copy slices");
-    constexpr int grp = (SL >> 2) * 4096, imm = (SL & 3) * 1024;
+    constexpr int grp = (SL >> 2) * 4096;
     const int part = NSL * c.wave_off + grp;
-    const char *src = NEXT ? c.cpy_src2 : c.cpy_src;
-    char *dst = NEXT ? c.cpy_dst2 : c.cpy_dst;
-    __builtin_amdgcn_global_load_lds((const void *)(src + part + c.lane_off), (lds_void *)(dst + part), 16, imm, 0);
+    bwd1_copy16<(SL & 3) * 1024>(c.gtile, c.gbytes, c.lane_off + NSL * c.wave_off,
+                                 (NEXT ? c.cpy_off2 : c.cpy_off) + grp, (NEXT ? c.cpy_dst2 : c.cpy_dst) + part);
 }
 
 // A wait for every outstanding LDS operation written with the compiler's own instruction, so that its
@@ -1058,12 +1067,13 @@ template <int BAR, int D>
 constexpr int bwd1_copy_after(int slot) { return slot == BAR + 1 ? 0 : slot == BAR + 1 + D ? 1 : -1; }
 template <int NSL, int D>
 constexpr int bwd1_copy_next(int slot) { return slot % D == 0 && slot / D + 2 < NSL ? slot / D + 2 : -1; }
-// The three-product chunk places them by its LDS waits instead: the compiler counts the copies among
-// the LDS operations, and with one outstanding it makes the next wait for an LDS read a wait for all
-// of them (slots 32, 48, 80, 96, 128 and 144 of the chunk, the first uses of the lo and hi B reads),
-// which the copy may then hold up.  Slices 2 .. 15 go right after such a wait and at least 15 slots
-// before the next one; slices 0 and 1 go after an explicit wait for the next chunk's hi B reads, at
-// slots 188 and 190, so that the next chunk's first MFMAs need no wait at all.
+// The three-product chunk places them by its LDS waits instead (slots 32, 48, 80, 96, 128 and 144 of
+// the chunk, the first uses of the lo and hi B reads): slices 2 .. 15 right after such a wait and at
+// least 15 slots before the next one, slices 0 and 1 after an explicit wait for the next chunk's hi B
+// reads, at slots 188 and 190, so that the next chunk's first MFMAs need no wait at all.  (The plan
+// dates from copies issued as global loads into LDS, which the compiler also books as LDS accesses,
+// turning every later LDS wait into a wait for all of them; the buffer form it uses now counts as a
+// memory load only, and the plan measured no worse with it.)
 constexpr int kBwd1CopyNext[14] = {1, 5, 9, 13, 49, 53, 57, 61, 97, 101, 105, 109, 145, 149};
 constexpr int bwd1x3_copy_next(int slot) {
     for (int k = 0; k < 14; ++k)
@@ -1248,7 +1258,7 @@ __global__ __launch_bounds__(256) void k_bwd1_bf16(int64_t n, BwdAxisBf16 ax) {
         __builtin_amdgcn_global_load_lds((const void *)(gb + sl * 4096 + tid * 16),
                                          (lds_void *)(smem + sl * 4096 + wave * 1024), 16, 0, 0);
     bf16x8 ah[2], al[2], bh[8], bl[8];
-    Bwd1Ctx<KA> c{smem, smem + BBUF, smem + BBUF, gb + (Q > 1 ? tile_bytes : 0), smem + BBUF, gb,
+    Bwd1Ctx<KA> c{smem, smem + BBUF, smem + BBUF, Q > 1 ? (unsigned)BBUF : 0u, smem + BBUF, 0u, gb, Q * BBUF,
                   g, ah, al, bh, bl, acc, h, j, (unsigned)lane * 16u, wave * 1024};
     if (Q > 1) {
         bwd1_copy_slice<0, X3 ? 16 : 8, false>(c);
@@ -1273,9 +1283,9 @@ __global__ __launch_bounds__(256) void k_bwd1_bf16(int64_t n, BwdAxisBf16 ax) {
         c.cur = smem + (q & 1) * BBUF;
         c.nxt = smem + ((q & 1) ^ 1) * BBUF;
         c.cpy_dst = smem + (q & 1) * BBUF;
-        c.cpy_src = gb + (size_t)min(q + 2, Q - 1) * tile_bytes;
+        c.cpy_off = (unsigned)min(q + 2, Q - 1) * (unsigned)BBUF;
         c.cpy_dst2 = smem + ((q & 1) ^ 1) * BBUF;
-        c.cpy_src2 = gb + (size_t)min(q + 1, Q - 1) * tile_bytes;
+        c.cpy_off2 = (unsigned)min(q + 1, Q - 1) * (unsigned)BBUF;
         bwd1_slots<X3>(c, std::make_integer_sequence<int, X3 ? 192 : 64>{});
     }
     wait_copies();   // the copies issued in the last chunks must land before the buffers are reused
