@@ -208,13 +208,19 @@ __device__ __forceinline__ i32x8 as_op(const unsigned (&w)[8]) {
     return i32x8{(int)w[0], (int)w[1], (int)w[2], (int)w[3], (int)w[4], (int)w[5], (int)w[6], (int)w[7]};
 }
 
-__device__ __forceinline__ void copy_tile8(const char *__restrict__ src, char *dst, int tid) {
+// One operand tile (chunk at byte offset off of the N tile's operand gtile, gbytes long) into dst, as
+// buffer loads into LDS: 16 bytes per thread and slice, each wave's 1 KB at the same offset of the
+// buffer.  (The global form of the direct copy is booked by the compiler as an LDS access too, which
+// makes every later wait for an LDS read a full one while a copy is in flight; the buffer form counts
+// as a memory load only.)
+__device__ __forceinline__ void copy_tile8(const char *gtile, int gbytes, unsigned off, char *dst, int tid) {
     typedef __attribute__((address_space(3))) void lds_void;
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc((void *)gtile, (short)0, gbytes, 0x00020000);
     const int wave = tid >> 6;
 #pragma unroll
     for (int s = 0; s < F8_TILE / 4096; ++s)
-        __builtin_amdgcn_global_load_lds((const void *)(src + s * 4096 + tid * 16),
-                                         (lds_void *)(dst + s * 4096 + wave * 1024), 16, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (lds_void *)(dst + s * 4096 + wave * 1024), 16,
+                                                  (unsigned)tid * 16u, off + (unsigned)(s * 4096), 0, 0);
 }
 
 // B operand of column tile b from a chunk buffer: lane (j, h) holds row 32 b + j, K values
@@ -267,8 +273,8 @@ __global__ __launch_bounds__(256) void k_bwd_fp8(int64_t n, BwdAxisFp8 ax) {
         g[a].template piece<2>(ah[a], al[a]);
         g[a].template piece<3>(ah[a], al[a]);
     }
-    copy_tile8(gb, smem, tid);
-    if (Q > 1) copy_tile8(gb + F8_TILE, smem + F8_TILE, tid);
+    copy_tile8(gb, Q * F8_TILE, 0u, smem, tid);
+    if (Q > 1) copy_tile8(gb, Q * F8_TILE, (unsigned)F8_TILE, smem + F8_TILE, tid);
     const int sa = opaque(kBasisCode);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
@@ -312,7 +318,7 @@ __global__ __launch_bounds__(256) void k_bwd_fp8(int64_t n, BwdAxisFp8 ax) {
         // all reads of this chunk's buffer are done, the next chunk's tile has landed
         wait_copies();
         lds_barrier();
-        if (q + 2 < Q) copy_tile8(gb + (size_t)(q + 2) * F8_TILE, smem + (q & 1) * F8_TILE, tid);
+        if (q + 2 < Q) copy_tile8(gb, Q * F8_TILE, (unsigned)(q + 2) * (unsigned)F8_TILE, smem + (q & 1) * F8_TILE, tid);
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
