@@ -1082,6 +1082,64 @@ constexpr int bwd1x3_copy_next(int slot) {
 }
 constexpr int bwd1x3_copy_after(int slot) { return slot == 188 ? 0 : slot == 190 ? 1 : -1; }
 
+// Compile-time check of the copy plans against the chunk's reads and barrier, for 1 to 6 chunks.
+// Copies land at the barrier's wait (each wave waits for its own, then all meet), and waves are
+// ordered only by barriers, so: every read of a buffer finds there the whole operand tile of the
+// chunk it expects (NSL slices), none of it still in flight, and a copy writes a buffer only when
+// every read of that buffer lies at or before the last barrier.  Reads: three products, lo B at
+// slots 16-23 and hi B at slots 32-39 of each step (the next chunk's hi B, from the other buffer, in
+// step 3), barrier after slot 175; one product, hi B at slots 8-15 of each step (the next chunk's in
+// step 3), barrier after slot 55.
+template <bool X3>
+constexpr bool bwd1_copy_plan_ok() {
+    constexpr int NS = X3 ? 192 : 64, BAR = X3 ? 175 : 55, NSL = X3 ? 16 : 8, STEP = X3 ? 48 : 16;
+    for (int Q = 1; Q <= 6; ++Q) {
+        int have[2][16] = {}, src[2][16] = {};
+        bool pend[2][16] = {};
+        int lastread[2] = {-1, -1}, lastbar = -1;
+        for (int b = 0; b < 2; ++b)
+            for (int sl = 0; sl < 16; ++sl) have[b][sl] = -1;
+        for (int sl = 0; sl < NSL; ++sl) have[0][sl] = 0;       // prologue: chunk 0,
+        if (Q > 1) have[1][0] = have[1][1] = 1;                 // the first two slices of chunk 1
+        for (int q = 0; q < Q; ++q) {
+            const int cur = q & 1, nxt = cur ^ 1;
+            const int after = q + 2 < Q - 1 ? q + 2 : Q - 1, next = q + 1 < Q - 1 ? q + 1 : Q - 1;
+            for (int i = 0; i < NS; ++i) {
+                const int g = q * NS + i, s = i / STEP, t = i % STEP;
+                const int ca = X3 ? bwd1x3_copy_after(i) : bwd1_copy_after<55, 4>(i);
+                const int cn = X3 ? bwd1x3_copy_next(i) : bwd1_copy_next<8, 4>(i);
+                if (ca >= 0) {
+                    if (lastread[cur] > lastbar) return false;
+                    pend[cur][ca] = true;
+                    src[cur][ca] = after;
+                }
+                if (cn >= 0) {
+                    if (lastread[nxt] > lastbar) return false;
+                    pend[nxt][cn] = true;
+                    src[nxt][cn] = next;
+                }
+                int rb = -1, need = 0;   // buffer read in this slot and the chunk it must hold
+                if (X3 && t >= 16 && t < 24) rb = cur, need = q;
+                if (t >= (X3 ? 32 : 8) && t < (X3 ? 40 : 16)) rb = s < 3 ? cur : nxt, need = s < 3 ? q : q + 1;
+                if (rb >= 0) {
+                    if (need < Q)
+                        for (int sl = 0; sl < NSL; ++sl)
+                            if (pend[rb][sl] || have[rb][sl] != need) return false;
+                    lastread[rb] = g;
+                }
+                if (i == BAR) {
+                    for (int b = 0; b < 2; ++b)
+                        for (int sl = 0; sl < 16; ++sl)
+                            if (pend[b][sl]) have[b][sl] = src[b][sl], pend[b][sl] = false;
+                    lastbar = g;
+                }
+            }
+        }
+    }
+    return true;
+}
+static_assert(bwd1_copy_plan_ok<true>() && bwd1_copy_plan_ok<false>(), "copy plan hazard");
+
 // B operand of column tile b, K step s of a chunk buffer: row 32 b + j, logical segment 4 h + s,
 // physical segment XORed with (j / 2) % 8.
 __device__ __forceinline__ bf16x8 bwd1_readb(const char *buf, int hl, int b, int s, int h, int j) {
