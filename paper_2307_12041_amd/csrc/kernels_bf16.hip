@@ -748,7 +748,8 @@ __global__ __launch_bounds__(256) void k_fwd1_bf16(int64_t n, int Mu, int Mp, co
 // A (sine differences along the K axis) is held in MFMA operand layout: lane half h = lane / 32
 // walks frequencies h * Kh + 8 t (t = 0, 1, ...), so each lane's recurrence (or table row) runs over
 // contiguous frequencies.  B is staged per chunk of 32 + 32 frequencies
-// (4 K steps) in LDS by direct global->LDS copies: the global operand is pre-tiled in exactly the
+// (4 K steps) in LDS by direct copies (global memory to LDS, no registers; buffer loads in the
+// regenerating kernel, global ones in the store-mode kernel): the global operand is pre-tiled in exactly the
 // LDS byte order, one contiguous 64 KB block (hi then lo) per (N tile, chunk), rows of 128 bytes
 // whose 16-byte segments are XOR-swizzled by (row / 2) % 8: any 16 consecutive rows then cover all
 // 16 bank groups of 16 bytes, so the b128 operand reads are conflict free.
