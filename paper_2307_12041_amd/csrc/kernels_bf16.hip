@@ -425,7 +425,7 @@ struct RunStages {
 
 // Slots of the run stages in a chunk of 96 MFMA slots: the X run's stages spread over slots 0-40,
 // the Y run's over slots 41-81 (stage s at slot offset floor(41 s / 33)), so that no slot holds more
-// than one stage and the last store precedes the chunk's barrier after slot 81.
+// than one stage and the last store precedes the chunk's barrier after slot 83.
 constexpr int kRunSlots = 41;
 constexpr int run_stage_at(int slot) {
     for (int st = 0; st < RunStages::kStages; ++st)
@@ -435,16 +435,18 @@ constexpr int run_stage_at(int slot) {
 static_assert((RunStages::kStages - 1) * kRunSlots / RunStages::kStages < kRunSlots, "stage plan");
 // Slots of the 16-byte stores of the three-product chunk, [run (X, Y)][segment][hi, lo]: one store in
 // each stage-free slot from the one after the stage completing the segment on (the X run's slots
-// 10-40 and 46, the Y run's 51-76), the Y run's last segment both in slot 81, before the barrier.
+// 10-40 and 46, the Y run's 51-76), the Y run's last segment in slots 81 and 82, so that the barrier's
+// wait for the stores (after slot 83) does not wait for stores issued in the slot before it.
 constexpr int kFwdStoreSlot[2][4][2] = {{{10, 15}, {20, 25}, {30, 35}, {40, 46}},
-                                        {{51, 56}, {61, 66}, {71, 76}, {81, 81}}};
+                                        {{51, 56}, {61, 66}, {71, 76}, {81, 82}}};
+constexpr int kFwdBarrier = 83;   // the chunk's barrier follows this slot
 constexpr bool fwd1_stores_ok() {
     for (int run = 0; run < 2; ++run)
         for (int m = 0; m < 4; ++m)
             for (int hl = 0; hl < 2; ++hl) {
                 const int sl = kFwdStoreSlot[run][m][hl], done = run * kRunSlots + (8 * m + 8) * kRunSlots / RunStages::kStages;
                 const int off = sl - run * kRunSlots;
-                if (sl <= done || sl > 81 || (off >= 0 && off < kRunSlots && run_stage_at(off) >= 0)) return false;
+                if (sl <= done || sl > kFwdBarrier || (off >= 0 && off < kRunSlots && run_stage_at(off) >= 0)) return false;
                 if (run == 0 && sl >= kRunSlots && run_stage_at(sl - kRunSlots) >= 0) return false;
             }
     return true;
@@ -494,14 +496,15 @@ struct Fwd1Ctx {
 
 // Operand reads are placed in the slots that hold no generator stage (a stage issues about six
 // VALU instructions, which one wave issues beside a 32-cycle MFMA at little cost; a stage slot with
-// two LDS reads on top stretches the MFMA slot).  Step-0 operands 0-13 of the next chunk are read in
-// slots 82-95, after the chunk's barrier, and operands 14 and 15 of the chunk itself in its
-// stage-free slots 30 and 35; the step-1 operands in the stage-free slots 5-76, beside at most one
+// two LDS reads on top stretches the MFMA slot).  Step-0 operands 0-11 of the next chunk are read in
+// slots 84-95, after the chunk's barrier, and operands 12-15 of the chunk itself in its stage-free
+// slots 10, 25, 30 and 35; the step-1 operands in the stage-free slots 5-76, beside at most one
 // store, two per slot where the deadlines crowd.  Every read lands at least six slots before its
 // operand's first use.
 constexpr int kFwdRead1Slot[16] = {5, 5, 10, 15, 20, 25, 40, 46, 46, 51, 51, 56, 61, 66, 71, 76};
+constexpr int fwd1_read0_at(int op) { return op < 12 ? kFwdBarrier + 1 + op : op == 12 ? 10 : op == 13 ? 25 : op == 14 ? 30 : 35; }
 template <int OP>
-constexpr int fwd1_read0_slot() { return OP < 14 ? 82 + OP : OP == 14 ? 30 : 35; }
+constexpr int fwd1_read0_slot() { return fwd1_read0_at(OP); }
 template <int OP>
 constexpr int fwd1_read1_slot() { return kFwdRead1Slot[OP]; }
 // First use of operand OP in a K step (MFMA order of fwd1_mfma: ah[a] at 4a, bh[b] at b, bl[b] at
@@ -514,7 +517,7 @@ constexpr bool fwd1_reads_ok() {
         const int s1 = kFwdRead1Slot[op];
         if (s1 < kRunSlots ? run_stage_at(s1) >= 0 : run_stage_at(s1 - kRunSlots) >= 0) return false;
         if (s1 + 6 > 48 + fwd1_first_use(op)) return false;
-        const int s0 = op < 14 ? 82 + op - 96 : op == 14 ? 30 : 35;
+        const int s0 = op < 12 ? fwd1_read0_at(op) - 96 : fwd1_read0_at(op);
         if (s0 >= 0 && run_stage_at(s0) >= 0) return false;
         if (s0 + 6 > fwd1_first_use(op)) return false;
     }
@@ -560,12 +563,12 @@ __device__ __forceinline__ void fwd1_slot(Fwd1Ctx &c) {
     if constexpr (XS >= 0) c.gx.template stage<XS, true, false>(c.ux, c.smem + F1_XH(N), c.smem + F1_XL(N), c.k, c.r);
     if constexpr (YS >= 0) c.gy.template stage<YS, true, false>(c.uy, c.smem + F1_YH(N), c.smem + F1_YL(N), c.k, c.r);
     fwd1_stores_at<I, N>(c, std::make_integer_sequence<int, 16>{});
-    // The generator's last store is in slot 81 at the latest: after the barrier the next chunk's
+    // The generator's last store is in slot 82 at the latest: after the barrier the next chunk's
     // tiles are complete (its first step-0 operands are read in the following slots, well before the
     // next chunk's first MFMA) and this chunk's buffer is free for the next chunk's generator.
-    static_assert(2 * kRunSlots - 1 <= 81, "slot plan");
-    if constexpr (I == 81) lds_barrier();
-    if constexpr (I >= 82) fwd1_reads0_at<I, N>(c, std::make_integer_sequence<int, 14>{});
+    static_assert(2 * kRunSlots - 1 <= kFwdBarrier && kFwdBarrier + 12 == 95, "slot plan");
+    if constexpr (I == kFwdBarrier) lds_barrier();
+    if constexpr (I > kFwdBarrier) fwd1_reads0_at<I, N>(c, std::make_integer_sequence<int, 12>{});
     if constexpr (I <= 35) fwd1_reads0_at<I, B>(c, std::make_integer_sequence<int, 16>{});
     __builtin_amdgcn_sched_barrier(0);
 }
@@ -579,7 +582,7 @@ __device__ __forceinline__ void fwd1_slots(Fwd1Ctx &c, std::integer_sequence<int
 // buffer 1 - B.  96 slots of one MFMA each; the X run's stages spread over slots 0-40, the Y run's
 // over slots 41-81, the hi and lo halves of each run segment stored in stage-free slots after the
 // stage completing it (kFwdStoreSlot); the operand reads in the stage-free slots too
-// (fwd1_read0_slot, fwd1_read1_slot); the chunk's one barrier follows slot 81.
+// (fwd1_read0_slot, fwd1_read1_slot); the chunk's one barrier follows slot 83.
 template <int B>
 __device__ __forceinline__ void fwd1_chunk(char *smem, const OpBase &ox, const OpBase &oy, f32x16 (&acc)[4][4],
                                            RunStages &gx, RunStages &gy, FwdOps1 &o0, int ux, int uy, int k,
@@ -646,12 +649,12 @@ __device__ __forceinline__ void fwd1_chunk_any(char *smem, const OpBase &ox, con
     }
 }
 
-// Step-0 operands of the first chunk that the loop expects already read: 0-13 for the three-product
+// Step-0 operands of the first chunk that the loop expects already read: 0-11 for the three-product
 // schedule, 0-4 for the one-product one.
 template <bool X3, int... OP>
 __device__ __forceinline__ void fwd1_prologue_reads(const char *smem, const OpBase &ox, const OpBase &oy, FwdOps1 &o0,
                                                     std::integer_sequence<int, OP...>) {
-    ((X3 || OP < 5 ? fwd1_read<0, OP, 0>(smem, ox, oy, o0) : void()), ...);
+    (((X3 ? OP < 12 : OP < 5) ? fwd1_read<0, OP, 0>(smem, ox, oy, o0) : void()), ...);
 }
 
 // X3: three products per pair (hi*hi, lo*hi, hi*lo); otherwise one (hi*hi).  skip_u x skip_p: the
